@@ -1,0 +1,103 @@
+"""The synthetic workloads, shaped like the paper's experiments.
+
+* ``config1``: 64^3 grid at 0.5 mm, 12 spheres + 4 planes, two linear sweeps of
+  100 frames (128^2 uint8 at 0.25 mm) tilted +-20 deg in-plane, 16 slices of 128^2.
+* ``config2``: 256^3 grid at 0.125 mm (the paper's voxel size), 30 spheres + 10
+  planes, three azimuth sweeps (0/120/240 deg) of 600 frames of 256^2 at
+  0.125 mm with 1 mm / 2 deg jitter, 1000 slices of 512^2 at 0.0625 mm
+  (80 % near acquired poses, 20 % uniformly random).
+* ``config3_slices``: 1000 slices of 512^2 at 0.0625 mm through the config-1 volume.
+* ``serving_volume``: N^3 volumes at 0.125 mm built from three azimuth sweeps of
+  N^2 frames.
+* ``tiny_workload``: a few small frames on a small grid, for brute-force checks.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .phantom import Phantom, make_phantom
+from .poses import WORLD_OFFSET_MM, make_calibration
+from .render import render_frames
+from .sweeps import SliceSet, Sweep, azimuth_sweeps, linear_tilted_sweeps, slice_poses
+
+
+@dataclass
+class Workload:
+    name: str
+    dims: tuple                   # (nx, ny, nz)
+    spacing: float                # voxel size h, mm
+    origin: np.ndarray            # world mm of voxel (0,0,0)'s centre
+    calib: np.ndarray             # (4,4) float64 image-mm -> probe
+    phantom: Phantom
+    sweep: Sweep
+    slices: SliceSet
+    frame_seed: int
+    params: dict = field(default_factory=dict)
+    frames: object = None         # torch uint8 (F,H,W), filled by ``render``
+
+    def render(self, device="cpu"):
+        self.frames = render_frames(self.phantom, self.sweep.probe_poses, self.calib,
+                                    self.sweep.width, self.sweep.height, self.sweep.pitch,
+                                    seed=self.frame_seed, device=device)
+        return self.frames
+
+
+DEFAULT_PARAMS = dict(k_normal=10.0, k_inplane=5.0, thr_normal_deg=25.0, thr_inplane_deg=15.0,
+                      radius_vox=1.0, bin_tol_deg=3.0, max_bins=64, normal_axis=2)
+
+
+def config1(n_slices: int = 16, n_near: int = 12) -> Workload:
+    N, h, w, pitch = 64, 0.5, 128, (0.25, 0.25)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=1, L=N * h, n_sph=12, n_pl=4, shell_mm=h)
+    sw = linear_tilted_sweeps(N, h, 100, w, w, pitch, (20.0, -20.0), C)
+    sl = slice_poses(101, sw, n_slices, n_near, 128, 128, (0.25, 0.25), N, h, C)
+    return Workload("config1: 64^3 @0.5mm, 2x100 frames 128^2, 16 slices 128^2", (N, N, N), h,
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=1, params=dict(DEFAULT_PARAMS))
+
+
+def config2(n_slices: int = 1000, n_near: int = 800) -> Workload:
+    N, h, w, pitch = 256, 0.125, 256, (0.125, 0.125)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=2, L=N * h, n_sph=30, n_pl=10, shell_mm=h)
+    sw = azimuth_sweeps(N, h, 600, w, w, pitch, (0.0, 120.0, 240.0), 1.0, 2.0, seed=202, calib=C)
+    sl = slice_poses(203, sw, n_slices, n_near, 512, 512, (0.0625, 0.0625), N, h, C)
+    return Workload("config2: 256^3 @0.125mm, 3x600 frames 256^2, 1000 slices 512^2", (N, N, N), h,
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=2, params=dict(DEFAULT_PARAMS))
+
+
+def config3_slices(wl1: Workload, n_slices: int = 1000, n_near: int = 800) -> SliceSet:
+    N = wl1.dims[0]
+    return slice_poses(3, wl1.sweep, n_slices, n_near, 512, 512, (0.0625, 0.0625), N,
+                       wl1.spacing, wl1.calib)
+
+
+def serving_volume(N: int, seed: int, n_frames: int = 600, n_slices: int = 64) -> Workload:
+    h, pitch = 0.125, (0.125, 0.125)
+    C = make_calibration(N, pitch[0])
+    ph = make_phantom(seed=seed, L=N * h, n_sph=30, n_pl=10, shell_mm=h)
+    sw = azimuth_sweeps(N, h, n_frames, N, N, pitch, (0.0, 120.0, 240.0), 1.0, 2.0,
+                        seed=seed * 100 + 1, calib=C)
+    sl = slice_poses(seed * 100 + 2, sw, n_slices, int(0.8 * n_slices), 512, 512,
+                     (N * h / 512, N * h / 512), N, h, C)
+    return Workload(f"serving volume {N}^3 @0.125mm", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph,
+                    sw, sl, frame_seed=seed, params=dict(DEFAULT_PARAMS))
+
+
+def tiny_workload(seed: int, N: int = 8, n_frames: int = 6, w: int = 6, n_slices: int = 4,
+                  slice_w: int = 7, slice_h: int = 5, jitter_deg: float = 12.0,
+                  exponent: float = 4.0, speckle: float = 0.3) -> Workload:
+    """A handful of jittered frames on a small grid: for brute-force and literal checks."""
+    h = 1.0
+    pitch = (N * h / w, N * h / w)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=seed, L=N * h, n_sph=3, n_pl=2, shell_mm=2 * h, exponent=exponent,
+                      speckle_sigma=speckle)
+    sw = azimuth_sweeps(N, h, n_frames // 2, w, w, pitch, (0.0, 30.0), 0.5, jitter_deg,
+                        seed=seed * 7 + 3, calib=C)
+    sl = slice_poses(seed * 7 + 5, sw, n_slices, max(1, n_slices - 1), slice_w, slice_h,
+                     (N * h / slice_w, N * h / slice_h), N, h, C, max_rot_deg=20.0)
+    return Workload(f"tiny {N}^3 seed {seed}", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl,
+                    frame_seed=seed, params=dict(DEFAULT_PARAMS))
