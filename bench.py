@@ -1,0 +1,390 @@
+#!/usr/bin/env python3
+"""Benchmark of the directionality-aware reslice on one MI355X.
+
+Workload (synthetic, shaped like the paper's timing experiment): a 256^3 grid
+of 0.125 mm voxels compounded from three azimuth sweeps of 600 frames of
+256^2 uint8 pixels (1 mm / 2 deg pose jitter), then 1000 slices of 512^2
+pixels at 0.0625 mm, 80 % near acquired poses and 20 % uniformly oriented,
+resliced with an interpolation radius of one voxel.
+
+A step is one pass over the 1000-slice batch with one dare_reslice launch per
+slice (FP32 storage, FP64 positions, FP32 blending), inputs resident in HBM.
+The same run also measures: the reconstruction (compounding) of the frames,
+BF16/FP16/FP8 storage and the batched entry point on the same slices,
+unloaded submit-to-host latency, the reslice kernel's average launch time
+with HIP events against its algorithmic bytes (the HBM roofline), and the FP64
+CPU oracle on a bounded sample of the same workload.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as ct
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PAIR_BYTES = {"f32": 8, "bf16": 4, "f16": 4, "fp8": 2}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dare_reslice.hip", "dare_codec.h", "dare_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_26325_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def footprint_voxels(torch, P, calib, origin, h, dims, W, H, pitch):
+    """Distinct in-grid voxels with non-zero trilinear weight over one slice (untimed)."""
+    dev = "cuda"
+    T = torch.tensor(P, dtype=torch.float64, device=dev) @ torch.tensor(calib, dtype=torch.float64, device=dev)
+    i = torch.arange(W, device=dev, dtype=torch.float64) * pitch[0]
+    j = torch.arange(H, device=dev, dtype=torch.float64) * pitch[1]
+    p = T[:3, 3] + i[None, :, None] * T[:3, 0] + j[:, None, None] * T[:3, 1]
+    c = (p - torch.tensor(origin, dtype=torch.float64, device=dev)) / h
+    b = torch.floor(c)
+    f = c - b
+    b = b.to(torch.int64)
+    n = torch.tensor(dims, device=dev)
+    keys = []
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                d = torch.tensor([dx, dy, dz], device=dev)
+                v = b + d
+                ok = ((v >= 0) & (v < n)).all(-1)
+                nz = torch.ones_like(ok)
+                for a, da in enumerate((dx, dy, dz)):
+                    if da == 1:
+                        nz &= f[..., a] > 0
+                ok &= nz
+                vv = v[ok]
+                keys.append((vv[:, 2] * n[1] + vv[:, 1]) * n[0] + vv[:, 0])
+    return int(torch.unique(torch.cat(keys)).numel())
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--slices", type=int, default=1000)
+    ap.add_argument("--cpu-slices", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--roofline-sample", type=int, default=100)
+    ap.add_argument("--latency-sample", type=int, default=200)
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "reslice_traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures one GPU's share of the work "
+              "(--gpus 1); multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_26325_amd as dare
+    import synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sh = ct.c_void_p(stream.cuda_stream)
+
+    wl = synth.config2(n_slices=args.slices, n_near=int(round(0.8 * args.slices)))
+    log(f"workload: {wl.name}")
+    t0 = time.perf_counter()
+    frames = wl.render(dev)
+    torch.cuda.synchronize()
+    log(f"rendered {tuple(frames.shape)} frames on the GPU in {time.perf_counter() - t0:.1f} s")
+    poses = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).to(dev)
+    geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+    prm = dare.default_params()
+    nb = 1
+    for d in wl.dims:
+        nb *= (d + 7) // 8
+    pitch_f = wl.sweep.pitch
+    F, Hf, Wf = frames.shape
+
+    def build_volume(dtype):
+        vol = dare.Volume(geom, prm, dtype=dtype, bricks=nb * 40)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        vol.reconstruct(frames, poses, pitch_f)
+        torch.cuda.synchronize()
+        return vol, time.perf_counter() - t
+
+    vol, _ = build_volume("f32")          # first build warms up the kernels
+    recon_times = []
+    for _ in range(3):
+        v2, dt = build_volume("f32")
+        recon_times.append(dt)
+        del v2
+    info = vol.info()
+    log(f"volume: {info.bins} bins, {info.bricks_used} bricks of 8^3 used; reconstruct median "
+        f"{1e3 * np.median(recon_times):.2f} ms")
+
+    sl = wl.slices
+    W, H, pitch = sl.width, sl.height, sl.pitch
+    specs = [dare.make_spec(P, W, H, pitch) for P in sl.probe_poses]
+    spec_refs = [ct.byref(s) for s in specs]
+    outs = torch.empty((len(specs), H, W), dtype=torch.float32, device=dev)
+    out_ptrs = [ct.c_void_p(outs[k].data_ptr()) for k in range(len(specs))]
+    reslice = dare.lib.dare_reslice
+
+    def step(v):
+        h = v.handle
+        for k in range(len(specs)):
+            st = reslice(h, spec_refs[k], out_ptrs[k], sh)
+            if st != 0:
+                raise dare.DareError(st, "dare_reslice")
+
+    for _ in range(args.warmup):
+        step(vol)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step(vol)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    px_per_step = len(specs) * W * H
+    value = px_per_step / (ms_per_step / 1e3) / 1e6
+    log(f"fp32 one launch per slice: {ms_per_step:.2f} ms/step ({ev0.elapsed_time(ev1) / args.steps:.2f} ms "
+        f"device), {value:.0f} Mpixel/s")
+    nan_frac = float(torch.isnan(outs).float().mean().item())
+
+    # ---- roofline of the reslice kernel: per-launch HIP events, algorithmic bytes per launch
+    nroof = min(args.roofline_sample, len(specs))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nroof)]
+    for k in range(nroof):
+        evs[k][0].record(stream)
+        reslice(vol.handle, spec_refs[k], out_ptrs[k], sh)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    durs = np.array([a.elapsed_time(b) * 1e-3 for a, b in evs])    # seconds
+    algo = []
+    kacts = []
+    for k in range(nroof):
+        kact = len(vol.active_bins(sl.probe_poses[k], W, H, pitch)[0])
+        nvox = footprint_voxels(torch, sl.probe_poses[k], wl.calib, wl.origin, wl.spacing, wl.dims, W, H, pitch)
+        algo.append(4 * W * H + nvox * kact * PAIR_BYTES["f32"])
+        kacts.append(kact)
+    algo = np.array(algo, dtype=np.float64)
+    achieved = float(algo.sum() / durs.sum() / 1e9)
+    traffic = None
+    try:
+        with open(args.traffic) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_hash") == kernel_source_hash() and tj.get("workload") == "config2-fp32":
+            traffic = tj.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_reslice_r1<fp32>", "avg_launch_us": round(1e6 * float(durs.mean()), 2),
+                "algo_bytes_per_launch": round(float(algo.mean())), "sample_launches": nroof,
+                "mean_active_bins": round(float(np.mean(kacts)), 2),
+                "bytes_per_px": round(float(algo.mean()) / (W * H), 2)}
+    log(f"roofline: {achieved:.0f} GB/s algorithmic over {nroof} launches, mean {1e6 * durs.mean():.1f} us, "
+        f"{algo.mean() / 1e6:.2f} MB/launch, active bins {np.mean(kacts):.2f}")
+
+    # ---- copy bandwidth on this machine (calibrates the roofline and the byte counters)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dare.dare_copy_probe(src, dst, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        dare.dare_copy_probe(src, dst, nbytes)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roofline["copy_probe_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+
+    # ---- unloaded latency: submit -> result in pinned host memory, one request at a time
+    lat_out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    lat_ptr = ct.c_void_p(lat_out.data_ptr())
+
+    def latencies(v, n):
+        host = torch.empty((H, W), dtype=torch.float32, pin_memory=True)
+        lat, dlat = [], []
+        for k in range(n):
+            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t = time.perf_counter()
+            e_a.record(stream)
+            reslice(v.handle, spec_refs[k % len(specs)], lat_ptr, sh)
+            e_b.record(stream)
+            host.copy_(lat_out, non_blocking=True)
+            stream.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t))
+            dlat.append(e_a.elapsed_time(e_b))
+        return {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4),
+                "device_p50": round(percentile(dlat, 50), 4), "device_p99": round(percentile(dlat, 99), 4)}
+
+    lat32 = latencies(vol, args.latency_sample)
+    log(f"fp32 latency submit->host p50 {lat32['p50']:.3f} ms p99 {lat32['p99']:.3f} ms")
+
+    # ---- precision forms and the batched entry point on the same slices
+    forms = {}
+    form_vols = {}
+    if not args.no_forms:
+        for dt in ("bf16", "f16", "fp8"):
+            v, dtr = build_volume(dt)
+            form_vols[dt] = v
+            outs_f = torch.empty_like(outs)
+            ptrs_f = [ct.c_void_p(outs_f[k].data_ptr()) for k in range(len(specs))]
+            for _ in range(max(1, args.warmup)):
+                for k in range(len(specs)):
+                    reslice(v.handle, spec_refs[k], ptrs_f[k], sh)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for k in range(len(specs)):
+                reslice(v.handle, spec_refs[k], ptrs_f[k], sh)
+            torch.cuda.synchronize()
+            mpx = px_per_step / (time.perf_counter() - t) / 1e6
+            m = ~torch.isnan(outs)
+            diff = (outs_f - outs)[m].abs()
+            forms[dt] = {"one_launch_per_slice_Mpx_s": round(mpx, 1),
+                         "max_abs_diff_vs_fp32": round(float(diff.max().item()), 4),
+                         "mean_abs_diff_vs_fp32": round(float(diff.mean().item()), 5),
+                         "reconstruct_ms": round(1e3 * dtr, 2)}
+            if dt == "bf16":
+                forms[dt]["latency_ms"] = latencies(v, args.latency_sample)
+            log(f"{dt}: {mpx:.0f} Mpixel/s, max |diff| vs fp32 {forms[dt]['max_abs_diff_vs_fp32']}")
+            del outs_f
+        # batched: groups of 64 slices per dare_reslice_batch call
+        for dt, v in (("f32", vol), ("bf16", form_vols["bf16"])):
+            G = 64
+            groups = [list(range(a, min(a + G, len(specs)))) for a in range(0, len(specs), G)]
+            ws_bytes = max(dare.dare_reslice_batch_workspace_bytes([v] * len(g), [specs[k] for k in g])
+                           for g in groups)
+            wss = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in groups]
+            outs_b = torch.empty_like(outs)
+
+            def run_batches():
+                for gi, g in enumerate(groups):
+                    dare.dare_reslice_batch([v] * len(g), [specs[k] for k in g], [outs_b[k] for k in g], wss[gi])
+
+            run_batches()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                run_batches()
+            torch.cuda.synchronize()
+            mpx = args.steps * px_per_step / (time.perf_counter() - t) / 1e6
+            key = "fp32" if dt == "f32" else dt
+            forms.setdefault(key, {})["batched64_Mpx_s"] = round(mpx, 1)
+            if dt == "f32":
+                same = bool(torch.equal(torch.nan_to_num(outs_b, nan=-1.0), torch.nan_to_num(outs, nan=-1.0)))
+                forms[key]["batched_equals_alone"] = same
+            log(f"{dt} batched x64: {mpx:.0f} Mpixel/s")
+            del outs_b, wss
+
+    # ---- the FP64 oracle on the host cores: bounded sample of the same workload
+    cpu_baseline = None
+    if not args.no_cpu_baseline:
+        from oracle import compound, reslice as oreslice
+        from oracle.reslice import Params as OParams
+        oprm = OParams()
+        fr_host = frames.cpu().numpy()
+        t = time.perf_counter()
+        g = compound.empty_grid(wl.origin, wl.spacing, wl.dims, oprm.bin_tol_deg, oprm.max_bins)
+        compound.compound(g, fr_host, wl.sweep.probe_poses, wl.calib, pitch_f)
+        t_comp = time.perf_counter() - t
+        log(f"oracle compounding of {F} frames: {t_comp:.1f} s, {g.K} bins")
+        ncs = min(args.cpu_slices, len(specs))
+        t = time.perf_counter()
+        a64, c64 = g.mean_count()
+        rep_n, rep_x = g.codebook.arrays()
+        refs = [oreslice.reslice(a64, c64, g.origin, g.spacing, rep_n, rep_x, wl.calib, sl.probe_poses[k], W, H,
+                                 pitch, oprm) for k in range(ncs)]
+        t_res = time.perf_counter() - t
+        cpu_mpx = ncs * W * H / t_res / 1e6
+        errs = {}
+        for name, o in (("fp32", outs), *((k, None) for k in form_vols)):
+            if o is None:
+                o = torch.empty((ncs, H, W), dtype=torch.float32, device=dev)
+                for k in range(ncs):
+                    reslice(form_vols[name].handle, spec_refs[k], ct.c_void_p(o[k].data_ptr()), sh)
+                torch.cuda.synchronize()
+            worst, mean_acc, cnt, mask_ok = 0.0, 0.0, 0, True
+            for k in range(ncs):
+                got = o[k].cpu().numpy().astype(np.float64)
+                m = ~np.isnan(refs[k])
+                mask_ok &= bool(np.array_equal(np.isnan(got), np.isnan(refs[k])))
+                if m.any():
+                    d = np.abs(got[m] - refs[k][m])
+                    worst = max(worst, float(d.max()))
+                    mean_acc += float(d.sum())
+                    cnt += int(m.sum())
+            errs[name] = {"max_abs_grey": round(worst, 5), "mean_abs_grey": round(mean_acc / max(cnt, 1), 6),
+                          "nan_mask_equal": mask_ok}
+        cpu_baseline = {"value": round(cpu_mpx, 4), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                        "sample": f"FP64 NumPy oracle reslicing {ncs} of the {len(specs)} 512x512 slices "
+                                  f"({ncs * W * H} pixels, {t_res:.1f} s) on its own grid; compounding all {F} "
+                                  f"frames took {t_comp:.1f} s and is not in the rate",
+                        "seconds_per_slice": round(t_res / ncs, 3),
+                        "compound_seconds": round(t_comp, 2),
+                        "gpu_error_vs_fp64_on_sample": errs}
+        log(f"oracle: {cpu_mpx:.3f} Mpixel/s ({t_res / ncs:.2f} s per slice); errors {errs}")
+
+    result = {
+        "metric": "reslice Mpixel/s + p50/p99 latency, served BF16 vs plain FP32; % HBM roofline",
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config2: 256^3 grid @0.125 mm from 3x600 frames 256^2 (1 mm/2 deg jitter); "
+                               f"{len(specs)} slices 512^2 @0.0625 mm, one dare_reslice launch per slice, radius 1",
+                   "grid": list(wl.dims), "voxel_mm": wl.spacing, "frames": int(F), "slices": len(specs),
+                   "slice_px": [W, H], "storage": "fp32", "positions": "f64", "bins": int(info.bins),
+                   "bricks_used": int(info.bricks_used), "unassigned_fraction": round(nan_frac, 4)},
+        "roofline": roofline,
+        "latency_ms": {"fp32": lat32, **({"bf16": forms["bf16"]["latency_ms"]} if "bf16" in forms else {})},
+        "reconstruct": {"frames": int(F), "frame_px": [Wf, Hf], "median_ms": round(1e3 * float(np.median(recon_times)), 3),
+                        "frames_per_s": round(F / float(np.median(recon_times)), 1),
+                        "input_Mpx_s": round(F * Wf * Hf / float(np.median(recon_times)) / 1e6, 1)},
+        "forms": forms,
+        "cpu_baseline": cpu_baseline,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * dare.h -- C ABI of the MI355X (gfx950) directionality-aware ultrasound
+ * reconstruction and reslicing library.
+ *
+ * Method: "Real-time, Directionality Aware 3D Ultrasound Reconstruction and
+ * Re-Slicing" (DARE), Sec. 2.1.  Tracked 2D frames are voxelized into a grid
+ * that keeps, per voxel, what was seen from each acquisition direction
+ * ("Volume reconstruction", Fig. 1); a virtual plane at any pose is then
+ * resliced by gathering each pixel's cubic neighbourhood, discarding samples
+ * whose direction is misaligned beyond two angular thresholds and blending
+ * the rest with the exponential weights of Eq. 1 and Eq. 2, weighted by
+ * distance (Fig. 2); a pixel with no surviving sample is unassigned.
+ *
+ * Conventions shared by every entry point:
+ *   - Millimetres everywhere.  4x4 poses are row-major; the last row is
+ *     (0, 0, 0, 1).  A *probe pose* maps probe coordinates to world (what the
+ *     tracker reports); the calibration maps image millimetres to the probe,
+ *     so an image's pose is T = P . C.  Column 0 of T is the lateral (x)
+ *     axis, column 1 the depth (beam) axis, column 2 the plane normal.
+ *   - Pixel (i, j) of a frame or slice is column i (lateral), row j (depth);
+ *     it lies at image millimetres (i * pitch[0], j * pitch[1], 0).  Images
+ *     are row-major, row j at offset j * width.
+ *   - Voxel (ix, iy, iz) has its centre at origin + spacing * (ix, iy, iz).
+ *   - Pose composition and sample positions are evaluated in FP64 on the GPU,
+ *     without fused multiply-add and in a fixed order, so that nearest-voxel
+ *     decisions are reproducible bit for bit.
+ *   - "_dev" pointers are device memory of the current HIP device; host
+ *     structs are read before the call returns.  Every call that takes a
+ *     stream is asynchronous on it unless documented otherwise; device
+ *     buffers must stay valid until the stream reaches the call.
+ *   - Errors are status codes; no exception crosses the ABI.  On any error
+ *     other than DARE_WARN_BINS_SATURATED nothing has been enqueued, or the
+ *     volume has been restored to its state before the call.
+ *   - A `stream` argument is a hipStream_t passed as void*; NULL is the
+ *     default stream.
+ */
+#ifndef DARE_H
+#define DARE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DARE_OK = 0,
+    DARE_ERR_INVALID_ARG = 1,     /* null pointer, size <= 0, unsupported radius or dtype     */
+    DARE_ERR_BAD_POSE = 2,        /* non-finite pose, or rotation with |R^T R - I|_inf > 1e-4 */
+    DARE_ERR_BUDGET = 3,          /* the volume's arena cannot hold the new bricks            */
+    DARE_ERR_HIP = 4,             /* a HIP runtime call failed                                */
+    DARE_WARN_BINS_SATURATED = 5, /* codebook full: frames went to their closest bin         */
+    DARE_ERR_NOT_READY = 6,       /* server ticket still in flight                            */
+    DARE_ERR_QUEUE_FULL = 7       /* server admission queue is full                           */
+} dare_status;
+
+/* Storage precision of the directional grid (values and counts).  The
+ * reslice accumulates in FP32 whatever the storage; poses and positions are
+ * always FP64.  FP8 is OCP e4m3fn with one FP32 scale per (bin, brick) for
+ * the values and one for the counts. */
+typedef enum { DARE_F32 = 0, DARE_BF16 = 1, DARE_F16 = 2, DARE_FP8_E4M3 = 3 } dare_dtype;
+
+/* Volume geometry (Sec. 2.1: "a 3D bounding box ... voxelized into a 3D grid"). */
+typedef struct {
+    double origin_mm[3];   /* world position of voxel (0,0,0)'s centre                     */
+    double spacing_mm;     /* isotropic voxel size h > 0                                    */
+    int32_t dims[3];       /* nx, ny, nz > 0                                                */
+    double calib[16];      /* image-mm -> probe, row-major (the probe calibration)          */
+} dare_geometry;
+
+/* Method parameters.  Defaults (dare_default_params): k_normal = 10,
+ * k_inplane = 5, thresholds 25 and 15 degrees (Sec. 2.1, constants after
+ * Eq. 2); radius_vox = 1 (interpolation distance of one voxel, the paper's
+ * 0.125 mm at 0.125 mm voxels); bin_tol_deg = 5 and max_bins = 64 for the
+ * codebook of acquisition orientations; normal_axis = 2 (the acquisition
+ * normal of Eq. 1 is the image-plane normal; 1 selects the beam axis). */
+typedef struct {
+    double k_normal, k_inplane;
+    double thr_normal_deg, thr_inplane_deg;
+    double radius_vox;     /* R: integer 1..8; the neighbourhood is |c - v|_inf < R         */
+    double bin_tol_deg;    /* leader-clustering tolerance delta, degrees, >= 0              */
+    int32_t max_bins;      /* 1..64                                                         */
+    int32_t normal_axis;   /* 1 or 2                                                        */
+} dare_params;
+
+/* A reslice request: the virtual image plane of Sec. 2.1 "Reslicing". */
+typedef struct {
+    double probe_pose[16]; /* probe -> world, row-major, FP64                               */
+    int32_t width, height; /* output pixels, > 0                                            */
+    double pitch_mm[2];    /* pixel spacing along the lateral and depth axes, > 0           */
+} dare_slice_spec;
+
+typedef struct dare_volume dare_volume;
+
+typedef struct {
+    int32_t bins;             /* codebook size K                                         */
+    int32_t saturated;        /* 1 once a frame could not open a new bin                 */
+    int64_t bricks_used;      /* allocated (bin, 8^3 brick) slots                        */
+    int64_t bricks_capacity;  /* slots the arena can hold                                */
+    int64_t bytes_per_brick;  /* accumulators + stored pairs (+ scales) per slot         */
+    int64_t brick_grid[3];    /* bricks along x, y, z                                    */
+} dare_volume_info;
+
+/* Fill *p with the paper's parameters (see dare_params). */
+void dare_default_params(dare_params* p);
+
+/* Text of a status code (static storage). */
+const char* dare_status_str(dare_status s);
+
+/* Bytes of arena a volume needs for `bricks` allocated (bin, brick) slots,
+ * including its fixed tables.  Use it to size `arena_bytes`. */
+uint64_t dare_volume_arena_bytes(const dare_geometry* g, const dare_params* p, dare_dtype dtype,
+                                 int64_t bricks);
+
+/* Create an empty volume whose whole device state lives in the caller's
+ * arena [arena_dev, arena_dev + arena_bytes) on the current device; the
+ * arena size is the volume's HBM budget.  The arena must stay allocated
+ * until dare_volume_destroy.  Synchronous.  Errors: INVALID_ARG (null,
+ * non-positive dims/spacing, bad params, arena smaller than the fixed
+ * tables), BAD_POSE (calibration not rigid), HIP. */
+dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dare_dtype dtype,
+                               void* arena_dev, uint64_t arena_bytes, dare_volume** out);
+
+/* Release the handle (not the arena).  Synchronises the device first. */
+dare_status dare_volume_destroy(dare_volume* v);
+
+/* Volume reconstruction (Sec. 2.1, Fig. 1): compose each frame's pose with
+ * the calibration, assign it to a direction bin, voxelize every pixel to its
+ * nearest voxel (ties rounded up) and add its intensity and a count to that
+ * (bin, voxel); pixels outside the grid are dropped.  Frames are added to
+ * what the volume already holds (incremental), in the given order.
+ *   frames_dev       n * h * w uint8, frame-major, row-major images
+ *   probe_poses_dev  n * 16 float32, row-major probe poses
+ *   pitch_mm         pixel spacing of the frames (host)
+ * Sums are exact integers, so the result does not depend on thread order.
+ * Synchronises `stream` once per batch of up to 4096 frames (pose check and
+ * budget admission); the final finalize step is left enqueued.
+ * Errors: INVALID_ARG, BAD_POSE (a frame pose is not rigid: that batch is
+ * rolled back), BUDGET (the new bricks do not fit: that batch is rolled
+ * back), HIP.  Returns DARE_WARN_BINS_SATURATED when the codebook is full. */
+dare_status dare_reconstruct_frames(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w,
+                                    int32_t h, const double pitch_mm[2], const float* probe_poses_dev,
+                                    void* stream);
+
+/* Reslice one plane (Sec. 2.1 "Reslicing", Eq. 1, Eq. 2): for each output
+ * pixel, the FP64 sample position, its neighbourhood |c - v|_inf < R with
+ * tent weights prod(1 - |c_a - v_a| / R), per-voxel direction blending with
+ * the angular weight of each bin that passes both thresholds, then the
+ * distance-weighted average over valid voxels.
+ *   out_dev   height * width float32, row-major; NaN marks an unassigned pixel.
+ * Enqueues a single kernel; allocates nothing.  Errors: INVALID_ARG,
+ * BAD_POSE (slice pose not rigid), HIP. */
+dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, float* out_dev, void* stream);
+
+/* Bytes of device workspace dare_reslice_batch needs for these n requests. */
+uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, const dare_slice_spec* specs,
+                                            int32_t n);
+
+/* Reslice n planes, possibly of different volumes, sizes and poses, in one
+ * launch per (storage dtype, radius) group.  Each request's result equals
+ * what dare_reslice gives for it alone.
+ *   vols       n volume handles (host array)
+ *   specs      n requests (host array)
+ *   outs_dev   n device output pointers (host array), each height*width float32
+ *   workspace_dev / workspace_bytes: device scratch for the request table,
+ *              at least dare_reslice_batch_workspace_bytes; must not be in use
+ *              by another in-flight call.
+ * Errors: INVALID_ARG, BAD_POSE, HIP. */
+dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_spec* specs,
+                               float* const* outs_dev, int32_t n, void* workspace_dev,
+                               uint64_t workspace_bytes, void* stream);
+
+/* Bounding box of the frames (Sec. 2.1: computed from the collected
+ * transducer positions): the axis-aligned box of every frame's four corner
+ * pixel centres, origin = its minimum corner, dims = ceil(extent / h) + 1.
+ * Host-only.  probe_poses_host: n * 16 float32.  Copies the calibration into
+ * out->calib.  Errors: INVALID_ARG, BAD_POSE. */
+dare_status dare_bounds_from_frames(const float* probe_poses_host, int32_t n, int32_t w, int32_t h,
+                                    const double pitch_mm[2], const double calib[16], double spacing_mm,
+                                    dare_geometry* out);
+
+/* Volume bookkeeping.  Synchronises the device. */
+dare_status dare_volume_get_info(const dare_volume* v, dare_volume_info* out);
+
+/* Codebook readback: up to 64 representative (normal, x-axis) unit vectors,
+ * 3 doubles each, and the bin count.  Synchronises the device. */
+dare_status dare_volume_get_codebook(const dare_volume* v, double* rep_n_host, double* rep_x_host,
+                                     int32_t* bins);
+
+/* Dense copies for tests and tools.  All arrays are (bins, nz, ny, nx),
+ * x fastest, on the device; `bins` must equal the volume's bin count.
+ *   download_sums:    exact per-(bin, voxel) intensity sums and counts.
+ *   download_storage: the stored values and counts as the reslice reads them
+ *                     (dequantised to float32), 0 where the voxel is empty.
+ *   upload_sums:      replace the volume's content with given sums/counts and
+ *                     codebook (rep arrays: bins * 3 doubles, host), then
+ *                     finalize; BUDGET if the occupied bricks do not fit.
+ * upload synchronises the stream; the downloads are asynchronous. */
+dare_status dare_volume_download_sums(const dare_volume* v, uint32_t* sums_dev, uint32_t* counts_dev,
+                                      int32_t bins, void* stream);
+dare_status dare_volume_download_storage(const dare_volume* v, float* values_dev, float* counts_dev,
+                                         int32_t bins, void* stream);
+dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n_host, const double* rep_x_host,
+                                    int32_t bins, const uint32_t* sums_dev, const uint32_t* counts_dev,
+                                    void* stream);
+
+/* The direction bins that survive both thresholds for this slice pose and
+ * their Eq. 2 weights (Sec. 2.1, Eq. 1 and Eq. 2), evaluated on the host in
+ * FP64 from the volume's codebook.  bins_out / weights_out (may be NULL)
+ * receive up to 64 entries; *count the number.  Synchronises the device.
+ * Errors: INVALID_ARG, BAD_POSE, HIP. */
+dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* spec, int32_t* bins_out,
+                                   double* weights_out, int32_t* count);
+
+/* Streaming copy of n_bytes (multiple of 16) from src_dev to dst_dev: the
+ * bandwidth probe that calibrates the HBM roofline and the byte counters. */
+dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DARE_H */

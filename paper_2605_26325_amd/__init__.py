@@ -1,0 +1,293 @@
+"""Python binding of libdare, the MI355X directionality-aware reslicing library.
+
+Thin ctypes marshalling over the C ABI in include/dare.h: every step of the
+reconstruction and reslice runs in the library's HIP kernels.  torch supplies
+device memory (arenas, frames, outputs) and streams.  There is no fallback:
+importing this package without the built library raises.
+
+The functions named like the C entry points (``dare_reconstruct_frames``,
+``dare_reslice``, ``dare_reslice_batch``, ...) take the same arguments with
+Python/torch types; ``Volume`` bundles a volume handle with its arena.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import warnings
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdare.so")
+
+F32, BF16, F16, FP8 = 0, 1, 2, 3
+DTYPES = {"f32": F32, "fp32": F32, "bf16": BF16, "f16": F16, "fp16": F16, "fp8": FP8, "fp8_e4m3": FP8}
+DTYPE_NAMES = {F32: "fp32", BF16: "bf16", F16: "fp16", FP8: "fp8"}
+
+OK, ERR_INVALID_ARG, ERR_BAD_POSE, ERR_BUDGET, ERR_HIP, WARN_BINS_SATURATED, ERR_NOT_READY, ERR_QUEUE_FULL = range(8)
+
+
+class Geometry(ct.Structure):
+    _fields_ = [("origin_mm", ct.c_double * 3), ("spacing_mm", ct.c_double), ("dims", ct.c_int32 * 3),
+                ("calib", ct.c_double * 16)]
+
+
+class Params(ct.Structure):
+    _fields_ = [("k_normal", ct.c_double), ("k_inplane", ct.c_double), ("thr_normal_deg", ct.c_double),
+                ("thr_inplane_deg", ct.c_double), ("radius_vox", ct.c_double), ("bin_tol_deg", ct.c_double),
+                ("max_bins", ct.c_int32), ("normal_axis", ct.c_int32)]
+
+
+class SliceSpec(ct.Structure):
+    _fields_ = [("probe_pose", ct.c_double * 16), ("width", ct.c_int32), ("height", ct.c_int32),
+                ("pitch_mm", ct.c_double * 2)]
+
+
+class VolumeInfo(ct.Structure):
+    _fields_ = [("bins", ct.c_int32), ("saturated", ct.c_int32), ("bricks_used", ct.c_int64),
+                ("bricks_capacity", ct.c_int64), ("bytes_per_brick", ct.c_int64), ("brick_grid", ct.c_int64 * 3)]
+
+
+class DareError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2605_26325_amd/build.py`")
+    lib = ct.CDLL(LIB_PATH)
+    P, V, I32, I64, U64, D = ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint64, ct.c_double
+    sig = {
+        "dare_default_params": (None, [ct.POINTER(Params)]),
+        "dare_status_str": (ct.c_char_p, [ct.c_int]),
+        "dare_volume_arena_bytes": (U64, [ct.POINTER(Geometry), ct.POINTER(Params), ct.c_int, I64]),
+        "dare_volume_create": (ct.c_int, [ct.POINTER(Geometry), ct.POINTER(Params), ct.c_int, P, U64,
+                                          ct.POINTER(V)]),
+        "dare_volume_destroy": (ct.c_int, [V]),
+        "dare_reconstruct_frames": (ct.c_int, [V, P, I32, I32, I32, ct.POINTER(D), P, P]),
+        "dare_reslice": (ct.c_int, [V, ct.POINTER(SliceSpec), P, P]),
+        "dare_reslice_batch_workspace_bytes": (U64, [ct.POINTER(V), ct.POINTER(SliceSpec), I32]),
+        "dare_reslice_batch": (ct.c_int, [ct.POINTER(V), ct.POINTER(SliceSpec), ct.POINTER(P), I32, P, U64, P]),
+        "dare_bounds_from_frames": (ct.c_int, [P, I32, I32, I32, ct.POINTER(D), ct.POINTER(D), D,
+                                               ct.POINTER(Geometry)]),
+        "dare_volume_get_info": (ct.c_int, [V, ct.POINTER(VolumeInfo)]),
+        "dare_volume_get_codebook": (ct.c_int, [V, ct.POINTER(D), ct.POINTER(D), ct.POINTER(I32)]),
+        "dare_volume_download_sums": (ct.c_int, [V, P, P, I32, P]),
+        "dare_volume_download_storage": (ct.c_int, [V, P, P, I32, P]),
+        "dare_volume_upload_sums": (ct.c_int, [V, ct.POINTER(D), ct.POINTER(D), I32, P, P, P]),
+        "dare_copy_probe": (ct.c_int, [P, P, U64, P]),
+        "dare_slice_active_bins": (ct.c_int, [V, ct.POINTER(SliceSpec), ct.POINTER(I32), ct.POINTER(D),
+                                              ct.POINTER(I32)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(s: int) -> str:
+    return lib.dare_status_str(int(s)).decode()
+
+
+def _check(status: int, where: str, allow_warn: bool = True) -> int:
+    if status == OK:
+        return status
+    if status == WARN_BINS_SATURATED and allow_warn:
+        warnings.warn(f"{where}: {status_str(status)}", RuntimeWarning, stacklevel=3)
+        return status
+    raise DareError(status, where)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t) -> ct.c_void_p:
+    return ct.c_void_p(t.data_ptr())
+
+
+def default_params(**over) -> Params:
+    p = Params()
+    lib.dare_default_params(ct.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def make_geometry(origin, spacing, dims, calib) -> Geometry:
+    g = Geometry()
+    g.origin_mm[:] = [float(v) for v in origin]
+    g.spacing_mm = float(spacing)
+    g.dims[:] = [int(v) for v in dims]
+    g.calib[:] = [float(v) for v in np.asarray(calib, np.float64).reshape(16)]
+    return g
+
+
+def make_spec(probe_pose, width, height, pitch) -> SliceSpec:
+    s = SliceSpec()
+    s.probe_pose[:] = [float(v) for v in np.asarray(probe_pose, np.float64).reshape(16)]
+    s.width, s.height = int(width), int(height)
+    s.pitch_mm[:] = [float(pitch[0]), float(pitch[1])]
+    return s
+
+
+def dare_volume_arena_bytes(geometry: Geometry, params: Params, dtype: int, bricks: int) -> int:
+    return int(lib.dare_volume_arena_bytes(ct.byref(geometry), ct.byref(params), int(dtype), int(bricks)))
+
+
+def dare_bounds_from_frames(probe_poses, width, height, pitch, calib, spacing) -> Geometry:
+    P = np.ascontiguousarray(np.asarray(probe_poses, np.float32).reshape(-1, 16))
+    g = Geometry()
+    pitch_arr = (ct.c_double * 2)(float(pitch[0]), float(pitch[1]))
+    cal = (ct.c_double * 16)(*[float(v) for v in np.asarray(calib, np.float64).reshape(16)])
+    _check(lib.dare_bounds_from_frames(P.ctypes.data_as(ct.c_void_p), len(P), int(width), int(height), pitch_arr,
+                                       cal, float(spacing), ct.byref(g)), "dare_bounds_from_frames")
+    return g
+
+
+def dare_reconstruct_frames(vol: "Volume", frames, width, height, pitch, probe_poses, stream=None) -> int:
+    n = int(frames.shape[0]) if frames.dim() == 3 else int(frames.shape[0])
+    pitch_arr = (ct.c_double * 2)(float(pitch[0]), float(pitch[1]))
+    return _check(lib.dare_reconstruct_frames(vol.handle, _ptr(frames), n, int(width), int(height), pitch_arr,
+                                              _ptr(probe_poses), _stream(stream)), "dare_reconstruct_frames")
+
+
+def dare_reslice(vol: "Volume", spec: SliceSpec, out, stream=None) -> int:
+    return _check(lib.dare_reslice(vol.handle, ct.byref(spec), _ptr(out), _stream(stream)), "dare_reslice")
+
+
+def dare_reslice_batch_workspace_bytes(vols, specs) -> int:
+    n = len(vols)
+    hv = (ct.c_void_p * n)(*[v.handle for v in vols])
+    hs = (SliceSpec * n)(*specs)
+    return int(lib.dare_reslice_batch_workspace_bytes(hv, hs, n))
+
+
+def dare_reslice_batch(vols, specs, outs, workspace, stream=None) -> int:
+    n = len(vols)
+    hv = (ct.c_void_p * n)(*[v.handle for v in vols])
+    hs = (SliceSpec * n)(*specs)
+    ho = (ct.c_void_p * n)(*[o.data_ptr() for o in outs])
+    return _check(lib.dare_reslice_batch(hv, hs, ho, n, _ptr(workspace), int(workspace.numel()),
+                                         _stream(stream)), "dare_reslice_batch")
+
+
+def dare_copy_probe(src, dst, nbytes, stream=None) -> int:
+    return _check(lib.dare_copy_probe(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)), "dare_copy_probe")
+
+
+class Volume:
+    """A volume handle plus the torch-owned device arena it lives in."""
+
+    def __init__(self, geometry: Geometry, params: Params | None = None, dtype="f32", bricks: int | None = None,
+                 arena_bytes: int | None = None, device="cuda"):
+        import torch
+        self.geometry = geometry
+        self.params = params if params is not None else default_params()
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if arena_bytes is None:
+            if bricks is None:
+                # every (bin, brick) when that fits in 2 GiB, else room for 8 bins' worth
+                nb = 1
+                for d in geometry.dims:
+                    nb *= (int(d) + 7) // 8
+                bricks = nb * int(self.params.max_bins)
+                if dare_volume_arena_bytes(geometry, self.params, self.dtype, bricks) > (2 << 30):
+                    bricks = nb * 8
+            arena_bytes = dare_volume_arena_bytes(geometry, self.params, self.dtype, bricks)
+            if arena_bytes == 0:
+                raise DareError(ERR_INVALID_ARG, "dare_volume_arena_bytes")
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ct.c_void_p()
+        _check(lib.dare_volume_create(ct.byref(geometry), ct.byref(self.params), self.dtype, _ptr(self.arena),
+                                      int(arena_bytes), ct.byref(h)), "dare_volume_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.dare_volume_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dims(self):
+        return tuple(int(d) for d in self.geometry.dims)
+
+    def reconstruct(self, frames, probe_poses, pitch, stream=None) -> int:
+        F, H, W = frames.shape
+        return dare_reconstruct_frames(self, frames, W, H, pitch, probe_poses, stream)
+
+    def reslice(self, probe_pose, width, height, pitch, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((height, width), dtype=torch.float32, device=self.arena.device)
+        dare_reslice(self, make_spec(probe_pose, width, height, pitch), out, stream)
+        return out
+
+    def active_bins(self, probe_pose, width, height, pitch):
+        """(bins, weights) that pass both angular thresholds for this slice."""
+        b = (ct.c_int32 * 64)()
+        w = (ct.c_double * 64)()
+        n = ct.c_int32()
+        _check(lib.dare_slice_active_bins(self.handle, ct.byref(make_spec(probe_pose, width, height, pitch)), b, w,
+                                          ct.byref(n)), "dare_slice_active_bins")
+        return list(b[:n.value]), list(w[:n.value])
+
+    def info(self) -> VolumeInfo:
+        inf = VolumeInfo()
+        _check(lib.dare_volume_get_info(self.handle, ct.byref(inf)), "dare_volume_get_info")
+        return inf
+
+    def codebook(self):
+        rn = (ct.c_double * (64 * 3))()
+        rx = (ct.c_double * (64 * 3))()
+        k = ct.c_int32()
+        _check(lib.dare_volume_get_codebook(self.handle, rn, rx, ct.byref(k)), "dare_volume_get_codebook")
+        K = k.value
+        return (np.array(rn[:K * 3]).reshape(K, 3), np.array(rx[:K * 3]).reshape(K, 3))
+
+    def _dense(self, dtype):
+        import torch
+        K = self.info().bins
+        nx, ny, nz = self.dims
+        shape = (K, nz, ny, nx)
+        return K, torch.zeros(shape, dtype=dtype, device=self.arena.device), \
+            torch.zeros(shape, dtype=dtype, device=self.arena.device)
+
+    def download_sums(self, stream=None):
+        import torch
+        K, S, C = self._dense(torch.int32)
+        if K:
+            _check(lib.dare_volume_download_sums(self.handle, _ptr(S), _ptr(C), K, _stream(stream)),
+                   "dare_volume_download_sums")
+        return S, C
+
+    def download_storage(self, stream=None):
+        import torch
+        K, A, C = self._dense(torch.float32)
+        if K:
+            _check(lib.dare_volume_download_storage(self.handle, _ptr(A), _ptr(C), K, _stream(stream)),
+                   "dare_volume_download_storage")
+        return A, C
+
+    def upload_sums(self, rep_n, rep_x, S, C, stream=None):
+        """S, C: int32/uint32 (K, nz, ny, nx) device tensors; rep_n, rep_x: (K, 3) arrays."""
+        K = int(S.shape[0])
+        rn = (ct.c_double * max(1, 3 * K))(*np.asarray(rep_n, np.float64).reshape(-1).tolist())
+        rx = (ct.c_double * max(1, 3 * K))(*np.asarray(rep_x, np.float64).reshape(-1).tolist())
+        return _check(lib.dare_volume_upload_sums(self.handle, rn, rx, K, _ptr(S.contiguous()),
+                                                  _ptr(C.contiguous()), _stream(stream)), "dare_volume_upload_sums")

@@ -1,0 +1,581 @@
+// C ABI: argument validation, arena layout, reconstruction orchestration,
+// reslice launches and the batched request planner.  Host code only; the
+// kernels live in dare_compound.hip and dare_reslice.hip.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "dare_internal.h"
+
+using namespace dare;
+
+struct dare_volume {
+    int device = 0;
+    dare_geometry g{};
+    dare_params p{};
+    dare_dtype dtype = DARE_F32;
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    VolDev host{};              // host mirror of the device header (pointers, geometry, codebook)
+    VolDev* dev = nullptr;      // device header at the start of the arena
+    VolState* st_pinned = nullptr;
+    int K = 0;
+    int saturated = 0;
+    uint32_t used = 0;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_all(const double* v, int n) {
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return false;
+    return true;
+}
+
+// Rigid 4x4 row-major transform: finite, |R^T R - I|_inf <= 1e-4, last row (0,0,0,1).
+bool rigid(const double* M) {
+    if (!finite_all(M, 16)) return false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double d = (M[a] * M[b] + M[4 + a] * M[4 + b]) + M[8 + a] * M[8 + b];
+            if (fabs(d - (a == b ? 1.0 : 0.0)) > 1e-4) return false;
+        }
+    return fabs(M[12]) <= 1e-4 && fabs(M[13]) <= 1e-4 && fabs(M[14]) <= 1e-4 && fabs(M[15] - 1.0) <= 1e-4;
+}
+
+bool valid_dtype(int d) { return d >= DARE_F32 && d <= DARE_FP8_E4M3; }
+
+dare_status check_params(const dare_params* p) {
+    if (!p) return DARE_ERR_INVALID_ARG;
+    if (!std::isfinite(p->k_normal) || !std::isfinite(p->k_inplane)) return DARE_ERR_INVALID_ARG;
+    if (!(p->thr_normal_deg >= 0.0 && p->thr_normal_deg <= 180.0)) return DARE_ERR_INVALID_ARG;
+    if (!(p->thr_inplane_deg >= 0.0 && p->thr_inplane_deg <= 180.0)) return DARE_ERR_INVALID_ARG;
+    if (!(p->bin_tol_deg >= 0.0 && p->bin_tol_deg <= 180.0)) return DARE_ERR_INVALID_ARG;
+    if (!(p->radius_vox >= 1.0 && p->radius_vox <= 8.0) || p->radius_vox != floor(p->radius_vox))
+        return DARE_ERR_INVALID_ARG;
+    if (p->max_bins < 1 || p->max_bins > kMaxBins) return DARE_ERR_INVALID_ARG;
+    if (p->normal_axis != 1 && p->normal_axis != 2) return DARE_ERR_INVALID_ARG;
+    return DARE_OK;
+}
+
+dare_status check_geometry(const dare_geometry* g) {
+    if (!g) return DARE_ERR_INVALID_ARG;
+    if (!finite_all(g->origin_mm, 3) || !(g->spacing_mm > 0.0) || !std::isfinite(g->spacing_mm))
+        return DARE_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (g->dims[a] <= 0 || g->dims[a] > (1 << 16)) return DARE_ERR_INVALID_ARG;
+    if (!rigid(g->calib)) return DARE_ERR_BAD_POSE;
+    return DARE_OK;
+}
+
+dare_status check_spec(const dare_slice_spec* s) {
+    if (!s) return DARE_ERR_INVALID_ARG;
+    if (s->width <= 0 || s->height <= 0 || (int64_t)s->width * s->height > (int64_t)1 << 30)
+        return DARE_ERR_INVALID_ARG;
+    if (!(s->pitch_mm[0] > 0.0) || !(s->pitch_mm[1] > 0.0) || !std::isfinite(s->pitch_mm[0]) ||
+        !std::isfinite(s->pitch_mm[1]))
+        return DARE_ERR_INVALID_ARG;
+    if (!rigid(s->probe_pose)) return DARE_ERR_BAD_POSE;
+    return DARE_OK;
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int64_t nbx, nby, nbz, nbricks;
+    uint64_t off_table, off_frames, off_fbin, off_new, off_dirty, off_flags, off_acc, off_data, off_scales, end;
+    uint64_t fixed;
+    uint64_t per_slot;
+};
+
+Layout layout(const dare_geometry* g, const dare_params* p, int dtype, uint64_t cap) {
+    Layout L{};
+    L.nbx = (g->dims[0] + kBrick - 1) / kBrick;
+    L.nby = (g->dims[1] + kBrick - 1) / kBrick;
+    L.nbz = (g->dims[2] + kBrick - 1) / kBrick;
+    L.nbricks = L.nbx * L.nby * L.nbz;
+    uint64_t off = align_up(sizeof(VolDev));
+    L.off_table = off;
+    off = align_up(off + (uint64_t)p->max_bins * L.nbricks * sizeof(int32_t));
+    L.off_frames = off;
+    off = align_up(off + (uint64_t)kFrameChunk * sizeof(FrameDesc));
+    L.off_fbin = off;
+    off = align_up(off + (uint64_t)kFrameChunk * sizeof(int32_t));
+    L.fixed = off + 6 * kAlign;
+    L.per_slot = 3 * sizeof(int32_t) + kBrickVox * sizeof(unsigned long long) + kBrickVox * pair_bytes(dtype) +
+                 sizeof(float2);
+    L.off_new = off;
+    off = align_up(off + cap * sizeof(int32_t));
+    L.off_dirty = off;
+    off = align_up(off + cap * sizeof(int32_t));
+    L.off_flags = off;
+    off = align_up(off + cap * sizeof(uint32_t));
+    L.off_acc = off;
+    off = align_up(off + cap * kBrickVox * sizeof(unsigned long long));
+    L.off_data = off;
+    off = align_up(off + cap * kBrickVox * (uint64_t)pair_bytes(dtype));
+    L.off_scales = off;
+    off = align_up(off + cap * sizeof(float2));
+    L.end = off;
+    return L;
+}
+
+dare_status hip_status(hipError_t e) { return e == hipSuccess ? DARE_OK : DARE_ERR_HIP; }
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return DARE_ERR_HIP;    \
+    } while (0)
+
+dare_status read_state(dare_volume* v, hipStream_t stream, VolState* out) {
+    HIP_TRY(hipMemcpyAsync(v->st_pinned, &v->dev->st, sizeof(VolState), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    *out = *v->st_pinned;
+    return DARE_OK;
+}
+
+void compose_host(const double* P, const double* C, double* T) {
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double acc = P[r * 4 + 0] * C[0 * 4 + c];
+            acc = acc + P[r * 4 + 1] * C[1 * 4 + c];
+            acc = acc + P[r * 4 + 2] * C[2 * 4 + c];
+            acc = acc + P[r * 4 + 3] * C[3 * 4 + c];
+            T[r * 4 + c] = acc;
+        }
+}
+
+SliceArgs make_args(const dare_slice_spec* s, float* out) {
+    SliceArgs a{};
+    memcpy(a.P, s->probe_pose, sizeof(a.P));
+    a.sx = s->pitch_mm[0];
+    a.sy = s->pitch_mm[1];
+    a.W = s->width;
+    a.H = s->height;
+    a.tiles_x = (s->width + kTile - 1) / kTile;
+    a.tiles = a.tiles_x * ((s->height + kTile - 1) / kTile);
+    a.out = out;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dare_default_params(dare_params* p) {
+    if (!p) return;
+    p->k_normal = 10.0;
+    p->k_inplane = 5.0;
+    p->thr_normal_deg = 25.0;
+    p->thr_inplane_deg = 15.0;
+    p->radius_vox = 1.0;
+    p->bin_tol_deg = 5.0;
+    p->max_bins = 64;
+    p->normal_axis = 2;
+}
+
+const char* dare_status_str(dare_status s) {
+    switch (s) {
+        case DARE_OK: return "ok";
+        case DARE_ERR_INVALID_ARG: return "invalid argument";
+        case DARE_ERR_BAD_POSE: return "pose is not a rigid transform";
+        case DARE_ERR_BUDGET: return "arena budget exhausted";
+        case DARE_ERR_HIP: return "HIP runtime error";
+        case DARE_WARN_BINS_SATURATED: return "direction codebook saturated";
+        case DARE_ERR_NOT_READY: return "not ready";
+        case DARE_ERR_QUEUE_FULL: return "queue full";
+    }
+    return "unknown status";
+}
+
+uint64_t dare_volume_arena_bytes(const dare_geometry* g, const dare_params* p, dare_dtype dtype, int64_t bricks) {
+    if (check_geometry(g) != DARE_OK || check_params(p) != DARE_OK || !valid_dtype(dtype) || bricks < 0) return 0;
+    return layout(g, p, dtype, (uint64_t)bricks).end;
+}
+
+dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dare_dtype dtype, void* arena_dev,
+                               uint64_t arena_bytes, dare_volume** out) {
+    if (!out || !arena_dev || !valid_dtype(dtype)) return DARE_ERR_INVALID_ARG;
+    *out = nullptr;
+    dare_status st = check_geometry(g);
+    if (st != DARE_OK) return st;
+    if ((st = check_params(p)) != DARE_OK) return st;
+    if (((uintptr_t)arena_dev % kAlign) != 0) return DARE_ERR_INVALID_ARG;
+    Layout L0 = layout(g, p, dtype, 0);
+    if (arena_bytes <= L0.fixed) return DARE_ERR_INVALID_ARG;
+    uint64_t cap = (arena_bytes - L0.off_new) / L0.per_slot;   // upper bound; alignment trims below
+    if (cap > 0x7FFFFFFFull) cap = 0x7FFFFFFFull;
+    while (cap > 0 && layout(g, p, dtype, cap).end > arena_bytes) --cap;
+    const Layout L = layout(g, p, dtype, cap);
+
+    dare_volume* v = new dare_volume();
+    if (hipGetDevice(&v->device) != hipSuccess) { delete v; return DARE_ERR_HIP; }
+    v->g = *g;
+    v->p = *p;
+    v->dtype = dtype;
+    v->arena = (char*)arena_dev;
+    v->arena_bytes = arena_bytes;
+    VolDev& h = v->host;
+    memset(&h, 0, sizeof(h));
+    for (int a = 0; a < 3; ++a) h.origin[a] = g->origin_mm[a];
+    h.h = g->spacing_mm;
+    h.inv_h = 1.0 / g->spacing_mm;
+    h.nx = g->dims[0];
+    h.ny = g->dims[1];
+    h.nz = g->dims[2];
+    h.nbx = (int32_t)L.nbx;
+    h.nby = (int32_t)L.nby;
+    h.nbz = (int32_t)L.nbz;
+    h.nbricks = L.nbricks;
+    memcpy(h.calib, g->calib, sizeof(h.calib));
+    h.k_normal = p->k_normal;
+    h.k_inplane = p->k_inplane;
+    h.cos_normal = cos(p->thr_normal_deg * (kPi / 180.0));
+    h.cos_inplane = cos(p->thr_inplane_deg * (kPi / 180.0));
+    h.cos_tol = cos(p->bin_tol_deg * (kPi / 180.0));
+    h.radius = (int32_t)p->radius_vox;
+    h.max_bins = p->max_bins;
+    h.normal_axis = p->normal_axis;
+    h.dtype = dtype;
+    h.cap = (uint32_t)cap;
+    char* base = v->arena;
+    h.table = (int32_t*)(base + L.off_table);
+    h.frames = (FrameDesc*)(base + L.off_frames);
+    h.frame_bin = (int32_t*)(base + L.off_fbin);
+    h.new_list = (int32_t*)(base + L.off_new);
+    h.dirty_list = (int32_t*)(base + L.off_dirty);
+    h.dirty_flags = (uint32_t*)(base + L.off_flags);
+    h.acc = (unsigned long long*)(base + L.off_acc);
+    h.data = (void*)(base + L.off_data);
+    h.scales = (float2*)(base + L.off_scales);
+    v->dev = (VolDev*)base;
+    if (hipHostMalloc((void**)&v->st_pinned, sizeof(VolState), hipHostMallocDefault) != hipSuccess) {
+        delete v;
+        return DARE_ERR_HIP;
+    }
+    hipError_t e = hipMemcpy(v->dev, &h, sizeof(VolDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_table_fill(h.table, (int64_t)p->max_bins * L.nbricks, nullptr);
+    if (e == hipSuccess && cap > 0) e = hipMemset(h.dirty_flags, 0, cap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipHostFree(v->st_pinned);
+        delete v;
+        return DARE_ERR_HIP;
+    }
+    *out = v;
+    return DARE_OK;
+}
+
+dare_status dare_volume_destroy(dare_volume* v) {
+    if (!v) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    hipError_t e = hipDeviceSynchronize();
+    (void)hipHostFree(v->st_pinned);
+    delete v;
+    return hip_status(e);
+}
+
+dare_status dare_reconstruct_frames(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
+                                    const double pitch_mm[2], const float* probe_poses_dev, void* stream_) {
+    if (!v || !pitch_mm || n < 0) return DARE_ERR_INVALID_ARG;
+    if (n == 0) return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
+    if (!frames_dev || !probe_poses_dev || w <= 0 || h <= 0 || (int64_t)w * h > (int64_t)1 << 30)
+        return DARE_ERR_INVALID_ARG;
+    if (!(pitch_mm[0] > 0.0) || !(pitch_mm[1] > 0.0) || !std::isfinite(pitch_mm[0]) || !std::isfinite(pitch_mm[1]))
+        return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    hipStream_t stream = (hipStream_t)stream_;
+    VolDev* vd = v->dev;
+    for (int32_t f0 = 0; f0 < n; f0 += kFrameChunk) {
+        const int nf = std::min<int32_t>(kFrameChunk, n - f0);
+        const int K0 = v->K, sat0 = v->saturated;
+        const uint32_t used = v->used;
+        HIP_TRY(launch_compose_frames(vd, probe_poses_dev + (size_t)f0 * 16, nf, stream));
+        HIP_TRY(launch_assign_bins(vd, nf, K0, stream));
+        HIP_TRY(launch_mark_pixels(vd, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
+        VolState st;
+        dare_status s = read_state(v, stream, &st);
+        if (s != DARE_OK) return s;
+        const bool bad = st.bad_pose != 0;
+        const bool over = (uint64_t)used + st.new_count > v->host.cap;
+        if (bad || over) {
+            HIP_TRY(launch_rollback(vd, st.new_count, st.dirty_count, K0, sat0, stream));
+            if (st.new_count > v->host.cap)   // marks beyond the list: clear them table-wide
+                HIP_TRY(launch_clear_marks(v->host.table, (int64_t)v->p.max_bins * v->host.nbricks, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            return bad ? DARE_ERR_BAD_POSE : DARE_ERR_BUDGET;
+        }
+        HIP_TRY(launch_alloc(vd, st.new_count, used, st.dirty_count, stream));
+        HIP_TRY(launch_accumulate(vd, frames_dev + (size_t)f0 * w * h, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
+        HIP_TRY(launch_finalize(vd, v->dtype, st.dirty_count + st.new_count, stream));
+        v->K = st.K;
+        v->saturated = st.saturated;
+        v->used = used + st.new_count;
+    }
+    return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
+}
+
+dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, float* out_dev, void* stream) {
+    if (!v || !out_dev) return DARE_ERR_INVALID_ARG;
+    const dare_status st = check_spec(spec);
+    if (st != DARE_OK) return st;
+    DeviceGuard dg(v->device);
+    const SliceArgs a = make_args(spec, out_dev);
+    return hip_status(launch_reslice(v->dev, v->dtype, (int)v->p.radius_vox, a, (hipStream_t)stream));
+}
+
+namespace {
+
+struct Group {
+    std::vector<BatchReq> reqs;
+    std::vector<int2> units;
+};
+
+uint64_t group_bytes(size_t nreq, size_t nunits) {
+    return align_up(sizeof(int)) + align_up(nreq * sizeof(BatchReq)) + align_up(nunits * sizeof(int2));
+}
+
+}  // namespace
+
+uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, const dare_slice_spec* specs, int32_t n) {
+    if (!vols || !specs || n <= 0) return 0;
+    std::map<std::pair<int, int>, std::pair<size_t, size_t>> cnt;
+    for (int k = 0; k < n; ++k) {
+        if (!vols[k]) return 0;
+        const int R = (int)vols[k]->p.radius_vox;
+        auto& c = cnt[{vols[k]->dtype, R}];
+        c.first += 1;
+        c.second += (size_t)reslice_units(R, specs[k].width, specs[k].height);
+    }
+    uint64_t total = 0;
+    for (auto& kv : cnt) total += group_bytes(kv.second.first, kv.second.second);
+    return total;
+}
+
+dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_spec* specs, float* const* outs_dev,
+                               int32_t n, void* workspace_dev, uint64_t workspace_bytes, void* stream_) {
+    if (!vols || !specs || !outs_dev || n < 0) return DARE_ERR_INVALID_ARG;
+    if (n == 0) return DARE_OK;
+    if (!workspace_dev) return DARE_ERR_INVALID_ARG;
+    int device = -1;
+    for (int k = 0; k < n; ++k) {
+        if (!vols[k] || !outs_dev[k]) return DARE_ERR_INVALID_ARG;
+        const dare_status st = check_spec(specs + k);
+        if (st != DARE_OK) return st;
+        if (device < 0) device = vols[k]->device;
+        if (vols[k]->device != device) return DARE_ERR_INVALID_ARG;
+    }
+    if (workspace_bytes < dare_reslice_batch_workspace_bytes(vols, specs, n)) return DARE_ERR_INVALID_ARG;
+    if (((uintptr_t)workspace_dev % kAlign) != 0) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(device);
+    hipStream_t stream = (hipStream_t)stream_;
+    std::map<std::pair<int, int>, Group> groups;
+    for (int k = 0; k < n; ++k) {
+        const int R = (int)vols[k]->p.radius_vox;
+        Group& g = groups[{vols[k]->dtype, R}];
+        const int r = (int)g.reqs.size();
+        BatchReq q;
+        q.vol = vols[k]->dev;
+        q.s = make_args(specs + k, outs_dev[k]);
+        g.reqs.push_back(q);
+        const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
+        for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
+    }
+    char* ws = (char*)workspace_dev;
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        const int nunits = (int)g.units.size();
+        const uint64_t o_req = align_up(sizeof(int));
+        const uint64_t o_units = o_req + align_up(g.reqs.size() * sizeof(BatchReq));
+        std::vector<char> host(group_bytes(g.reqs.size(), g.units.size()));
+        memcpy(host.data(), &nunits, sizeof(int));
+        memcpy(host.data() + o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
+        memcpy(host.data() + o_units, g.units.data(), g.units.size() * sizeof(int2));
+        HIP_TRY(hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_reslice_batch(kv.first.first, kv.first.second, (const BatchReq*)(ws + o_req),
+                                     (const int2*)(ws + o_units), (const int*)ws, nunits, stream));
+        ws += host.size();
+    }
+    return DARE_OK;
+}
+
+dare_status dare_bounds_from_frames(const float* poses, int32_t n, int32_t w, int32_t h, const double pitch_mm[2],
+                                    const double calib[16], double spacing_mm, dare_geometry* out) {
+    if (!poses || n <= 0 || w <= 0 || h <= 0 || !pitch_mm || !calib || !out || !(spacing_mm > 0.0))
+        return DARE_ERR_INVALID_ARG;
+    if (!rigid(calib)) return DARE_ERR_BAD_POSE;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int f = 0; f < n; ++f) {
+        double P[16], T[16];
+        for (int k = 0; k < 16; ++k) P[k] = (double)poses[(size_t)f * 16 + k];
+        if (!rigid(P)) return DARE_ERR_BAD_POSE;
+        compose_host(P, calib, T);
+        const int ci[4] = {0, w - 1, 0, w - 1}, cj[4] = {0, 0, h - 1, h - 1};
+        for (int k = 0; k < 4; ++k) {
+            const double is = (double)ci[k] * pitch_mm[0], js = (double)cj[k] * pitch_mm[1];
+            for (int a = 0; a < 3; ++a) {
+                const double p = (T[a * 4 + 3] + is * T[a * 4 + 0]) + js * T[a * 4 + 1];
+                lo[a] = std::min(lo[a], p);
+                hi[a] = std::max(hi[a], p);
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        out->origin_mm[a] = lo[a];
+        const double d = ceil((hi[a] - lo[a]) / spacing_mm) + 1.0;
+        if (!(d >= 1.0 && d <= (double)(1 << 16))) return DARE_ERR_INVALID_ARG;
+        out->dims[a] = (int32_t)d;
+    }
+    out->spacing_mm = spacing_mm;
+    memcpy(out->calib, calib, sizeof(out->calib));
+    return DARE_OK;
+}
+
+dare_status dare_volume_get_info(const dare_volume* v, dare_volume_info* out) {
+    if (!v || !out) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    HIP_TRY(hipDeviceSynchronize());
+    out->bins = v->K;
+    out->saturated = v->saturated;
+    out->bricks_used = v->used;
+    out->bricks_capacity = v->host.cap;
+    const Layout L = layout(&v->g, &v->p, v->dtype, 0);
+    out->bytes_per_brick = (int64_t)L.per_slot;
+    out->brick_grid[0] = L.nbx;
+    out->brick_grid[1] = L.nby;
+    out->brick_grid[2] = L.nbz;
+    return DARE_OK;
+}
+
+dare_status dare_volume_get_codebook(const dare_volume* v, double* rep_n, double* rep_x, int32_t* bins) {
+    if (!v || !rep_n || !rep_x || !bins) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    HIP_TRY(hipDeviceSynchronize());
+    VolDev tmp;
+    HIP_TRY(hipMemcpy(&tmp, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost));
+    *bins = tmp.st.K;
+    for (int b = 0; b < tmp.st.K; ++b)
+        for (int a = 0; a < 3; ++a) {
+            rep_n[b * 3 + a] = tmp.rep_n[b][a];
+            rep_x[b * 3 + a] = tmp.rep_x[b][a];
+        }
+    return DARE_OK;
+}
+
+dare_status dare_volume_download_sums(const dare_volume* v, uint32_t* S, uint32_t* C, int32_t bins, void* stream) {
+    if (!v || !S || !C || bins != v->K) return DARE_ERR_INVALID_ARG;
+    if (bins == 0) return DARE_OK;
+    DeviceGuard dg(v->device);
+    return hip_status(launch_download_sums(v->dev, S, C, bins, v->g.dims[0], v->g.dims[1], v->g.dims[2],
+                                           (hipStream_t)stream));
+}
+
+dare_status dare_volume_download_storage(const dare_volume* v, float* A, float* C, int32_t bins, void* stream) {
+    if (!v || !A || !C || bins != v->K) return DARE_ERR_INVALID_ARG;
+    if (bins == 0) return DARE_OK;
+    DeviceGuard dg(v->device);
+    return hip_status(launch_download_storage(v->dev, v->dtype, A, C, bins, v->g.dims[0], v->g.dims[1],
+                                              v->g.dims[2], (hipStream_t)stream));
+}
+
+dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n, const double* rep_x, int32_t bins,
+                                    const uint32_t* S, const uint32_t* C, void* stream_) {
+    if (!v || bins < 0 || bins > v->p.max_bins) return DARE_ERR_INVALID_ARG;
+    if (bins > 0 && (!rep_n || !rep_x || !S || !C)) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    hipStream_t stream = (hipStream_t)stream_;
+    VolDev h = v->host;
+    memset(&h.st, 0, sizeof(h.st));
+    h.st.K = bins;
+    for (int b = 0; b < bins; ++b)
+        for (int a = 0; a < 3; ++a) {
+            h.rep_n[b][a] = rep_n[b * 3 + a];
+            h.rep_x[b][a] = rep_x[b * 3 + a];
+        }
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(v->dev, &h, sizeof(VolDev), hipMemcpyHostToDevice));
+    HIP_TRY(launch_table_fill(h.table, (int64_t)v->p.max_bins * h.nbricks, stream));
+    if (h.cap) HIP_TRY(hipMemsetAsync(h.dirty_flags, 0, (size_t)h.cap * sizeof(uint32_t), stream));
+    v->host.st = h.st;
+    memcpy(v->host.rep_n, h.rep_n, sizeof(h.rep_n));
+    memcpy(v->host.rep_x, h.rep_x, sizeof(h.rep_x));
+    v->K = bins;
+    v->saturated = 0;
+    v->used = 0;
+    if (bins == 0) return hip_status(hipStreamSynchronize(stream));
+    HIP_TRY(launch_dense_mark(v->dev, C, bins, stream));
+    VolState st;
+    dare_status s = read_state(v, stream, &st);
+    if (s != DARE_OK) return s;
+    if (st.new_count > h.cap) {
+        HIP_TRY(launch_rollback(v->dev, st.new_count, 0, 0, 0, stream));
+        HIP_TRY(launch_clear_marks(h.table, (int64_t)v->p.max_bins * h.nbricks, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        v->K = 0;
+        return DARE_ERR_BUDGET;
+    }
+    HIP_TRY(launch_alloc(v->dev, st.new_count, 0, 0, stream));
+    HIP_TRY(launch_dense_scatter(v->dev, S, C, bins, stream));
+    HIP_TRY(launch_finalize(v->dev, v->dtype, st.new_count, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    v->used = st.new_count;
+    return DARE_OK;
+}
+
+dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* spec, int32_t* bins_out,
+                                   double* weights_out, int32_t* count) {
+    if (!v || !count) return DARE_ERR_INVALID_ARG;
+    const dare_status st = check_spec(spec);
+    if (st != DARE_OK) return st;
+    DeviceGuard dg(v->device);
+    HIP_TRY(hipDeviceSynchronize());
+    VolDev tmp;
+    HIP_TRY(hipMemcpy(&tmp, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost));
+    double T[16];
+    compose_host(spec->probe_pose, v->g.calib, T);
+    const int ax = v->p.normal_axis;
+    const double e0[3] = {T[0], T[4], T[8]}, en[3] = {T[ax], T[4 + ax], T[8 + ax]};
+    const double l0 = sqrt((e0[0] * e0[0] + e0[1] * e0[1]) + e0[2] * e0[2]);
+    const double ln = sqrt((en[0] * en[0] + en[1] * en[1]) + en[2] * en[2]);
+    const double xr[3] = {e0[0] / l0, e0[1] / l0, e0[2] / l0}, nr[3] = {en[0] / ln, en[1] / ln, en[2] / ln};
+    int n = 0;
+    for (int b = 0; b < tmp.st.K; ++b) {
+        const double* rn = tmp.rep_n[b];
+        const double* rx = tmp.rep_x[b];
+        const double dn = (rn[0] * nr[0] + rn[1] * nr[1]) + rn[2] * nr[2];
+        const double di = fabs((rx[0] * xr[0] + rx[1] * xr[1]) + rx[2] * xr[2]);
+        if (dn >= tmp.cos_normal && di >= tmp.cos_inplane) {
+            if (bins_out) bins_out[n] = b;
+            if (weights_out) weights_out[n] = exp(tmp.k_normal * (dn - 1.0) + tmp.k_inplane * (di - 1.0));
+            ++n;
+        }
+    }
+    *count = n;
+    return DARE_OK;
+}
+
+dare_status dare_copy_probe(const void* src, void* dst, uint64_t n, void* stream) {
+    if (!src || !dst || n == 0 || (n % 16) != 0) return DARE_ERR_INVALID_ARG;
+    return hip_status(launch_copy_probe(src, dst, n, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,530 @@
+// Volume reconstruction kernels (Sec. 2.1 "Volume reconstruction", Fig. 1):
+// frame pose composition, direction-bin assignment, brick occupancy and
+// allocation, nearest-voxel accumulation and finalisation into the stored
+// precision.  Positions are FP64 with no contraction so that every
+// nearest-voxel decision is reproducible; sums and counts are exact integers
+// accumulated with 64-bit atomics, so the result is independent of order.
+#include <math.h>
+
+#include "dare_codec.h"
+#include "dare_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace dare {
+
+namespace {
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+__device__ __forceinline__ double norm3(const double* v) { return sqrt(dot3(v, v)); }
+
+// Nearest voxel of frame pixel (i, j); false when outside the grid.
+__device__ __forceinline__ bool pixel_voxel(const VolDev* __restrict__ vd, const FrameDesc* __restrict__ fd,
+                                            int i, int j, double sx, double sy, int& vx, int& vy, int& vz) {
+    const double is = (double)i * sx;
+    const double js = (double)j * sy;
+    double c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double p = (fd->t[a] + is * fd->e0[a]) + js * fd->e1[a];
+        c[a] = floor((p - vd->origin[a]) * vd->inv_h + 0.5);
+    }
+    if (!(c[0] >= 0.0 && c[0] < (double)vd->nx && c[1] >= 0.0 && c[1] < (double)vd->ny && c[2] >= 0.0 &&
+          c[2] < (double)vd->nz))
+        return false;
+    vx = (int)c[0];
+    vy = (int)c[1];
+    vz = (int)c[2];
+    return true;
+}
+
+__device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, int vy, int vz) {
+    return (int64_t)b * vd->nbricks + ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
+}
+
+__device__ __forceinline__ int brick_local(int vx, int vy, int vz) {
+    return (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+}
+
+}  // namespace
+
+// K1: T = P . C per frame (row-major, summed left to right), rigidity check of P.
+__global__ void k_compose_frames(VolDev* vd, const float* __restrict__ poses, int n) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    double P[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) P[k] = (double)poses[(size_t)f * 16 + k];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ok = ok && isfinite(P[k]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double d = (P[a] * P[b] + P[4 + a] * P[4 + b]) + P[8 + a] * P[8 + b];
+            ok = ok && fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-4;
+        }
+    ok = ok && fabs(P[12]) <= 1e-4 && fabs(P[13]) <= 1e-4 && fabs(P[14]) <= 1e-4 && fabs(P[15] - 1.0) <= 1e-4;
+    if (!ok) atomicOr(&vd->st.bad_pose, 1);
+    const double* C = vd->calib;
+    double T[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double acc = P[r * 4 + 0] * C[0 * 4 + c];
+            acc = acc + P[r * 4 + 1] * C[1 * 4 + c];
+            acc = acc + P[r * 4 + 2] * C[2 * 4 + c];
+            acc = acc + P[r * 4 + 3] * C[3 * 4 + c];
+            T[r * 4 + c] = acc;
+        }
+    FrameDesc d;
+    double e2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d.t[a] = T[a * 4 + 3];
+        d.e0[a] = T[a * 4 + 0];
+        d.e1[a] = T[a * 4 + 1];
+        e2[a] = T[a * 4 + 2];
+    }
+    const double l0 = norm3(d.e0);
+    const double* en = vd->normal_axis == 1 ? d.e1 : e2;
+    const double ln = norm3(en);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d.xh[a] = d.e0[a] / l0;
+        d.nh[a] = en[a] / ln;
+    }
+    d.pad = 0.0;
+    vd->frames[f] = d;
+}
+
+// K2: leader clustering of frame orientations, frames in order; one wave,
+// lane b holds representative b in registers.
+__global__ void __launch_bounds__(64) k_assign_bins(VolDev* vd, int n, int K0) {
+    const int lane = threadIdx.x;
+    double rn[3] = {0, 0, 0}, rx[3] = {0, 0, 0};
+    if (lane < K0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            rn[a] = vd->rep_n[lane][a];
+            rx[a] = vd->rep_x[lane][a];
+        }
+    }
+    int K = K0;
+    int sat = vd->st.saturated;
+    const double ct = vd->cos_tol;
+    const int kmax = vd->max_bins;
+    for (int f = 0; f < n; ++f) {
+        const FrameDesc* fd = vd->frames + f;
+        double nf[3], xf[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            nf[a] = fd->nh[a];
+            xf[a] = fd->xh[a];
+        }
+        double s = -INFINITY, key = -INFINITY;
+        if (lane < K) {
+            const double dn = dot3(nf, rn);
+            const double di = fabs(dot3(xf, rx));
+            s = dn + di;
+            if (dn >= ct && di >= ct) key = s;
+        }
+        // argmax over qualifying bins and over all bins; ties go to the lowest index
+        double bk = key, ak = s;
+        int bi = lane, ai = lane;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ok = __shfl_xor(bk, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ok > bk || (ok == bk && oi < bi)) { bk = ok; bi = oi; }
+            const double ok2 = __shfl_xor(ak, off);
+            const int oi2 = __shfl_xor(ai, off);
+            if (ok2 > ak || (ok2 == ak && oi2 < ai)) { ak = ok2; ai = oi2; }
+        }
+        int b;
+        if (bk > -INFINITY) {
+            b = bi;
+        } else if (K < kmax) {
+            b = K;
+            if (lane == K) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { rn[a] = nf[a]; rx[a] = xf[a]; }
+            }
+            ++K;
+        } else {
+            b = ai;
+            sat = 1;
+        }
+        if (lane == 0) vd->frame_bin[f] = b;
+    }
+    if (lane < K) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            vd->rep_n[lane][a] = rn[a];
+            vd->rep_x[lane][a] = rx[a];
+        }
+    }
+    if (lane == 0) {
+        vd->st.K = K;
+        vd->st.saturated = sat;
+    }
+}
+
+__device__ __forceinline__ void mark_entry(VolDev* vd, int64_t e) {
+    int32_t* te = vd->table + e;
+    const int cur = __atomic_load_n(te, __ATOMIC_RELAXED);
+    if (cur == -1) {
+        if (atomicCAS(te, -1, -2) == -1) {
+            const uint32_t k = atomicAdd(&vd->st.new_count, 1u);
+            if (k < vd->cap) vd->new_list[k] = (int32_t)e;
+        }
+    } else if (cur >= 0) {
+        if (__atomic_load_n(vd->dirty_flags + cur, __ATOMIC_RELAXED) == 0u &&
+            atomicExch(vd->dirty_flags + cur, 1u) == 0u) {
+            const uint32_t d = atomicAdd(&vd->st.dirty_count, 1u);
+            vd->dirty_list[d] = cur;
+        }
+    }
+}
+
+// K3a: mark every (bin, brick) that a pixel of the batch lands in.
+__global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, double sx, double sy) {
+    const int f = blockIdx.y;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= w * h) return;
+    int vx, vy, vz;
+    if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
+    mark_entry(vd, brick_entry(vd, vd->frame_bin[f], vx, vy, vz));
+}
+
+// Undo the marks of a rejected batch and restore the codebook size.
+__global__ void k_rollback(VolDev* vd, uint32_t new_count, uint32_t dirty_count, int K0, int sat0) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < new_count && k < vd->cap) vd->table[vd->new_list[k]] = -1;
+    if (k < dirty_count) vd->dirty_flags[vd->dirty_list[k]] = 0u;
+    if (k == 0) {
+        vd->st.new_count = 0u;
+        vd->st.dirty_count = 0u;
+        vd->st.K = K0;
+        vd->st.saturated = sat0;
+        vd->st.bad_pose = 0;
+    }
+}
+
+// K3b: give each marked entry the next pool slot, zero its accumulators and
+// queue it for finalisation.
+__global__ void __launch_bounds__(256) k_alloc(VolDev* vd, uint32_t new_count, uint32_t used,
+                                               uint32_t dirty_count) {
+    const uint32_t k = blockIdx.x;
+    const uint32_t slot = used + k;
+    unsigned long long* acc = vd->acc + (size_t)slot * kBrickVox;
+    acc[threadIdx.x] = 0ull;
+    acc[threadIdx.x + 256] = 0ull;
+    if (threadIdx.x == 0) {
+        vd->table[vd->new_list[k]] = (int32_t)slot;
+        vd->dirty_flags[slot] = 1u;
+        vd->dirty_list[dirty_count + k] = (int32_t)slot;
+        if (k == 0) {
+            vd->st.used = used + new_count;
+            vd->st.dirty_count = dirty_count + new_count;
+            vd->st.new_count = 0u;
+        }
+    }
+}
+
+// K4: add each pixel's intensity and a count to its (bin, voxel).
+__global__ void __launch_bounds__(256) k_accumulate(const VolDev* __restrict__ vd, const uint8_t* __restrict__ frames,
+                                                    int w, int h, double sx, double sy) {
+    const int f = blockIdx.y;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= w * h) return;
+    int vx, vy, vz;
+    if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
+    const int slot = vd->table[brick_entry(vd, vd->frame_bin[f], vx, vy, vz)];
+    if (slot < 0) return;   // unreachable: every entry hit here was marked and allocated
+    const unsigned long long inten = frames[(size_t)f * w * h + pix];
+    atomicAdd(vd->acc + (size_t)slot * kBrickVox + brick_local(vx, vy, vz), (inten << 32) | 1ull);
+}
+
+// K5: exact sums -> stored (value, count) pairs of every dirty slot.
+template <int DT>
+__global__ void __launch_bounds__(256) k_finalize(VolDev* vd) {
+    __shared__ float red[2][4];
+    const int slot = vd->dirty_list[blockIdx.x];
+    const unsigned long long* acc = vd->acc + (size_t)slot * kBrickVox;
+    float a[2], c[2];
+    uint32_t C[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const unsigned long long u = acc[threadIdx.x + 256 * k];
+        C[k] = (uint32_t)(u & 0xFFFFFFFFull);
+        const uint32_t S = (uint32_t)(u >> 32);
+        c[k] = (float)C[k];
+        a[k] = C[k] ? (float)S / c[k] : 0.0f;
+    }
+    const size_t base = (size_t)slot * kBrickVox;
+    const float inv = 1.0f / 127.5f;
+    if constexpr (DT == DARE_F32) {
+        float2* d = (float2*)vd->data + base;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) d[threadIdx.x + 256 * k] = make_float2(a[k], c[k]);
+    } else if constexpr (DT == DARE_BF16 || DT == DARE_F16) {
+        uint32_t* d = (uint32_t*)vd->data + base;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint32_t q = 0u, qc = 0u;
+            if (C[k]) {
+                const float x = (a[k] - 127.5f) * inv;
+                if constexpr (DT == DARE_BF16) {
+                    q = f32_to_bf16_rne(x);
+                    qc = f32_to_bf16_rne(c[k]);
+                } else {
+                    q = f32_to_f16_rne(x);
+                    qc = f32_to_f16_rne(fminf(c[k], 65504.0f));
+                }
+            }
+            d[threadIdx.x + 256 * k] = q | (qc << 16);
+        }
+    } else {
+        // per-brick scales: largest |a - 127.5| and largest count over occupied voxels
+        float m = 0.0f, cm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (C[k]) {
+                m = fmaxf(m, fabsf(a[k] - 127.5f));
+                cm = fmaxf(cm, c[k]);
+            }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            m = fmaxf(m, __shfl_xor(m, off));
+            cm = fmaxf(cm, __shfl_xor(cm, off));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = m;
+            red[1][threadIdx.x >> 6] = cm;
+        }
+        __syncthreads();
+        m = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+        cm = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+        const float s = fmaxf(m / 448.0f, 9.5367431640625e-07f);   // floor 2^-20
+        const float t = cm > 0.0f ? cm / 448.0f : 1.0f;
+        uint16_t* d = (uint16_t*)vd->data + base;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint32_t q = 0u, qc = 0u;
+            if (C[k]) {
+                q = f32_to_e4m3_rne((a[k] - 127.5f) / s);
+                qc = f32_to_e4m3_rne(c[k] / t);
+            }
+            d[threadIdx.x + 256 * k] = (uint16_t)(q | (qc << 8));
+        }
+        if (threadIdx.x == 0) vd->scales[slot] = make_float2(s, t);
+    }
+    if (threadIdx.x == 0) {
+        vd->dirty_flags[slot] = 0u;
+        if (blockIdx.x == 0) vd->st.dirty_count = 0u;
+    }
+}
+
+// Marks (-2) of a rejected batch that did not fit the new-entry list.
+__global__ void k_clear_marks(int32_t* t, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        if (t[k] == -2) t[k] = -1;
+}
+
+__global__ void k_table_fill(int32_t* t, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        t[k] = -1;
+}
+
+// Test hooks: dense (bin, z, y, x) arrays <-> the bricked pool.
+__global__ void k_dense_mark(VolDev* vd, const uint32_t* __restrict__ C, int K) {
+    const int64_t nvox = (int64_t)vd->nx * vd->ny * vd->nz;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nvox * K;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (C[k] == 0u) continue;
+        const int b = (int)(k / nvox);
+        int64_t r = k - b * nvox;
+        const int vx = (int)(r % vd->nx);
+        r /= vd->nx;
+        const int vy = (int)(r % vd->ny);
+        const int vz = (int)(r / vd->ny);
+        mark_entry(vd, brick_entry(vd, b, vx, vy, vz));
+    }
+}
+
+__global__ void k_dense_scatter(const VolDev* vd, const uint32_t* __restrict__ S, const uint32_t* __restrict__ C,
+                                int K) {
+    const int64_t nvox = (int64_t)vd->nx * vd->ny * vd->nz;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nvox * K;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (C[k] == 0u) continue;
+        const int b = (int)(k / nvox);
+        int64_t r = k - b * nvox;
+        const int vx = (int)(r % vd->nx);
+        r /= vd->nx;
+        const int vy = (int)(r % vd->ny);
+        const int vz = (int)(r / vd->ny);
+        const int slot = vd->table[brick_entry(vd, b, vx, vy, vz)];
+        vd->acc[(size_t)slot * kBrickVox + brick_local(vx, vy, vz)] =
+            ((unsigned long long)S[k] << 32) | (unsigned long long)C[k];
+    }
+}
+
+__global__ void k_download_sums(const VolDev* vd, uint32_t* __restrict__ S, uint32_t* __restrict__ C, int K) {
+    const int64_t nvox = (int64_t)vd->nx * vd->ny * vd->nz;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nvox * K;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(k / nvox);
+        int64_t r = k - b * nvox;
+        const int vx = (int)(r % vd->nx);
+        r /= vd->nx;
+        const int vy = (int)(r % vd->ny);
+        const int vz = (int)(r / vd->ny);
+        const int slot = vd->table[brick_entry(vd, b, vx, vy, vz)];
+        unsigned long long u = 0ull;
+        if (slot >= 0) u = vd->acc[(size_t)slot * kBrickVox + brick_local(vx, vy, vz)];
+        S[k] = (uint32_t)(u >> 32);
+        C[k] = (uint32_t)(u & 0xFFFFFFFFull);
+    }
+}
+
+template <int DT>
+__global__ void k_download_storage(const VolDev* vd, float* __restrict__ A, float* __restrict__ Cout, int K) {
+    using P = Pair<DT>;
+    const int64_t nvox = (int64_t)vd->nx * vd->ny * vd->nz;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nvox * K;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(k / nvox);
+        int64_t r = k - b * nvox;
+        const int vx = (int)(r % vd->nx);
+        r /= vd->nx;
+        const int vy = (int)(r % vd->ny);
+        const int vz = (int)(r / vd->ny);
+        const int slot = vd->table[brick_entry(vd, b, vx, vy, vz)];
+        float a = 0.0f, c = 0.0f;
+        if (slot >= 0) {
+            const typename P::T p = ((const typename P::T*)vd->data)[(size_t)slot * kBrickVox + brick_local(vx, vy, vz)];
+            const float2 s = DT == DARE_FP8_E4M3 ? vd->scales[slot] : make_float2(0.0f, 0.0f);
+            P::decode(p, s, a, c);
+            if (!(c > 0.0f)) { a = 0.0f; c = 0.0f; }
+        }
+        A[k] = a;
+        Cout[k] = c;
+    }
+}
+
+__global__ void k_copy_probe(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n) {
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+static inline int grid_for(int64_t n, int block, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+hipError_t launch_compose_frames(const VolDev* vd, const float* poses, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_compose_frames, dim3((n + 63) / 64), dim3(64), 0, stream, const_cast<VolDev*>(vd), poses, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_bins(VolDev* vd, int n, int K0, hipStream_t stream) {
+    hipLaunchKernelGGL(k_assign_bins, dim3(1), dim3(64), 0, stream, vd, n, K0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_pixels(const VolDev* vd, int n, int w, int h, double sx, double sy, hipStream_t stream) {
+    hipLaunchKernelGGL(k_mark_pixels, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, const_cast<VolDev*>(vd),
+                       w, h, sx, sy);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollback(VolDev* vd, uint32_t new_count, uint32_t dirty_count, int K0, int sat0,
+                           hipStream_t stream) {
+    const uint32_t m = new_count > dirty_count ? new_count : dirty_count;
+    hipLaunchKernelGGL(k_rollback, dim3(grid_for(m ? m : 1, 256)), dim3(256), 0, stream, vd, new_count,
+                       dirty_count, K0, sat0);
+    return hipGetLastError();
+}
+
+hipError_t launch_alloc(VolDev* vd, uint32_t new_count, uint32_t used, uint32_t dirty_count, hipStream_t stream) {
+    if (new_count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alloc, dim3(new_count), dim3(256), 0, stream, vd, new_count, used, dirty_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const VolDev* vd, const uint8_t* frames, int n, int w, int h, double sx, double sy,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(k_accumulate, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, vd, frames, w, h, sx, sy);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(VolDev* vd, int dtype, uint32_t dirty_count, hipStream_t stream) {
+    if (dirty_count == 0) return hipSuccess;
+    switch (dtype) {
+        case DARE_F32: hipLaunchKernelGGL(k_finalize<DARE_F32>, dim3(dirty_count), dim3(256), 0, stream, vd); break;
+        case DARE_BF16: hipLaunchKernelGGL(k_finalize<DARE_BF16>, dim3(dirty_count), dim3(256), 0, stream, vd); break;
+        case DARE_F16: hipLaunchKernelGGL(k_finalize<DARE_F16>, dim3(dirty_count), dim3(256), 0, stream, vd); break;
+        case DARE_FP8_E4M3:
+            hipLaunchKernelGGL(k_finalize<DARE_FP8_E4M3>, dim3(dirty_count), dim3(256), 0, stream, vd);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_marks(int32_t* table, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(n, 256, 4096)), dim3(256), 0, stream, table, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_fill(int32_t* table, int64_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_table_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, stream, table, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_mark(const VolDev* vd, const uint32_t* C, int K, hipStream_t stream) {
+    hipLaunchKernelGGL(k_dense_mark, dim3(4096), dim3(256), 0, stream, const_cast<VolDev*>(vd), C, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_scatter(const VolDev* vd, const uint32_t* S, const uint32_t* C, int K, hipStream_t stream) {
+    hipLaunchKernelGGL(k_dense_scatter, dim3(4096), dim3(256), 0, stream, vd, S, C, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_download_sums(const VolDev* vd, uint32_t* S, uint32_t* C, int K, int, int, int,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(k_download_sums, dim3(4096), dim3(256), 0, stream, vd, S, C, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float* C, int K, int, int, int,
+                                   hipStream_t stream) {
+    switch (dtype) {
+        case DARE_F32: hipLaunchKernelGGL(k_download_storage<DARE_F32>, dim3(4096), dim3(256), 0, stream, vd, A, C, K); break;
+        case DARE_BF16: hipLaunchKernelGGL(k_download_storage<DARE_BF16>, dim3(4096), dim3(256), 0, stream, vd, A, C, K); break;
+        case DARE_F16: hipLaunchKernelGGL(k_download_storage<DARE_F16>, dim3(4096), dim3(256), 0, stream, vd, A, C, K); break;
+        case DARE_FP8_E4M3:
+            hipLaunchKernelGGL(k_download_storage<DARE_FP8_E4M3>, dim3(4096), dim3(256), 0, stream, vd, A, C, K);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream) {
+    const uint64_t n16 = n / 16;
+    hipLaunchKernelGGL(k_copy_probe, dim3(grid_for((int64_t)n16, 256, 256 * 64)), dim3(256), 0, stream,
+                       (const uint4*)src, (uint4*)dst, n16);
+    return hipGetLastError();
+}
+
+}  // namespace dare

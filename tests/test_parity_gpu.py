@@ -1,0 +1,335 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: compounding sums/counts, codebooks and stored pairs are bit-exact;
+reslices match within |d| <= 1e-5 max(|ref|, 1) with identical NaN masks;
+a request inside a batch equals the same request alone, bit for bit.
+"""
+from __future__ import annotations
+
+import math
+import warnings
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import assert_parity, make_volume, note, oracle_grid, upload_grid
+from helpers import random_grid, rodrigues, random_unit
+from oracle import compound, quant, reslice
+from oracle.reslice import Params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dare():
+    import paper_2605_26325_amd as d
+    return d
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    wl = synth.config1()
+    wl.render("cpu")
+    return wl
+
+
+@pytest.fixture(scope="module")
+def cfg1_grid(cfg1):
+    return oracle_grid(cfg1, cfg1.frames.numpy(), Params())
+
+
+def _sums(vol):
+    S, C = vol.download_sums()
+    import torch
+    torch.cuda.synchronize()
+    return S.cpu().numpy().view(np.uint32).astype(np.int64), C.cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+def _poses_dev(torch, P):
+    return torch.from_numpy(np.ascontiguousarray(P, dtype=np.float32)).cuda()
+
+
+# ----------------------------------------------------------------------------- compounding
+
+@pytest.mark.parametrize("seed,tol", [(1, 5.0), (2, 5.0), (3, 0.0), (4, 12.0)])
+def test_compound_bit_exact_tiny(dare, torch_cuda, seed, tol):
+    torch = torch_cuda
+    note(f"compound tiny seed={seed} tol={tol}")
+    wl = synth.tiny_workload(seed, N=12, n_frames=10, w=16)
+    frames = wl.render("cpu")
+    prm = Params(bin_tol_deg=tol)
+    g = oracle_grid(wl, frames.numpy(), prm)
+    vol = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, prm)
+    vol.reconstruct(frames.cuda(), _poses_dev(torch, wl.sweep.probe_poses), wl.sweep.pitch)
+    S, C = _sums(vol)
+    assert vol.info().bins == g.K
+    np.testing.assert_array_equal(C, g.C)
+    np.testing.assert_array_equal(S, g.S)
+    rn, rx = vol.codebook()
+    orn, orx = g.codebook.arrays()
+    np.testing.assert_array_equal(rn, orn)
+    np.testing.assert_array_equal(rx, orx)
+
+
+def test_compound_bit_exact_config1(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("compound config1 200 frames 128^2 -> 64^3")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    st = vol.reconstruct(cfg1.frames.cuda(), _poses_dev(torch, cfg1.sweep.probe_poses), cfg1.sweep.pitch)
+    assert st == dare.OK
+    S, C = _sums(vol)
+    np.testing.assert_array_equal(C, cfg1_grid.C)
+    np.testing.assert_array_equal(S, cfg1_grid.S)
+    # conservation: every in-grid pixel is counted once
+    assert C.sum() == cfg1_grid.C.sum() and S.sum() == cfg1_grid.S.sum()
+
+
+def test_compound_incremental_equals_single_call(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("compound config1 incremental in 3 calls")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    fr = cfg1.frames.cuda()
+    P = _poses_dev(torch, cfg1.sweep.probe_poses)
+    for a, b in ((0, 37), (37, 150), (150, 200)):
+        vol.reconstruct(fr[a:b], P[a:b], cfg1.sweep.pitch)
+    S, C = _sums(vol)
+    np.testing.assert_array_equal(C, cfg1_grid.C)
+    np.testing.assert_array_equal(S, cfg1_grid.S)
+
+
+def test_compound_saturated_codebook(dare, torch_cuda, cfg1):
+    torch = torch_cuda
+    note("compound config1 with max_bins=1 (saturation)")
+    prm = Params(max_bins=1)
+    g = oracle_grid(cfg1, cfg1.frames.numpy(), prm)
+    assert g.codebook.saturated
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, prm)
+    with warnings.catch_warnings(record=True) as wrn:
+        warnings.simplefilter("always")
+        st = vol.reconstruct(cfg1.frames.cuda(), _poses_dev(torch, cfg1.sweep.probe_poses), cfg1.sweep.pitch)
+    assert st == dare.WARN_BINS_SATURATED and any("saturated" in str(w.message) for w in wrn)
+    S, C = _sums(vol)
+    np.testing.assert_array_equal(C, g.C)
+    np.testing.assert_array_equal(S, g.S)
+
+
+def test_budget_exhaustion_rolls_back(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("budget exhaustion on a 300-brick arena")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(), bricks=300)
+    fr = cfg1.frames.cuda()
+    P = _poses_dev(torch, cfg1.sweep.probe_poses)
+    with pytest.raises(dare.DareError) as e:
+        vol.reconstruct(fr, P, cfg1.sweep.pitch)
+    assert e.value.status == dare.ERR_BUDGET
+    inf = vol.info()
+    assert inf.bins == 0 and inf.bricks_used == 0
+    # a batch that fits still goes in afterwards: one frame
+    vol.reconstruct(fr[:1], P[:1], cfg1.sweep.pitch)
+    S, C = _sums(vol)
+    g1 = compound.empty_grid(cfg1.origin, cfg1.spacing, cfg1.dims, 5.0, 64)
+    compound.compound(g1, cfg1.frames.numpy()[:1], cfg1.sweep.probe_poses[:1], cfg1.calib, cfg1.sweep.pitch)
+    np.testing.assert_array_equal(C, g1.C)
+    np.testing.assert_array_equal(S, g1.S)
+
+
+def test_bad_pose_rejected(dare, torch_cuda, cfg1):
+    torch = torch_cuda
+    note("non-rigid frame pose")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    P = np.array(cfg1.sweep.probe_poses[:4])
+    P[2, :3, :3] *= 1.01
+    with pytest.raises(dare.DareError) as e:
+        vol.reconstruct(cfg1.frames[:4].cuda(), _poses_dev(torch, P), cfg1.sweep.pitch)
+    assert e.value.status == dare.ERR_BAD_POSE
+    assert vol.info().bricks_used == 0 and vol.info().bins == 0
+    with pytest.raises(dare.DareError) as e:
+        vol.reslice(np.eye(4) * 2.0, 8, 8, (1.0, 1.0))
+    assert e.value.status == dare.ERR_BAD_POSE
+
+
+# ----------------------------------------------------------------------------- reslice, FP32
+
+def test_reslice_fp32_uploaded_config1(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("reslice fp32 config1 16 slices on the uploaded oracle grid")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    upload_grid(vol, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+    prm = Params()
+    checked = 0
+    sl = cfg1.slices
+    for k, P in enumerate(sl.probe_poses):
+        out = vol.reslice(P, sl.width, sl.height, sl.pitch)
+        ref = reslice.reslice_grid(cfg1_grid, cfg1.calib, P, sl.width, sl.height, sl.pitch, prm, form="fp32")
+        checked += assert_parity(out.cpu().numpy(), ref, what=f"slice {k}")
+    assert checked > 100000
+
+
+def test_reslice_end_to_end_config1(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("reconstruct + reslice config1 end to end")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    vol.reconstruct(cfg1.frames.cuda(), _poses_dev(torch, cfg1.sweep.probe_poses), cfg1.sweep.pitch)
+    prm = Params()
+    sl = cfg1.slices
+    outs = [vol.reslice(P, sl.width, sl.height, sl.pitch) for P in sl.probe_poses]
+    torch.cuda.synchronize()
+    for k, P in enumerate(sl.probe_poses):
+        ref = reslice.reslice_grid(cfg1_grid, cfg1.calib, P, sl.width, sl.height, sl.pitch, prm, form="fp64")
+        assert_parity(outs[k].cpu().numpy(), ref, what=f"slice {k}")
+
+
+def _random_case(seed, K=5, dims=(19, 13, 11), p_empty=0.35):
+    rng = np.random.default_rng(seed)
+    S, C = random_grid(rng, K, dims, p_empty=p_empty)
+    origin = np.array([-850.0, 310.0, -1620.0]) + rng.uniform(-1, 1, 3)
+    h = 0.5
+    n0 = random_unit(rng)
+    x0 = random_unit(rng)
+    x0 = x0 - (x0 @ n0) * n0
+    x0 /= np.linalg.norm(x0)
+    rn, rx = [], []
+    for b in range(K):            # bins scattered up to ~35 deg around (n0, x0): some pass, some not
+        R = rodrigues(random_unit(rng), math.radians(rng.uniform(0, 35)))
+        rn.append(R @ n0)
+        rx.append(R @ x0)
+    return rng, S, C, origin, h, np.array(rn), np.array(rx), n0, x0
+
+
+def _slice_pose(rng, origin, h, dims, n0, x0, W, H, pitch, calib, spread_deg=12.0, centre_jitter=3.0):
+    R = rodrigues(random_unit(rng), math.radians(rng.uniform(0, spread_deg)))
+    n, x = R @ n0, R @ x0
+    beam = np.cross(n, x)
+    centre = origin + h * (np.array(dims) - 1) / 2 + rng.normal(0, centre_jitter, 3)
+    T = np.eye(4)
+    T[:3, 0], T[:3, 1], T[:3, 2] = x, beam, n
+    T[:3, 3] = centre - x * (W - 1) * pitch[0] / 2 - beam * (H - 1) * pitch[1] / 2
+    return T @ np.linalg.inv(calib)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_reslice_brute_force_tiny_grids(dare, torch_cuda, seed):
+    torch = torch_cuda
+    note(f"reslice brute-force tiny grid seed={seed}")
+    rng, S, C, origin, h, rn, rx, n0, x0 = _random_case(seed)
+    calib = synth.make_calibration(16, 0.5)
+    prm = Params()
+    dims = (19, 13, 11)
+    vol = make_volume(origin, h, dims, calib, prm)
+    upload_grid(vol, S, C, rn, rx)
+    a, c = quant.storage(S, C, "fp32")
+    for (W, H, pitch) in ((37, 23, (0.21, 0.26)), (16, 16, (0.4, 0.4)), (5, 70, (0.13, 0.11)), (1, 1, (1, 1))):
+        P = _slice_pose(rng, origin, h, dims, n0, x0, W, H, pitch, calib)
+        out = vol.reslice(P, W, H, pitch).cpu().numpy()
+        ref = reslice.reslice(a, c, origin, h, rn, rx, calib, P, W, H, pitch, prm)
+        assert_parity(out, ref, what=f"{W}x{H}")
+    # a plane far outside the grid and a plane misaligned with every bin are all unassigned
+    P = _slice_pose(rng, origin, h, dims, n0, x0, 20, 20, (0.3, 0.3), calib)
+    P[:3, 3] += 500.0
+    assert np.isnan(vol.reslice(P, 20, 20, (0.3, 0.3)).cpu().numpy()).all()
+    P = _slice_pose(rng, origin, h, dims, -n0, x0, 20, 20, (0.3, 0.3), calib, spread_deg=0.0)
+    ref = reslice.reslice(a, c, origin, h, rn, rx, calib, P, 20, 20, (0.3, 0.3), prm)
+    assert np.isnan(ref).all()
+    assert np.isnan(vol.reslice(P, 20, 20, (0.3, 0.3)).cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("R", [2, 3, 4])
+def test_reslice_larger_radius(dare, torch_cuda, R):
+    torch = torch_cuda
+    note(f"reslice radius {R} on a random grid")
+    rng, S, C, origin, h, rn, rx, n0, x0 = _random_case(100 + R, K=3, dims=(21, 17, 19), p_empty=0.5)
+    calib = synth.make_calibration(16, 0.5)
+    prm = Params(radius_vox=R)
+    dims = (21, 17, 19)
+    vol = make_volume(origin, h, dims, calib, prm)
+    upload_grid(vol, S, C, rn, rx)
+    a, c = quant.storage(S, C, "fp32")
+    for (W, H, pitch) in ((29, 19, (0.3, 0.33)), (8, 8, (0.9, 0.9))):
+        P = _slice_pose(rng, origin, h, dims, n0, x0, W, H, pitch, calib)
+        out = vol.reslice(P, W, H, pitch).cpu().numpy()
+        ref = reslice.reslice(a, c, origin, h, rn, rx, calib, P, W, H, pitch, prm)
+        assert_parity(out, ref, what=f"R={R} {W}x{H}")
+
+
+def test_empty_volume_reslices_to_nan(dare, torch_cuda, cfg1):
+    note("empty volume")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
+    out = vol.reslice(cfg1.slices.probe_poses[0], 64, 48, (0.5, 0.5))
+    assert np.isnan(out.cpu().numpy()).all()
+
+
+# ----------------------------------------------------------------------------- precision forms
+
+@pytest.mark.parametrize("dtype,form", [("bf16", "bf16"), ("f16", "fp16"), ("fp8", "fp8")])
+def test_storage_forms_bit_exact(dare, torch_cuda, cfg1, cfg1_grid, dtype, form):
+    torch = torch_cuda
+    note(f"stored pairs {dtype} vs oracle emulation")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(), dtype=dtype)
+    vol.reconstruct(cfg1.frames.cuda(), _poses_dev(torch, cfg1.sweep.probe_poses), cfg1.sweep.pitch)
+    A, Cc = vol.download_storage()
+    torch.cuda.synchronize()
+    a_ref, c_ref = quant.storage(cfg1_grid.S, cfg1_grid.C, form)
+    np.testing.assert_array_equal(Cc.cpu().numpy(), c_ref)
+    np.testing.assert_array_equal(A.cpu().numpy(), a_ref)
+
+
+@pytest.mark.parametrize("dtype,form,max_storage_err", [("bf16", "bf16", 0.5), ("f16", "fp16", 0.05),
+                                                        ("fp8", "fp8", 8.0)])
+def test_reslice_precision_forms(dare, torch_cuda, cfg1, cfg1_grid, dtype, form, max_storage_err):
+    torch = torch_cuda
+    note(f"reslice {dtype} vs oracle on the same dequantised grid and vs FP64")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(), dtype=dtype)
+    vol.reconstruct(cfg1.frames.cuda(), _poses_dev(torch, cfg1.sweep.probe_poses), cfg1.sweep.pitch)
+    prm = Params()
+    sl = cfg1.slices
+    worst = 0.0
+    for k, P in enumerate(sl.probe_poses):
+        out = vol.reslice(P, sl.width, sl.height, sl.pitch).cpu().numpy()
+        ref_q = reslice.reslice_grid(cfg1_grid, cfg1.calib, P, sl.width, sl.height, sl.pitch, prm, form=form)
+        assert_parity(out, ref_q, what=f"{dtype} slice {k}")
+        ref64 = reslice.reslice_grid(cfg1_grid, cfg1.calib, P, sl.width, sl.height, sl.pitch, prm, form="fp64")
+        m = ~np.isnan(ref64)
+        if m.any():
+            worst = max(worst, float(np.abs(out[m] - ref64[m]).max()))
+    assert worst <= max_storage_err, worst
+
+
+# ----------------------------------------------------------------------------- batching
+
+def test_batch_equals_alone(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("batched reslice of mixed volumes, dtypes and sizes vs one by one")
+    vols = []
+    for dt in ("f32", "bf16", "fp8"):
+        v = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(), dtype=dt)
+        upload_grid(v, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+        vols.append(v)
+    rng = np.random.default_rng(5)
+    reqs = []
+    sizes = [(128, 128, (0.25, 0.25)), (37, 23, (0.6, 0.7)), (200, 90, (0.16, 0.3)), (1, 1, (1, 1)),
+             (64, 65, (0.5, 0.5))]
+    for k in range(14):
+        v = vols[k % 3]
+        W, H, pitch = sizes[k % len(sizes)]
+        P = cfg1.slices.probe_poses[int(rng.integers(len(cfg1.slices.probe_poses)))]
+        reqs.append((v, dare.make_spec(P, W, H, pitch)))
+    outs = [torch.full((s.height, s.width), -7.0, device="cuda") for _, s in reqs]
+    ws_bytes = dare.dare_reslice_batch_workspace_bytes([v for v, _ in reqs], [s for _, s in reqs])
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([v for v, _ in reqs], [s for _, s in reqs], outs, ws)
+    alone = []
+    for v, s in reqs:
+        o = torch.full((s.height, s.width), -9.0, device="cuda")
+        dare.dare_reslice(v, s, o)
+        alone.append(o)
+    torch.cuda.synchronize()
+    for k in range(len(reqs)):
+        assert np.array_equal(outs[k].cpu().numpy(), alone[k].cpu().numpy(), equal_nan=True), k
