@@ -45,11 +45,11 @@ __device__ __forceinline__ double uniform_f64(double x) {
 __device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Wave 0 only: slice pose, Eq. 1 / thresholds / Eq. 2 per bin, survivors compacted.
-__device__ __forceinline__ void slice_setup(const VolDev* __restrict__ vd, const double* __restrict__ P,
-                                            SetupLds& sh) {
+// Returns the number of surviving bins; T receives the composed pose (rows 0..2).
+__device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const double* __restrict__ P,
+                                           SetupLds& sh, double T[12]) {
     const int lane = threadIdx.x;
     const double* C = vd->calib;
-    double T[12];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -64,7 +64,14 @@ __device__ __forceinline__ void slice_setup(const VolDev* __restrict__ vd, const
 #pragma unroll
         for (int k = 0; k < 12; ++k) sh.T[k] = T[k];
     }
+    // every lane reads its representative unconditionally: one memory round trip, not two
     const int K = vd->st.K;
+    double rn[3], rx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rn[a] = vd->rep_n[lane][a];
+        rx[a] = vd->rep_x[lane][a];
+    }
     const int ax = vd->normal_axis;
     const double e0[3] = {T[0], T[4], T[8]};
     const double en[3] = {T[ax], T[4 + ax], T[8 + ax]};
@@ -75,8 +82,8 @@ __device__ __forceinline__ void slice_setup(const VolDev* __restrict__ vd, const
     bool keep = false;
     double w = 0.0;
     if (lane < K) {
-        const double dn = dot3(vd->rep_n[lane], nr);
-        const double di = fabs(dot3(vd->rep_x[lane], xr));
+        const double dn = dot3(rn, nr);
+        const double di = fabs(dot3(rx, xr));
         keep = dn >= vd->cos_normal && di >= vd->cos_inplane;
         if (keep) w = exp(vd->k_normal * (dn - 1.0) + vd->k_inplane * (di - 1.0));
     }
@@ -87,6 +94,7 @@ __device__ __forceinline__ void slice_setup(const VolDev* __restrict__ vd, const
         sh.act_w[idx] = (float)w;
     }
     if (lane == 0) sh.kact = __popcll(m);
+    return __popcll(m);
 }
 
 struct SlicePos {            // per-workgroup uniform position terms
@@ -126,33 +134,160 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 }
 
 // ---------------------------------------------------------------- radius 1: trilinear cell
+//
+// The per-voxel direction blend V_v = sum_b w_b c_vb a_vb / sum_b w_b c_vb does
+// not depend on the pixel, so a workgroup blends every voxel its 16x16 tile
+// touches once and keeps the result in LDS (NaN = no surviving sample); each
+// pixel then blends the 8 values of its cell with tent weights.
+//
+// The voxels a tile touches lie within |m.(v - c)| < |m|_1 of the slice plane
+// (m its unit normal, in voxel units) and within the tile's lateral extent
+// widened by the same support.  They are enumerated as short runs along the
+// normal's dominant axis, one run per column of the other two axes, so the
+// staging work follows the footprint rather than the tile's bounding box.
+// All surviving bins of a voxel are loaded before any is accumulated, to keep
+// several gathers in flight.  Tiles whose bounding box exceeds the LDS budget
+// (coarse output pitch, where neighbouring pixels share few voxels) gather per
+// pixel instead.
+
+constexpr int kBoxMax = 4096;        // LDS values per tile (its clamped voxel box)
+constexpr int kBoxEdgeMax = 17;      // voxels per axis: the box spans at most 3 bricks
+constexpr int kSlotMax = 1024;       // (surviving bin, box brick) slots resolved per tile
+constexpr int kBinChunk = 16;        // gathers issued together per voxel
+
 template <int DT>
-__device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, const SliceArgs& s, int unit,
-                                                SetupLds& sh) {
-    using PT = Pair<DT>;
-    if (threadIdx.x < 64) slice_setup(vd, s.P, sh);
-    __syncthreads();
+struct TileLds {
+    int mode;                        // 0: nothing in reach, 1: staged, 2: per-pixel gather
+    int lo[3], dim[3];
+    int blo[3], bdim[3], nbb;
+    int dax, pax, qax;               // dominant normal axis, the other two
+    int depth, ncols;
+    float m[3], c0[3], ua[3], va[3];
+    float thr_n, thr_u, thr_v, len_u, len_v, inv_md;
+    int nlist;                       // staged voxels (compacted)
+    int slot[kSlotMax];
+    float2 scale[DT == DARE_FP8_E4M3 ? kSlotMax : 1];
+    float V[kBoxMax];
+    unsigned short list[kBoxMax];    // box index of each voxel to stage
+};
+
+// Wave 0: the tile's voxel box, slice plane frame and work decomposition.
+// Lanes 0..3 place the tile's four corner pixels (FP64); positions are affine in
+// (i, j), so their cells bound every pixel's cell (one voxel of margin per side
+// absorbs rounding).  The plane frame only drives conservative candidate tests,
+// so every lane evaluates it in FP32 from the FP64 pose.
+template <int DT>
+__device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                           int kact, int i0, int j0, TileLds<DT>& tl) {
+    const int lane = threadIdx.x;
+    const int i1 = min(i0 + kTile - 1, s.W - 1), j1 = min(j0 + kTile - 1, s.H - 1);
     SlicePos q;
-    load_pos(vd, sh, s, q);
-    const int kact = uniform_i32(sh.kact);
-    const int tx = unit % s.tiles_x, ty = unit / s.tiles_x;
-    const int i = tx * kTile + (threadIdx.x & (kTile - 1));
-    const int j = ty * kTile + (threadIdx.x >> 4);
-    if (i >= s.W || j >= s.H) return;
-    float* out = s.out + (size_t)j * s.W + i;
-    const int nx = vd->nx, ny = vd->ny, nz = vd->nz;
-    double c[3];
-    pixel_coords(q, i, j, c);
-    if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)nx && c[1] >= -1.0 && c[1] < (double)ny && c[2] >= -1.0 &&
-                       c[2] < (double)nz)) {
-        *out = __builtin_nanf("");
-        return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.t[a] = T[a * 4 + 3];
+        q.e0[a] = T[a * 4 + 0];
+        q.e1[a] = T[a * 4 + 1];
+        q.o[a] = vd->origin[a];
     }
+    q.inv_h = vd->inv_h;
+    q.sx = s.sx;
+    q.sy = s.sy;
+    const int n[3] = {vd->nx, vd->ny, vd->nz};
+    // corner cells: floors as integers clamped far outside the grid
+    const int k = lane & 3;
+    double c[3];
+    pixel_coords(q, (k & 1) ? i1 : i0, (k & 2) ? j1 : j0, c);
+    int lo[3], hi[3];
+    float c0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int f = (int)fmin(fmax(floor(c[a]), -1048576.0), 1048576.0);
+        int mn = f, mx = f;
+#pragma unroll
+        for (int o = 1; o < 4; ++o) {
+            const int g = __shfl(f, o, 4);
+            mn = min(mn, g);
+            mx = max(mx, g);
+        }
+        lo[a] = max(mn - 1, 0);
+        hi[a] = min(mx + 2, n[a] - 1);
+        c0[a] = (float)__shfl(c[a], 0, 4);
+    }
+    // plane frame in voxel units (FP32)
+    float u[3], w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (float)(q.e0[a] * q.sx * q.inv_h);
+        w[a] = (float)(q.e1[a] * q.sy * q.inv_h);
+    }
+    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float lw = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    float m[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const float rm = 1.0f / sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    const float ru = 1.0f / lu, rw = 1.0f / lw;
+    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
+    int dax = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m[a] *= rm;
+        u[a] *= ru;
+        w[a] *= rw;
+        l1m += fabsf(m[a]);
+        l1u += fabsf(u[a]);
+        l1w += fabsf(w[a]);
+    }
+    if (fabsf(m[1]) > fabsf(m[dax])) dax = 1;
+    if (fabsf(m[2]) > fabsf(m[dax])) dax = 2;
+    if (lane != 0) return;
+    int mode = kact > 0 ? 1 : 0;
+    int nvox = 1, nbb = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] > hi[a]) mode = 0;
+        const int d = hi[a] - lo[a] + 1;
+        tl.lo[a] = lo[a];
+        tl.dim[a] = d > 0 ? d : 0;
+        if (d > kBoxEdgeMax) mode = mode ? 2 : 0;
+        nvox *= tl.dim[a];
+        tl.blo[a] = lo[a] >> 3;
+        tl.bdim[a] = d > 0 ? (hi[a] >> 3) - (lo[a] >> 3) + 1 : 0;
+        nbb *= tl.bdim[a];
+        tl.m[a] = m[a];
+        tl.ua[a] = u[a];
+        tl.va[a] = w[a];
+        tl.c0[a] = c0[a];
+    }
+    if (mode == 1 && (nvox > kBoxMax || kact * nbb > kSlotMax)) mode = 2;
+    tl.mode = mode;
+    tl.nbb = nbb;
+    // every voxel with non-zero weight for a pixel of the tile satisfies, for c0 the
+    // tile's first pixel: |m.(v - c0)| < |m|_1, and ua.(v - c0), va.(v - c0) within the
+    // tile's extent widened by |ua|_1, |va|_1 (margins cover FP32 rounding and the
+    // pose rigidity tolerance)
+    tl.thr_n = l1m + 2e-3f;
+    tl.thr_u = l1u + 0.02f;
+    tl.thr_v = l1w + 0.02f;
+    tl.len_u = (float)(i1 - i0) * lu;
+    tl.len_v = (float)(j1 - j0) * lw;
+    tl.dax = dax;
+    tl.pax = dax == 0 ? 1 : 0;
+    tl.qax = dax == 2 ? 1 : 2;
+    tl.inv_md = 1.0f / m[dax];
+    tl.depth = mode == 1 ? (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(m[dax])) + 2 : 0;
+    tl.ncols = mode == 1 ? tl.dim[tl.pax] * tl.dim[tl.qax] : 0;
+    tl.nlist = 0;
+}
+
+// Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).
+template <int DT>
+__device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, const SetupLds& sh, int kact,
+                                              const double c[3]) {
+    using PT = Pair<DT>;
+    const int nx = vd->nx, ny = vd->ny, nz = vd->nz;
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
     const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
     const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
     const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-    // brick coordinates, in-brick offsets and in-grid flags of the two voxels per axis
     const int nbx = vd->nbx, nby = vd->nby;
     int bx[2], lx[2], rowb[2][2], rowl[2][2];
     bool inx[2], inyz[2][2];
@@ -174,10 +309,13 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
         }
     const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
     const int64_t nbricks = vd->nbricks;
-    float num = 0.0f, den = 0.0f;
-    if (kact == 1) {
-        // one surviving direction: its weight cancels within each voxel
-        const int32_t* __restrict__ tab = vd->table + (int64_t)uniform_i32(sh.act_bin[0]) * nbricks;
+    float A[8], B[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { A[k] = 0.0f; B[k] = 0.0f; }
+    for (int k = 0; k < kact; ++k) {
+        const int b = uniform_i32(sh.act_bin[k]);
+        const float wgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k])));
+        const int32_t* __restrict__ tab = vd->table + (int64_t)b * nbricks;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
@@ -191,53 +329,188 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
                     if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
                     float a, cnt;
                     PT::decode(data[(size_t)slot * kBrickVox + (rowl[dz][dy] | lx[dx])], sc, a, cnt);
-                    if (cnt > 0.0f) {
-                        const float t = (wx[dx] * wy[dy]) * wz[dz];
-                        num = __builtin_fmaf(t, a, num);
-                        den = den + t;
-                    }
-                }
-    } else {
-        float A[8], B[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) { A[k] = 0.0f; B[k] = 0.0f; }
-        for (int k = 0; k < kact; ++k) {
-            const int b = uniform_i32(sh.act_bin[k]);
-            const float wgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k])));
-            const int32_t* __restrict__ tab = vd->table + (int64_t)b * nbricks;
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-                for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 2; ++dx) {
-                        if (!(inx[dx] && inyz[dz][dy])) continue;
-                        const int slot = tab[rowb[dz][dy] + bx[dx]];
-                        if (slot < 0) continue;
-                        float2 sc = make_float2(0.0f, 0.0f);
-                        if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
-                        float a, cnt;
-                        PT::decode(data[(size_t)slot * kBrickVox + (rowl[dz][dy] | lx[dx])], sc, a, cnt);
-                        const float wc = wgt * cnt;
-                        const int v = (dz << 2) | (dy << 1) | dx;
-                        A[v] = __builtin_fmaf(wc, a, A[v]);
-                        B[v] = B[v] + wc;
-                    }
-        }
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
+                    const float wc = wgt * cnt;
                     const int v = (dz << 2) | (dy << 1) | dx;
-                    if (B[v] > 0.0f) {
-                        const float t = (wx[dx] * wy[dy]) * wz[dz];
-                        num = __builtin_fmaf(t, A[v] / B[v], num);
-                        den = den + t;
-                    }
+                    A[v] = __builtin_fmaf(wc, a, A[v]);
+                    B[v] = B[v] + wc;
                 }
     }
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int v = (dz << 2) | (dy << 1) | dx;
+                if (B[v] > 0.0f) {
+                    const float t = (wx[dx] * wy[dy]) * wz[dz];
+                    num = __builtin_fmaf(t, A[v] / B[v], num);
+                    den = den + t;
+                }
+            }
+    return den > 0.0f ? num / den : __builtin_nanf("");
+}
+
+// Blend one staged voxel over the surviving bins; NaN when none holds a sample.
+template <int DT>
+__device__ __forceinline__ float blend_voxel(const typename Pair<DT>::T* __restrict__ data, const SetupLds& sh,
+                                             const TileLds<DT>& tl, int kact, int bb, int local) {
+    using PT = Pair<DT>;
+    const int nbb = tl.nbb;
+    if (kact == 1) {
+        const int slot = tl.slot[bb];
+        if (slot < 0) return __builtin_nanf("");
+        float2 sc = make_float2(0.0f, 0.0f);
+        if constexpr (DT == DARE_FP8_E4M3) sc = tl.scale[bb];
+        float a, cnt;
+        PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
+        return cnt > 0.0f ? a : __builtin_nanf("");
+    }
+    float A = 0.0f, B = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += kBinChunk) {
+        int sl[kBinChunk];
+        typename PT::T p[kBinChunk];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u) sl[u] = (k0 + u < kact) ? tl.slot[(k0 + u) * nbb + bb] : -1;
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u)
+            if (sl[u] >= 0) p[u] = data[(size_t)sl[u] * kBrickVox + local];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u) {
+            if (sl[u] < 0) continue;
+            float2 sc = make_float2(0.0f, 0.0f);
+            if constexpr (DT == DARE_FP8_E4M3) sc = tl.scale[(k0 + u) * nbb + bb];
+            float a, cnt;
+            PT::decode(p[u], sc, a, cnt);
+            const float wc = sh.act_w[k0 + u] * cnt;
+            A = __builtin_fmaf(wc, a, A);
+            B = B + wc;
+        }
+    }
+    return B > 0.0f ? A / B : __builtin_nanf("");
+}
+
+template <int DT>
+__device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, const SliceArgs& s, int unit,
+                                                SetupLds& sh, TileLds<DT>& tl) {
+    const int tx = unit % s.tiles_x, ty = unit / s.tiles_x;
+    const int i0 = tx * kTile, j0 = ty * kTile;
+    if (threadIdx.x < 64) {
+        double T[12];
+        const int ka = slice_setup(vd, s.P, sh, T);
+        tile_setup<DT>(vd, s, T, ka, i0, j0, tl);
+    }
+    __syncthreads();
+    const int kact = uniform_i32(sh.kact);
+    const int mode = uniform_i32(tl.mode);
+    if (mode == 1) {
+        // (a) brick slots (and FP8 scales) of every surviving bin over the box's bricks
+        const int nbb = tl.nbb;
+        const int64_t nbricks = vd->nbricks;
+        for (int e = threadIdx.x; e < kact * nbb; e += blockDim.x) {
+            const int k = e / nbb, r = e - k * nbb;
+            const int bxx = r % tl.bdim[0], byz = r / tl.bdim[0];
+            const int byy = byz % tl.bdim[1], bzz = byz / tl.bdim[1];
+            const int64_t brick = ((int64_t)(tl.blo[2] + bzz) * vd->nby + (tl.blo[1] + byy)) * vd->nbx + (tl.blo[0] + bxx);
+            const int slot = vd->table[(int64_t)sh.act_bin[k] * nbricks + brick];
+            tl.slot[e] = slot;
+            if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = slot >= 0 ? vd->scales[slot] : make_float2(0.0f, 0.0f);
+        }
+        // (b) the voxels the tile touches, compacted into a list (ALU work only)
+        {
+            const int dax = tl.dax, pax = tl.pax, qax = tl.qax, depth = tl.depth;
+            const int nwork = tl.ncols * depth;
+            const int lo[3] = {tl.lo[0], tl.lo[1], tl.lo[2]}, dim[3] = {tl.dim[0], tl.dim[1], tl.dim[2]};
+            const float m[3] = {tl.m[0], tl.m[1], tl.m[2]}, c0[3] = {tl.c0[0], tl.c0[1], tl.c0[2]};
+            const float ua[3] = {tl.ua[0], tl.ua[1], tl.ua[2]}, va[3] = {tl.va[0], tl.va[1], tl.va[2]};
+            const float thr_n = tl.thr_n, thr_u = tl.thr_u, thr_v = tl.thr_v, len_u = tl.len_u, len_v = tl.len_v;
+            const float inv_md = tl.inv_md, half = thr_n * fabsf(inv_md);
+            for (int e = threadIdx.x; e < nwork; e += blockDim.x) {
+                const int col = e / depth, k = e - col * depth;
+                const int vp = lo[pax] + col % dim[pax], vq = lo[qax] + col / dim[pax];
+                const float centre = c0[dax] - (m[pax] * ((float)vp - c0[pax]) + m[qax] * ((float)vq - c0[qax])) * inv_md;
+                // runs start one below the slab (or at the box floor): depth covers the whole slab
+                const int vdd = max((int)floorf(centre - half), lo[dax]) + k;
+                if (vdd >= lo[dax] + dim[dax]) continue;
+                const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
+                const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
+                const int vz = dax == 2 ? vdd : (pax == 2 ? vp : vq);
+                const float d0 = (float)vx - c0[0], d1 = (float)vy - c0[1], d2 = (float)vz - c0[2];
+                const float dn = m[0] * d0 + m[1] * d1 + m[2] * d2;
+                const float du = ua[0] * d0 + ua[1] * d1 + ua[2] * d2;
+                const float dv = va[0] * d0 + va[1] * d1 + va[2] * d2;
+                if (!(fabsf(dn) < thr_n && du > -thr_u && du < len_u + thr_u && dv > -thr_v && dv < len_v + thr_v))
+                    continue;
+                const int idx = atomicAdd(&tl.nlist, 1);
+                tl.list[idx] = (unsigned short)(((vz - lo[2]) * dim[1] + (vy - lo[1])) * dim[0] + (vx - lo[0]));
+            }
+        }
+        __syncthreads();
+        // (c) one thread per listed voxel: all its bins' gathers in flight at once, then the blend
+        const typename Pair<DT>::T* __restrict__ data = (const typename Pair<DT>::T*)vd->data;
+        const int nlist = tl.nlist;
+        const int dxb = tl.dim[0], dyb = tl.dim[1];
+        const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2];
+        const int bx0 = tl.blo[0], by0 = tl.blo[1], bz0 = tl.blo[2], bdx = tl.bdim[0], bdy = tl.bdim[1];
+        for (int e = threadIdx.x; e < nlist; e += blockDim.x) {
+            const int bi = tl.list[e];
+            const int ex = bi % dxb, eyz = bi / dxb;
+            const int vx = lox + ex, vy = loy + eyz % dyb, vz = loz + eyz / dyb;
+            const int bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
+            const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+            tl.V[bi] = blend_voxel<DT>(data, sh, tl, kact, bb, local);
+        }
+        __syncthreads();
+    }
+    const int i = i0 + (threadIdx.x & (kTile - 1));
+    const int j = j0 + (threadIdx.x >> 4);
+    if (i >= s.W || j >= s.H) return;
+    float* out = s.out + (size_t)j * s.W + i;
+    if (mode == 0) {
+        *out = __builtin_nanf("");
+        return;
+    }
+    SlicePos q;
+    load_pos(vd, sh, s, q);
+    const int nx = vd->nx, ny = vd->ny, nz = vd->nz;
+    double c[3];
+    pixel_coords(q, i, j, c);
+    if (!(c[0] >= -1.0 && c[0] < (double)nx && c[1] >= -1.0 && c[1] < (double)ny && c[2] >= -1.0 &&
+          c[2] < (double)nz)) {
+        *out = __builtin_nanf("");
+        return;
+    }
+    if (mode == 2) {
+        *out = pixel_direct<DT>(vd, sh, kact, c);
+        return;
+    }
+    const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
+    const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
+    const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
+    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+    const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2], dx = tl.dim[0], dy = tl.dim[1], dz = tl.dim[2];
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int ddz = 0; ddz < 2; ++ddz)
+#pragma unroll
+        for (int ddy = 0; ddy < 2; ++ddy)
+#pragma unroll
+            for (int ddx = 0; ddx < 2; ++ddx) {
+                const float t = (wx[ddx] * wy[ddy]) * wz[ddz];
+                if (!(t > 0.0f)) continue;   // only voxels with weight were staged
+                const int vx = x0 + ddx, vy = y0 + ddy, vz = z0 + ddz;
+                if ((unsigned)vx >= (unsigned)nx || (unsigned)vy >= (unsigned)ny || (unsigned)vz >= (unsigned)nz)
+                    continue;
+                const int ex = vx - lox, ey = vy - loy, ez = vz - loz;
+                if ((unsigned)ex >= (unsigned)dx || (unsigned)ey >= (unsigned)dy || (unsigned)ez >= (unsigned)dz)
+                    continue;   // unreachable: the box holds every in-grid cell voxel of the tile
+                const float V = tl.V[(ez * dy + ey) * dx + ex];
+                if (V == V) {
+                    num = __builtin_fmaf(t, V, num);
+                    den = den + t;
+                }
+            }
     *out = den > 0.0f ? num / den : __builtin_nanf("");
 }
 
@@ -247,7 +520,10 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
                                                 SetupLds& sh) {
     using PT = Pair<DT>;
     constexpr int PPW = 256 / G;   // pixels per workgroup
-    if (threadIdx.x < 64) slice_setup(vd, s.P, sh);
+    if (threadIdx.x < 64) {
+        double T[12];
+        slice_setup(vd, s.P, sh, T);
+    }
     __syncthreads();
     SlicePos q;
     load_pos(vd, sh, s, q);
@@ -323,7 +599,8 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
 template <int DT>
 __global__ void __launch_bounds__(256) k_reslice_r1(const VolDev* __restrict__ vd, SliceArgs s) {
     __shared__ SetupLds sh;
-    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh);
+    __shared__ TileLds<DT> tl;
+    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh, tl);
 }
 
 template <int DT, int G>
@@ -340,11 +617,13 @@ __global__ void __launch_bounds__(256) k_reslice_r1_batch(const BatchReq* __rest
                                                           const int2* __restrict__ units,
                                                           const int* __restrict__ nunits) {
     __shared__ SetupLds sh;
+    __shared__ TileLds<DT> tl;
     const int n = *nunits;
     for (int u = blockIdx.x; u < n; u += gridDim.x) {
-        const int2 ru = units[u];
-        const BatchReq& rq = reqs[ru.x];
-        reslice_tile_r1<DT>(rq.vol, rq.s, ru.y, sh);
+        const int r = __builtin_amdgcn_readfirstlane(units[u].x);
+        const int t = __builtin_amdgcn_readfirstlane(units[u].y);
+        const BatchReq& rq = reqs[r];
+        reslice_tile_r1<DT>(rq.vol, rq.s, t, sh, tl);
         __syncthreads();
     }
 }
@@ -356,9 +635,10 @@ __global__ void __launch_bounds__(256) k_reslice_rn_batch(const BatchReq* __rest
     __shared__ SetupLds sh;
     const int n = *nunits;
     for (int u = blockIdx.x; u < n; u += gridDim.x) {
-        const int2 ru = units[u];
-        const BatchReq& rq = reqs[ru.x];
-        reslice_unit_rn<DT, G>(rq.vol, rq.s, ru.y, sh);
+        const int r = __builtin_amdgcn_readfirstlane(units[u].x);
+        const int t = __builtin_amdgcn_readfirstlane(units[u].y);
+        const BatchReq& rq = reqs[r];
+        reslice_unit_rn<DT, G>(rq.vol, rq.s, t, sh);
         __syncthreads();
     }
 }
