@@ -83,6 +83,146 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
 
+class Console:
+    """A simulated expert console: a probe pose following a smooth random walk
+    (Ornstein-Uhlenbeck velocity and angular velocity, tau = 1 s, 5 mm/s and
+    20 deg/s scales), starting at an acquired pose, kept inside the volume."""
+
+    def __init__(self, rng, wl, vol_id, sizes):
+        self.rng = rng
+        self.vol_id = vol_id
+        self.wl = wl
+        f = int(rng.integers(len(wl.sweep.image_poses)))
+        self.R = wl.sweep.image_poses[f][:3, :3].copy()
+        self.c = wl.sweep.centers[f].copy()
+        self.v = np.zeros(3)
+        self.w = np.zeros(3)
+        self.sizes = sizes
+        self.lo = wl.origin + 0.15 * (np.array(wl.dims) - 1) * wl.spacing
+        self.hi = wl.origin + 0.85 * (np.array(wl.dims) - 1) * wl.spacing
+
+    def step(self, dt, synth):
+        tau, sv, sw = 1.0, 5.0, np.deg2rad(20.0)
+        a = np.exp(-dt / tau)
+        b = np.sqrt(max(0.0, 1.0 - a * a))
+        self.v = a * self.v + b * sv * self.rng.standard_normal(3)
+        self.w = a * self.w + b * sw * self.rng.standard_normal(3)
+        self.c = self.c + self.v * dt
+        for k in range(3):                     # reflect at the volume's inner bounds
+            if self.c[k] < self.lo[k]:
+                self.c[k] = 2 * self.lo[k] - self.c[k]
+                self.v[k] = -self.v[k]
+            if self.c[k] > self.hi[k]:
+                self.c[k] = 2 * self.hi[k] - self.c[k]
+                self.v[k] = -self.v[k]
+        self.R = synth.rotvec_to_matrix(self.w * dt) @ self.R
+        n = int(self.sizes[int(self.rng.integers(len(self.sizes)))])
+        L = self.wl.dims[0] * self.wl.spacing
+        pitch = (L / n, L / n)
+        T = synth.image_pose(self.c, self.R[:, 0], self.R[:, 1], n, n, pitch)
+        return synth.probe_pose_from_image_pose(T, self.wl.calib, dtype=np.float64), n, pitch
+
+
+def run_serving(dare, torch, synth, seconds, sat_seconds, log):
+    """Serving form: 4 resident BF16 volumes, 64 consoles, Poisson arrivals at 30 Hz each."""
+    dev = torch.device("cuda:0")
+    vols, wls = [], []
+    t0 = time.perf_counter()
+    for N, seed in ((128, 41), (256, 42), (256, 43), (384, 44)):
+        wl = synth.serving_volume(N, seed)
+        fr = wl.render(dev)
+        poses = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).to(dev)
+        geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+        nb = ((N + 7) // 8) ** 3
+        v = dare.Volume(geom, dare.default_params(), dtype="bf16", bricks=nb * 40)
+        v.reconstruct(fr, poses, wl.sweep.pitch)
+        del fr, poses
+        vols.append(v)
+        wls.append(wl)
+    torch.cuda.synchronize()
+    log(f"serving: built 4 BF16 volumes in {time.perf_counter() - t0:.1f} s: "
+        + ", ".join(f"{w.dims[0]}^3 {v.info().bins} bins" for w, v in zip(wls, vols)))
+    sizes = (256, 512, 768, 1024)
+    srv = dare.Server(2 << 30, n_streams=3, max_tick_requests=64, max_tick_pixels=16 << 20, max_queue=8192)
+    ids = [srv.add_volume(v) for v in vols]
+    rng = np.random.default_rng(2024)
+    consoles = [Console(rng, wls[k // 16], ids[k // 16], sizes) for k in range(64)]
+    ring = 6
+    bufs = [[torch.empty((1024 * 1024,), dtype=torch.float32, pin_memory=True) for _ in range(ring)]
+            for _ in range(64)]
+    for vi in range(4):                         # warm up every size once per volume
+        for n in sizes:
+            L = wls[vi].dims[0] * wls[vi].spacing
+            t = srv.submit(ids[vi], consoles[vi * 16].step(0.0, synth)[0], n, n, (L / n, L / n), bufs[0][0])
+            srv.drain()
+            srv.poll(t)
+
+    def run(duration, closed):
+        rate = 30.0
+        next_t = [time.perf_counter() + rng.exponential(1.0 / rate) for _ in range(64)] if not closed else None
+        last = [time.perf_counter()] * 64
+        slot = [0] * 64
+        pending = {}
+        lat = {n: [] for n in sizes}
+        dev_lat = []
+        px = 0
+        t_start = time.perf_counter()
+        st0 = srv.stats()
+        while True:
+            now = time.perf_counter()
+            if now - t_start > duration:
+                break
+            for k in range(64):
+                if closed:
+                    if any(v[0] == k for v in pending.values()):
+                        continue
+                elif now < next_t[k]:
+                    continue
+                c = consoles[k]
+                P, n, pitch = c.step(max(1e-3, now - last[k]), synth)
+                last[k] = now
+                buf = bufs[k][slot[k] % ring]
+                slot[k] += 1
+                t = srv.submit(c.vol_id, P, n, n, pitch, buf)
+                if t is not None:
+                    pending[t] = (k, n)
+                if not closed:
+                    next_t[k] += rng.exponential(1.0 / rate)
+            for t in list(pending):
+                tm = srv.poll(t)
+                if tm is not None:
+                    k, n = pending.pop(t)
+                    lat[n].append(1e3 * (tm.t_host_done - tm.t_submit))
+                    dev_lat.append(1e3 * (tm.t_device_done - tm.t_submit))
+                    px += n * n
+        srv.drain()
+        for t in list(pending):
+            tm = srv.poll(t)
+            if tm is not None:
+                k, n = pending.pop(t)
+                lat[n].append(1e3 * (tm.t_host_done - tm.t_submit))
+                px += n * n
+        el = time.perf_counter() - t_start
+        st1 = srv.stats()
+        alll = [x for v in lat.values() for x in v]
+        return {"seconds": round(el, 2), "requests": len(alll), "Mpx_s": round(px / el / 1e6, 1),
+                "latency_ms": {"p50": round(percentile(alll, 50), 3), "p99": round(percentile(alll, 99), 3),
+                               "p99_512": round(percentile(lat[512], 99), 3),
+                               "p50_512": round(percentile(lat[512], 50), 3),
+                               "p99_1024": round(percentile(lat[1024], 99), 3),
+                               "device_p99": round(percentile(dev_lat, 99), 3)},
+                "ticks": int(st1.ticks - st0.ticks),
+                "mean_requests_per_tick": round(len(alll) / max(1, st1.ticks - st0.ticks), 2)}
+
+    offered = run(seconds, closed=False)
+    log(f"serving at 64 x 30 Hz: {offered}")
+    sat = run(sat_seconds, closed=True)
+    log(f"serving saturated (closed loop): {sat}")
+    srv.close()
+    return {"volumes": [list(w.dims) for w in wls], "dtype": "bf16", "consoles": 64, "rate_hz_per_console": 30,
+            "sizes": list(sizes), "offered": offered, "saturation": sat}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +235,9 @@ def main():
     ap.add_argument("--roofline-sample", type=int, default=100)
     ap.add_argument("--latency-sample", type=int, default=200)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "reslice_traffic.json"))
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--saturation-seconds", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures one GPU's share of the work "
@@ -357,6 +500,14 @@ def main():
                         "gpu_error_vs_fp64_on_sample": errs}
         log(f"oracle: {cpu_mpx:.3f} Mpixel/s ({t_res / ncs:.2f} s per slice); errors {errs}")
 
+    # ---- serving form: continuous batching under console load
+    serving = None
+    if not args.no_serving:
+        form_vols.clear()
+        del outs
+        torch.cuda.empty_cache()
+        serving = run_serving(dare, torch, synth, args.serving_seconds, args.saturation_seconds, log)
+
     result = {
         "metric": "reslice Mpixel/s + p50/p99 latency, served BF16 vs plain FP32; % HBM roofline",
         "value": round(value, 1),
@@ -381,6 +532,7 @@ def main():
                         "frames_per_s": round(F / float(np.median(recon_times)), 1),
                         "input_Mpx_s": round(F * Wf * Hf / float(np.median(recon_times)) / 1e6, 1)},
         "forms": forms,
+        "serving": serving,
         "cpu_baseline": cpu_baseline,
     }
     print(json.dumps(result), flush=True)

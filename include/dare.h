@@ -216,6 +216,67 @@ dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* 
  * bandwidth probe that calibrates the HBM roofline and the byte counters. */
 dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of reslice requests from many consoles (the
+ * expert consoles of Sec. 1 each reslice the shared volume at their own
+ * pose).  A server owns a caller-supplied device arena (its HBM budget: one
+ * request table per stream plus result slots), up to `n_streams` (1..4) HIP
+ * streams of default priority, and a host thread that groups waiting
+ * requests into ticks.  A request is admitted, first come first served, when
+ * a result slot of its size can be allocated in the arena; each tick uploads
+ * its request table, replays a captured graph of the batched reslice on a
+ * free stream (ticks on different streams overlap on the device), then
+ * copies every result into its `host_out` buffer (pinned host memory keeps
+ * the copy asynchronous).  All volumes of one server share one storage dtype
+ * and radius.  Volumes must not be reconstructed while the server can
+ * reslice them.
+ * ------------------------------------------------------------------------ */
+typedef struct dare_server dare_server;
+
+typedef struct {
+    int64_t max_tick_pixels;  /* pixels per tick (bounds one launch); >= largest request    */
+    int32_t max_tick_requests;/* requests per tick, 1..4096                                 */
+    int32_t n_streams;        /* 1..4                                                        */
+    int32_t max_queue;        /* waiting requests before submit returns QUEUE_FULL          */
+    int32_t use_graphs;       /* 1: replay captured graphs per tick; 0: plain launches       */
+} dare_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t ticks;
+    int64_t pixels;
+    double busy_seconds;      /* host-measured time with at least one tick in flight         */
+} dare_server_stats;
+
+typedef struct {
+    double t_submit, t_admit, t_launch, t_device_done, t_host_done; /* seconds, steady clock */
+} dare_request_times;
+
+/* Defaults: 8 Mpixel and 64 requests per tick, 3 streams, 4096 queued, graphs on. */
+void dare_default_server_config(dare_server_config* c);
+/* arena_dev: 256-byte aligned device memory, kept allocated until destroy. */
+dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, uint64_t arena_bytes,
+                               dare_server** out);
+/* Register a volume; INVALID_ARG if its dtype or radius differs from the first one's. */
+dare_status dare_server_add_volume(dare_server* s, const dare_volume* v, int32_t* volume_id);
+/* Queue a request.  host_out (required) receives height*width float32,
+ * row-major, NaN where unassigned, once the request completes.  Returns
+ * QUEUE_FULL when max_queue requests wait, and INVALID_ARG when the request
+ * can never fit the arena's result space or one tick. */
+dare_status dare_server_submit(dare_server* s, int32_t volume_id, const dare_slice_spec* spec,
+                               float* host_out, uint64_t* ticket);
+/* DARE_OK with *times filled (may be NULL) once the result is in host
+ * memory, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed.  A
+ * ticket is forgotten once poll has returned DARE_OK or DARE_ERR_HIP. */
+dare_status dare_server_poll(dare_server* s, uint64_t ticket, dare_request_times* times);
+/* Block until every submitted request has completed. */
+dare_status dare_server_drain(dare_server* s);
+dare_status dare_server_get_stats(dare_server* s, dare_server_stats* out);
+/* Drain, stop the scheduler thread and release streams, graphs and staging (not the arena). */
+dare_status dare_server_destroy(dare_server* s);
+/* Steady-clock seconds used by the request times. */
+double dare_now_seconds(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,21 @@ class VolumeInfo(ct.Structure):
                 ("bricks_capacity", ct.c_int64), ("bytes_per_brick", ct.c_int64), ("brick_grid", ct.c_int64 * 3)]
 
 
+class ServerConfig(ct.Structure):
+    _fields_ = [("max_tick_pixels", ct.c_int64), ("max_tick_requests", ct.c_int32), ("n_streams", ct.c_int32),
+                ("max_queue", ct.c_int32), ("use_graphs", ct.c_int32)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("rejected", ct.c_int64),
+                ("ticks", ct.c_int64), ("pixels", ct.c_int64), ("busy_seconds", ct.c_double)]
+
+
+class RequestTimes(ct.Structure):
+    _fields_ = [("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_launch", ct.c_double),
+                ("t_device_done", ct.c_double), ("t_host_done", ct.c_double)]
+
+
 class DareError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -80,6 +95,15 @@ def _load():
         "dare_copy_probe": (ct.c_int, [P, P, U64, P]),
         "dare_slice_active_bins": (ct.c_int, [V, ct.POINTER(SliceSpec), ct.POINTER(I32), ct.POINTER(D),
                                               ct.POINTER(I32)]),
+        "dare_now_seconds": (D, []),
+        "dare_default_server_config": (None, [ct.POINTER(ServerConfig)]),
+        "dare_server_create": (ct.c_int, [ct.POINTER(ServerConfig), P, U64, ct.POINTER(V)]),
+        "dare_server_add_volume": (ct.c_int, [V, V, ct.POINTER(I32)]),
+        "dare_server_submit": (ct.c_int, [V, I32, ct.POINTER(SliceSpec), P, ct.POINTER(U64)]),
+        "dare_server_poll": (ct.c_int, [V, U64, ct.POINTER(RequestTimes)]),
+        "dare_server_drain": (ct.c_int, [V]),
+        "dare_server_get_stats": (ct.c_int, [V, ct.POINTER(ServerStats)]),
+        "dare_server_destroy": (ct.c_int, [V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -291,3 +315,76 @@ class Volume:
         rx = (ct.c_double * max(1, 3 * K))(*np.asarray(rep_x, np.float64).reshape(-1).tolist())
         return _check(lib.dare_volume_upload_sums(self.handle, rn, rx, K, _ptr(S.contiguous()),
                                                   _ptr(C.contiguous()), _stream(stream)), "dare_volume_upload_sums")
+
+
+def default_server_config(**over) -> ServerConfig:
+    c = ServerConfig()
+    lib.dare_default_server_config(ct.byref(c))
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Continuous-batching reslice server (C++ scheduler thread inside the library).
+
+    ``arena_bytes`` of device memory hold one request table per stream and the
+    result slots; requests wait in FIFO order until a slot of their size fits."""
+
+    def __init__(self, arena_bytes: int, device="cuda", **cfg):
+        import torch
+        self.config = default_server_config(**cfg)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ct.c_void_p()
+        _check(lib.dare_server_create(ct.byref(self.config), _ptr(self.arena), int(arena_bytes), ct.byref(h)),
+               "dare_server_create")
+        self.handle = h
+        self._volumes = []
+
+    def add_volume(self, vol: "Volume") -> int:
+        vid = ct.c_int32()
+        _check(lib.dare_server_add_volume(self.handle, vol.handle, ct.byref(vid)), "dare_server_add_volume")
+        self._volumes.append(vol)
+        return vid.value
+
+    def submit(self, volume_id: int, probe_pose, width, height, pitch, host_out):
+        """Queue a request; returns its ticket, or None when the queue is full."""
+        t = ct.c_uint64()
+        st = lib.dare_server_submit(self.handle, int(volume_id), ct.byref(make_spec(probe_pose, width, height, pitch)),
+                                    _ptr(host_out), ct.byref(t))
+        if st == ERR_QUEUE_FULL:
+            return None
+        _check(st, "dare_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        """RequestTimes once the result is in host memory, else None."""
+        tm = RequestTimes()
+        st = lib.dare_server_poll(self.handle, ct.c_uint64(ticket), ct.byref(tm))
+        if st == ERR_NOT_READY:
+            return None
+        _check(st, "dare_server_poll")
+        return tm
+
+    def drain(self):
+        _check(lib.dare_server_drain(self.handle), "dare_server_drain")
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib.dare_server_get_stats(self.handle, ct.byref(st)), "dare_server_get_stats")
+        return st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.dare_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_seconds() -> float:
+    return float(lib.dare_now_seconds())

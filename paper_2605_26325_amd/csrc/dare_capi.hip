@@ -30,6 +30,7 @@ struct dare_volume {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kBatchGrid = 2048;   // workgroups of the batched radius-1 kernel (persistent)
 
 struct DeviceGuard {
     int prev = -1;
@@ -178,6 +179,14 @@ SliceArgs make_args(const dare_slice_spec* s, float* out) {
 }
 
 }  // namespace
+
+namespace dare {
+const VolDev* volume_device(const dare_volume* v) { return v->dev; }
+int volume_dtype(const dare_volume* v) { return v->dtype; }
+int volume_radius(const dare_volume* v) { return (int)v->p.radius_vox; }
+int volume_device_id(const dare_volume* v) { return v->device; }
+dare_status check_slice_spec(const dare_slice_spec* s) { return check_spec(s); }
+}  // namespace dare
 
 extern "C" {
 
@@ -350,9 +359,23 @@ struct Group {
     std::vector<int2> units;
 };
 
-uint64_t group_bytes(size_t nreq, size_t nunits) {
-    return align_up(sizeof(int)) + align_up(nreq * sizeof(BatchReq)) + align_up(nunits * sizeof(int2));
+// Batch workspace of one launch group: [counts: units, requests] [requests] [units] [setup records].
+// The first three parts are uploaded; the setup records are written by the device pre-pass.
+struct GroupLayout {
+    uint64_t o_req, o_units, o_setup, upload, total;
+};
+
+GroupLayout group_layout(size_t nreq, size_t nunits) {
+    GroupLayout L;
+    L.o_req = align_up(4 * sizeof(int));
+    L.o_units = L.o_req + align_up(nreq * sizeof(BatchReq));
+    L.o_setup = L.o_units + align_up(nunits * sizeof(int2));
+    L.upload = L.o_setup;
+    L.total = L.o_setup + align_up(nreq * sizeof(SliceSetup));
+    return L;
 }
+
+uint64_t group_bytes(size_t nreq, size_t nunits) { return group_layout(nreq, nunits).total; }
 
 }  // namespace
 
@@ -404,16 +427,20 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
     for (auto& kv : groups) {
         Group& g = kv.second;
         const int nunits = (int)g.units.size();
-        const uint64_t o_req = align_up(sizeof(int));
-        const uint64_t o_units = o_req + align_up(g.reqs.size() * sizeof(BatchReq));
-        std::vector<char> host(group_bytes(g.reqs.size(), g.units.size()));
-        memcpy(host.data(), &nunits, sizeof(int));
-        memcpy(host.data() + o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
-        memcpy(host.data() + o_units, g.units.data(), g.units.size() * sizeof(int2));
+        const int nreq = (int)g.reqs.size();
+        const GroupLayout L = group_layout(g.reqs.size(), g.units.size());
+        std::vector<char> host(L.upload, 0);
+        const int counts[4] = {nunits, nreq, 0, 0};
+        memcpy(host.data(), counts, sizeof(counts));
+        memcpy(host.data() + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
+        memcpy(host.data() + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
         HIP_TRY(hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream));
-        HIP_TRY(launch_reslice_batch(kv.first.first, kv.first.second, (const BatchReq*)(ws + o_req),
-                                     (const int2*)(ws + o_units), (const int*)ws, nunits, stream));
-        ws += host.size();
+        const int R = kv.first.second;
+        const int grid = R <= 1 ? std::min(nunits, kBatchGrid) : std::min(nunits, 65535);
+        HIP_TRY(launch_reslice_batch(kv.first.first, R, (const BatchReq*)(ws + L.o_req), (SliceSetup*)(ws + L.o_setup),
+                                     (const int2*)(ws + L.o_units), (const int*)ws, std::min(nreq, 1024), grid,
+                                     stream));
+        ws += L.total;
     }
     return DARE_OK;
 }

@@ -91,6 +91,18 @@ struct BatchReq {
     SliceArgs s;
 };
 
+// Per-request reslice setup: composed pose, surviving bins and their Eq. 2
+// weights, and the plane frame used by the footprint tests.
+struct SliceSetup {
+    double T[12];                         // rows 0..2 of the image pose T = P . C
+    float fm[3], fu[3], fw[3];            // unit normal and in-plane unit axes, voxel units
+    float lu, lw;                         // voxels per pixel step along the two in-plane axes
+    int dax;                              // dominant axis of the normal
+    int kact;                             // surviving bins
+    int act_bin[kMaxBins];
+    float act_w[kMaxBins];
+};
+
 inline int pair_bytes(int dtype) {
     switch (dtype) {
         case DARE_F32: return 8;
@@ -123,8 +135,8 @@ hipError_t launch_download_sums(const VolDev* vd, uint32_t* S, uint32_t* C, int 
 hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float* C, int K, int nx, int ny,
                                    int nz, hipStream_t stream);
 hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream);
-hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, const int2* tiles,
-                                const int* ntiles_dev, int grid, hipStream_t stream);
+hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
+                                const int* counts, int nreq_grid, int grid, hipStream_t stream);
 hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream);
 
 // Reslice work decomposition: lanes per output pixel (1 for radius 1) and the

@@ -24,12 +24,7 @@ namespace dare {
 
 namespace {
 
-struct SetupLds {
-    double T[12];
-    int kact;
-    int act_bin[kMaxBins];
-    float act_w[kMaxBins];
-};
+using SetupLds = SliceSetup;
 
 __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
@@ -46,9 +41,10 @@ __device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_read
 
 // Wave 0 only: slice pose, Eq. 1 / thresholds / Eq. 2 per bin, survivors compacted.
 // Returns the number of surviving bins; T receives the composed pose (rows 0..2).
-__device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const double* __restrict__ P,
-                                           SetupLds& sh, double T[12]) {
+__device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SetupLds& sh,
+                                           double T[12]) {
     const int lane = threadIdx.x;
+    const double* P = s.P;
     const double* C = vd->calib;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -93,7 +89,35 @@ __device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const 
         sh.act_bin[idx] = lane;
         sh.act_w[idx] = (float)w;
     }
-    if (lane == 0) sh.kact = __popcll(m);
+    // plane frame in voxel units; it only drives conservative footprint tests, so FP32
+    const double inv_h = vd->inv_h;
+    float u[3], v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (float)(T[a * 4 + 0] * s.sx * inv_h);
+        v[a] = (float)(T[a * 4 + 1] * s.sy * inv_h);
+    }
+    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float lv = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    float nm[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+    const float rm = 1.0f / sqrtf(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
+    int dax = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nm[a] *= rm;
+    if (fabsf(nm[1]) > fabsf(nm[dax])) dax = 1;
+    if (fabsf(nm[2]) > fabsf(nm[dax])) dax = 2;
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            sh.fm[a] = nm[a];
+            sh.fu[a] = u[a] / lu;
+            sh.fw[a] = v[a] / lv;
+        }
+        sh.lu = lu;
+        sh.lw = lv;
+        sh.dax = dax;
+        sh.kact = __popcll(m);
+    }
     return __popcll(m);
 }
 
@@ -150,7 +174,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // (coarse output pitch, where neighbouring pixels share few voxels) gather per
 // pixel instead.
 
-constexpr int kBoxMax = 4096;        // LDS values per tile (its clamped voxel box)
+constexpr int kBoxMax = 3072;        // LDS values per tile (its clamped voxel box)
 constexpr int kBoxEdgeMax = 17;      // voxels per axis: the box spans at most 3 bricks
 constexpr int kSlotMax = 1024;       // (surviving bin, box brick) slots resolved per tile
 constexpr int kBinChunk = 16;        // gathers issued together per voxel
@@ -171,14 +195,13 @@ struct TileLds {
     unsigned short list[kBoxMax];    // box index of each voxel to stage
 };
 
-// Wave 0: the tile's voxel box, slice plane frame and work decomposition.
-// Lanes 0..3 place the tile's four corner pixels (FP64); positions are affine in
-// (i, j), so their cells bound every pixel's cell (one voxel of margin per side
-// absorbs rounding).  The plane frame only drives conservative candidate tests,
-// so every lane evaluates it in FP32 from the FP64 pose.
+// Wave 0: the tile's voxel box and work decomposition.  Lanes 0..3 place the
+// tile's four corner pixels (FP64); positions are affine in (i, j), so their
+// cells bound every pixel's cell (one voxel of margin per side absorbs
+// rounding).  Lane 0 derives the footprint tests from the slice's plane frame.
 template <int DT>
 __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
-                                           int kact, int i0, int j0, TileLds<DT>& tl) {
+                                           const SetupLds& sh, int kact, int i0, int j0, TileLds<DT>& tl) {
     const int lane = threadIdx.x;
     const int i1 = min(i0 + kTile - 1, s.W - 1), j1 = min(j0 + kTile - 1, s.H - 1);
     SlicePos q;
@@ -193,7 +216,6 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
     q.sx = s.sx;
     q.sy = s.sy;
     const int n[3] = {vd->nx, vd->ny, vd->nz};
-    // corner cells: floors as integers clamped far outside the grid
     const int k = lane & 3;
     double c[3];
     pixel_coords(q, (k & 1) ? i1 : i0, (k & 2) ? j1 : j0, c);
@@ -213,34 +235,10 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
         hi[a] = min(mx + 2, n[a] - 1);
         c0[a] = (float)__shfl(c[a], 0, 4);
     }
-    // plane frame in voxel units (FP32)
-    float u[3], w[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        u[a] = (float)(q.e0[a] * q.sx * q.inv_h);
-        w[a] = (float)(q.e1[a] * q.sy * q.inv_h);
-    }
-    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const float lw = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    float m[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
-    const float rm = 1.0f / sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-    const float ru = 1.0f / lu, rw = 1.0f / lw;
-    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
-    int dax = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        m[a] *= rm;
-        u[a] *= ru;
-        w[a] *= rw;
-        l1m += fabsf(m[a]);
-        l1u += fabsf(u[a]);
-        l1w += fabsf(w[a]);
-    }
-    if (fabsf(m[1]) > fabsf(m[dax])) dax = 1;
-    if (fabsf(m[2]) > fabsf(m[dax])) dax = 2;
     if (lane != 0) return;
     int mode = kact > 0 ? 1 : 0;
     int nvox = 1, nbb = 1;
+    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (lo[a] > hi[a]) mode = 0;
@@ -252,10 +250,13 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
         tl.blo[a] = lo[a] >> 3;
         tl.bdim[a] = d > 0 ? (hi[a] >> 3) - (lo[a] >> 3) + 1 : 0;
         nbb *= tl.bdim[a];
-        tl.m[a] = m[a];
-        tl.ua[a] = u[a];
-        tl.va[a] = w[a];
+        tl.m[a] = sh.fm[a];
+        tl.ua[a] = sh.fu[a];
+        tl.va[a] = sh.fw[a];
         tl.c0[a] = c0[a];
+        l1m += fabsf(sh.fm[a]);
+        l1u += fabsf(sh.fu[a]);
+        l1w += fabsf(sh.fw[a]);
     }
     if (mode == 1 && (nvox > kBoxMax || kact * nbb > kSlotMax)) mode = 2;
     tl.mode = mode;
@@ -264,16 +265,17 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
     // tile's first pixel: |m.(v - c0)| < |m|_1, and ua.(v - c0), va.(v - c0) within the
     // tile's extent widened by |ua|_1, |va|_1 (margins cover FP32 rounding and the
     // pose rigidity tolerance)
+    const int dax = sh.dax;
     tl.thr_n = l1m + 2e-3f;
     tl.thr_u = l1u + 0.02f;
     tl.thr_v = l1w + 0.02f;
-    tl.len_u = (float)(i1 - i0) * lu;
-    tl.len_v = (float)(j1 - j0) * lw;
+    tl.len_u = (float)(i1 - i0) * sh.lu;
+    tl.len_v = (float)(j1 - j0) * sh.lw;
     tl.dax = dax;
     tl.pax = dax == 0 ? 1 : 0;
     tl.qax = dax == 2 ? 1 : 2;
-    tl.inv_md = 1.0f / m[dax];
-    tl.depth = mode == 1 ? (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(m[dax])) + 2 : 0;
+    tl.inv_md = 1.0f / sh.fm[dax];
+    tl.depth = mode == 1 ? (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(sh.fm[dax])) + 2 : 0;
     tl.ncols = mode == 1 ? tl.dim[tl.pax] * tl.dim[tl.qax] : 0;
     tl.nlist = 0;
 }
@@ -391,15 +393,24 @@ __device__ __forceinline__ float blend_voxel(const typename Pair<DT>::T* __restr
     return B > 0.0f ? A / B : __builtin_nanf("");
 }
 
+// One 16x16 tile.  With have_setup the slice setup is already in `sh` (batched
+// requests share one record computed by a pre-pass); otherwise wave 0 computes it.
 template <int DT>
 __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, const SliceArgs& s, int unit,
-                                                SetupLds& sh, TileLds<DT>& tl) {
+                                                SetupLds& sh, TileLds<DT>& tl, bool have_setup) {
     const int tx = unit % s.tiles_x, ty = unit / s.tiles_x;
     const int i0 = tx * kTile, j0 = ty * kTile;
     if (threadIdx.x < 64) {
         double T[12];
-        const int ka = slice_setup(vd, s.P, sh, T);
-        tile_setup<DT>(vd, s, T, ka, i0, j0, tl);
+        int ka;
+        if (have_setup) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) T[k] = sh.T[k];
+            ka = sh.kact;
+        } else {
+            ka = slice_setup(vd, s, sh, T);
+        }
+        tile_setup<DT>(vd, s, T, sh, ka, i0, j0, tl);
     }
     __syncthreads();
     const int kact = uniform_i32(sh.kact);
@@ -522,7 +533,7 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
     constexpr int PPW = 256 / G;   // pixels per workgroup
     if (threadIdx.x < 64) {
         double T[12];
-        slice_setup(vd, s.P, sh, T);
+        slice_setup(vd, s, sh, T);
     }
     __syncthreads();
     SlicePos q;
@@ -600,7 +611,7 @@ template <int DT>
 __global__ void __launch_bounds__(256) k_reslice_r1(const VolDev* __restrict__ vd, SliceArgs s) {
     __shared__ SetupLds sh;
     __shared__ TileLds<DT> tl;
-    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh, tl);
+    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh, tl, false);
 }
 
 template <int DT, int G>
@@ -609,21 +620,45 @@ __global__ void __launch_bounds__(256) k_reslice_rn(const VolDev* __restrict__ v
     reslice_unit_rn<DT, G>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-// Batched form: a table of (request, unit) pairs; each workgroup walks units
-// blockIdx.x, blockIdx.x + gridDim.x, ... up to the device-side count, so the
-// grid can stay fixed while the work varies (graph replay).
+// Batched form.  A pre-pass composes every request's pose and evaluates its
+// gates and weights once (one wave per request); the tile kernel then walks a
+// table of (request, unit) pairs.  Each workgroup takes a contiguous run of the
+// table, so consecutive units mostly share a request and its setup record is
+// copied into LDS only when the request changes.  Counts are read from device
+// memory so a fixed grid serves any batch (graph replay).
+__global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__ reqs, SliceSetup* __restrict__ setups,
+                                                     const int* __restrict__ counts) {
+    const int nreq = counts[1];
+    for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
+        double T[12];
+        slice_setup(reqs[r].vol, reqs[r].s, setups[r], T);
+    }
+}
+
 template <int DT>
 __global__ void __launch_bounds__(256) k_reslice_r1_batch(const BatchReq* __restrict__ reqs,
+                                                          const SliceSetup* __restrict__ setups,
                                                           const int2* __restrict__ units,
-                                                          const int* __restrict__ nunits) {
+                                                          const int* __restrict__ counts) {
     __shared__ SetupLds sh;
     __shared__ TileLds<DT> tl;
-    const int n = *nunits;
-    for (int u = blockIdx.x; u < n; u += gridDim.x) {
+    const int n = counts[0];
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int u0 = xcd_remap(blockIdx.x, gridDim.x) * per;
+    const int u1 = min(n, u0 + per);
+    int cur = -1;
+    for (int u = u0; u < u1; ++u) {
         const int r = __builtin_amdgcn_readfirstlane(units[u].x);
         const int t = __builtin_amdgcn_readfirstlane(units[u].y);
+        if (r != cur) {
+            const int* src = (const int*)(setups + r);
+            int* dst = (int*)&sh;
+            for (int k = threadIdx.x; k < (int)(sizeof(SliceSetup) / 4); k += blockDim.x) dst[k] = src[k];
+            cur = r;
+            __syncthreads();
+        }
         const BatchReq& rq = reqs[r];
-        reslice_tile_r1<DT>(rq.vol, rq.s, t, sh, tl);
+        reslice_tile_r1<DT>(rq.vol, rq.s, t, sh, tl, true);
         __syncthreads();
     }
 }
@@ -631,9 +666,9 @@ __global__ void __launch_bounds__(256) k_reslice_r1_batch(const BatchReq* __rest
 template <int DT, int G>
 __global__ void __launch_bounds__(256) k_reslice_rn_batch(const BatchReq* __restrict__ reqs,
                                                           const int2* __restrict__ units,
-                                                          const int* __restrict__ nunits) {
+                                                          const int* __restrict__ counts) {
     __shared__ SetupLds sh;
-    const int n = *nunits;
+    const int n = counts[0];
     for (int u = blockIdx.x; u < n; u += gridDim.x) {
         const int r = __builtin_amdgcn_readfirstlane(units[u].x);
         const int t = __builtin_amdgcn_readfirstlane(units[u].y);
@@ -682,13 +717,14 @@ hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceAr
     return hipGetLastError();
 }
 
-hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, const int2* units, const int* nunits,
-                                int grid, hipStream_t stream) {
+hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
+                                const int* counts, int nreq_grid, int grid, hipStream_t stream) {
     const int G = reslice_lanes(radius);
-#define B1(D) hipLaunchKernelGGL(k_reslice_r1_batch<D>, dim3(grid), dim3(256), 0, stream, reqs, units, nunits)
-#define B16(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 16>), dim3(grid), dim3(256), 0, stream, reqs, units, nunits)
-#define B64(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 64>), dim3(grid), dim3(256), 0, stream, reqs, units, nunits)
+#define B1(D) hipLaunchKernelGGL(k_reslice_r1_batch<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, units, counts)
+#define B16(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 16>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
+#define B64(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 64>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
     if (G == 1) {
+        hipLaunchKernelGGL(k_batch_setup, dim3(nreq_grid), dim3(64), 0, stream, reqs, setups, counts);
         DARE_DISPATCH_DT(dtype, B1)
     } else if (G == 16) {
         DARE_DISPATCH_DT(dtype, B16)

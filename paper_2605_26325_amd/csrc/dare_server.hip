@@ -1,0 +1,429 @@
+// Serving: continuous batching of reslice requests from many consoles.
+//
+// A scheduler thread turns the FIFO of waiting requests into ticks.  A tick
+// takes requests from the head of the queue while they fit its pixel and tile
+// budget and while a result slot of their size can be allocated in the
+// server's arena (the HBM budget); the head request waits until slots free up,
+// so admission is first come, first served.  Each tick goes to one of up to
+// four streams: its request table is uploaded from pinned staging, a captured
+// graph runs the batched reslice (per-request setup pre-pass + persistent tile
+// kernel), the results are copied to the callers' host buffers and an event
+// marks completion.  Ticks on different streams overlap on the device, and
+// requests that arrive meanwhile are admitted into the next tick whose stream
+// is free.
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "dare_alloc.h"
+#include "dare_internal.h"
+
+using namespace dare;
+
+namespace dare {
+// Views into the C ABI's volume (defined in dare_capi.hip).
+const VolDev* volume_device(const dare_volume* v);
+int volume_dtype(const dare_volume* v);
+int volume_radius(const dare_volume* v);
+int volume_device_id(const dare_volume* v);
+dare_status check_slice_spec(const dare_slice_spec* s);
+}  // namespace dare
+
+namespace {
+
+constexpr int kMaxStreams = 4;
+constexpr uint64_t kAlignS = 256;
+constexpr int kServerGrid = 2048;
+
+uint64_t aup(uint64_t x) { return (x + kAlignS - 1) / kAlignS * kAlignS; }
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t units_of(int radius, int W, int H) { return reslice_units(radius, W, H); }
+
+enum ReqState { kWaiting = 0, kInFlight = 1, kDone = 2, kFailed = 3 };
+
+struct Request {
+    int vol = 0;
+    dare_slice_spec spec{};
+    float* host_out = nullptr;
+    uint64_t out_off = UINT64_MAX;
+    uint64_t bytes = 0;
+    int64_t units = 0;
+    int state = kWaiting;
+    dare_request_times t{};
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_kernels = nullptr, ev_done = nullptr;
+    hipGraphExec_t graph = nullptr;
+    char* ws = nullptr;           // device workspace: counts, requests, units, setup records
+    char* staging = nullptr;      // pinned host copy of the uploaded part
+    bool busy = false;
+    bool kernels_seen = false;
+    std::vector<uint64_t> tickets;
+};
+
+}  // namespace
+
+struct dare_server {
+    dare_server_config cfg{};
+    int device = 0;
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    // workspace layout (identical in every slot, sized for a full tick)
+    uint64_t o_req = 0, o_units = 0, o_setup = 0, ws_bytes = 0;
+    int64_t max_units = 0;
+    Slot slots[kMaxStreams];
+    RangeAlloc outs;
+    std::vector<const dare_volume*> vols;
+    int dtype = -1, radius = -1;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Request> reqs;
+    uint64_t next_ticket = 1;
+    dare_server_stats stats{};
+    std::atomic<bool> stop{false};
+    std::thread th;
+    double busy_since = -1.0;
+    bool failed = false;
+};
+
+namespace {
+
+// Launch the tick's kernels on the slot's stream (captured once into a graph when enabled).
+hipError_t enqueue_kernels(dare_server* S, Slot& sl) {
+    return launch_reslice_batch(S->dtype, S->radius, (const BatchReq*)(sl.ws + S->o_req),
+                                (SliceSetup*)(sl.ws + S->o_setup), (const int2*)(sl.ws + S->o_units),
+                                (const int*)sl.ws, std::min(S->cfg.max_tick_requests, 1024),
+                                S->radius <= 1 ? kServerGrid : 4096, sl.stream);
+}
+
+hipError_t ensure_graph(dare_server* S, Slot& sl) {
+    if (!S->cfg.use_graphs || sl.graph) return hipSuccess;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue_kernels(S, sl);
+    e = hipStreamEndCapture(sl.stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+// Complete finished ticks.  Caller holds the lock.
+void reap(dare_server* S) {
+    for (int k = 0; k < S->cfg.n_streams; ++k) {
+        Slot& sl = S->slots[k];
+        if (!sl.busy) continue;
+        const double t = now_s();
+        if (!sl.kernels_seen && hipEventQuery(sl.ev_kernels) == hipSuccess) {
+            sl.kernels_seen = true;
+            for (uint64_t id : sl.tickets) S->reqs[id].t.t_device_done = t;
+        }
+        const hipError_t q = hipEventQuery(sl.ev_done);
+        if (q == hipErrorNotReady) continue;
+        const bool ok = q == hipSuccess;
+        for (uint64_t id : sl.tickets) {
+            Request& r = S->reqs[id];
+            if (r.t.t_device_done == 0.0) r.t.t_device_done = t;
+            r.t.t_host_done = t;
+            r.state = ok ? kDone : kFailed;
+            S->outs.release(r.out_off, r.bytes);
+            S->stats.completed += 1;
+            S->stats.pixels += (int64_t)r.spec.width * r.spec.height;
+        }
+        if (!ok) S->failed = true;
+        sl.tickets.clear();
+        sl.busy = false;
+    }
+}
+
+int busy_slots(dare_server* S) {
+    int n = 0;
+    for (int k = 0; k < S->cfg.n_streams; ++k) n += S->slots[k].busy;
+    return n;
+}
+
+// Form and launch one tick on a free slot.  Caller holds the lock.  Returns false when
+// nothing could be admitted.
+bool launch_tick(dare_server* S, Slot& sl) {
+    if (S->queue.empty()) return false;
+    const double t_admit = now_s();
+    int64_t pixels = 0, units = 0;
+    int nreq = 0;
+    std::vector<BatchReq> breqs;
+    std::vector<int2> bunits;
+    while (!S->queue.empty() && nreq < S->cfg.max_tick_requests) {
+        Request& r = S->reqs[S->queue.front()];
+        const int64_t px = (int64_t)r.spec.width * r.spec.height;
+        if (nreq > 0 && (pixels + px > S->cfg.max_tick_pixels || units + r.units > S->max_units)) break;
+        const uint64_t off = S->outs.alloc(r.bytes);
+        if (off == UINT64_MAX) break;          // the head waits for result slots to free up
+        r.out_off = off;
+        r.state = kInFlight;
+        r.t.t_admit = t_admit;
+        BatchReq q{};
+        q.vol = volume_device(S->vols[r.vol]);
+        q.s.sx = r.spec.pitch_mm[0];
+        q.s.sy = r.spec.pitch_mm[1];
+        memcpy(q.s.P, r.spec.probe_pose, sizeof(q.s.P));
+        q.s.W = r.spec.width;
+        q.s.H = r.spec.height;
+        q.s.tiles_x = (r.spec.width + kTile - 1) / kTile;
+        q.s.tiles = q.s.tiles_x * ((r.spec.height + kTile - 1) / kTile);
+        q.s.out = (float*)(S->arena + off);
+        breqs.push_back(q);
+        for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
+        sl.tickets.push_back(S->queue.front());
+        S->queue.pop_front();
+        pixels += px;
+        units += r.units;
+        ++nreq;
+    }
+    if (nreq == 0) return false;
+    const int counts[4] = {(int)units, nreq, 0, 0};
+    memcpy(sl.staging, counts, sizeof(counts));
+    memcpy(sl.staging + S->o_req, breqs.data(), breqs.size() * sizeof(BatchReq));
+    memcpy(sl.staging + S->o_units, bunits.data(), bunits.size() * sizeof(int2));
+    const uint64_t upload = S->o_units + bunits.size() * sizeof(int2);
+    hipError_t e = hipMemcpyAsync(sl.ws, sl.staging, upload, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess) e = S->cfg.use_graphs ? hipGraphLaunch(sl.graph, sl.stream) : enqueue_kernels(S, sl);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev_kernels, sl.stream);
+    for (size_t k = 0; e == hipSuccess && k < sl.tickets.size(); ++k) {
+        Request& r = S->reqs[sl.tickets[k]];
+        e = hipMemcpyAsync(r.host_out, S->arena + r.out_off, r.bytes, hipMemcpyDeviceToHost, sl.stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(sl.ev_done, sl.stream);
+    const double t_launch = now_s();
+    for (uint64_t id : sl.tickets) S->reqs[id].t.t_launch = t_launch;
+    sl.busy = true;
+    sl.kernels_seen = false;
+    S->stats.ticks += 1;
+    if (e != hipSuccess) {
+        // nothing reliable is in flight on this stream: fail the tick's requests now
+        (void)hipStreamSynchronize(sl.stream);
+        for (uint64_t id : sl.tickets) {
+            Request& r = S->reqs[id];
+            r.state = kFailed;
+            S->outs.release(r.out_off, r.bytes);
+        }
+        sl.tickets.clear();
+        sl.busy = false;
+        S->failed = true;
+    }
+    return true;
+}
+
+void scheduler(dare_server* S) {
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->stop.load()) {
+        reap(S);
+        for (int k = 0; k < S->cfg.n_streams; ++k) {
+            Slot& sl = S->slots[k];
+            if (sl.busy) continue;
+            if (!launch_tick(S, sl)) break;
+        }
+        const int busy = busy_slots(S);
+        const double t = now_s();
+        if (busy > 0 && S->busy_since < 0.0) S->busy_since = t;
+        if (busy == 0 && S->busy_since >= 0.0) {
+            S->stats.busy_seconds += t - S->busy_since;
+            S->busy_since = -1.0;
+        }
+        if (busy == 0 && S->queue.empty()) {
+            S->cv.wait_for(lk, std::chrono::milliseconds(50));
+        } else {
+            // ticks in flight: poll their events again shortly
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+double dare_now_seconds(void) { return now_s(); }
+
+void dare_default_server_config(dare_server_config* c) {
+    if (!c) return;
+    c->max_tick_pixels = 8 << 20;
+    c->max_tick_requests = 64;
+    c->n_streams = 3;
+    c->max_queue = 4096;
+    c->use_graphs = 1;
+}
+
+dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, uint64_t arena_bytes,
+                               dare_server** out) {
+    if (!cfg || !arena_dev || !out) return DARE_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->n_streams < 1 || cfg->n_streams > kMaxStreams || cfg->max_tick_requests < 1 ||
+        cfg->max_tick_requests > 4096 || cfg->max_tick_pixels < 1 || cfg->max_queue < 1)
+        return DARE_ERR_INVALID_ARG;
+    if (((uintptr_t)arena_dev % kAlignS) != 0) return DARE_ERR_INVALID_ARG;
+    dare_server* S = new dare_server();
+    S->cfg = *cfg;
+    S->arena = (char*)arena_dev;
+    S->arena_bytes = arena_bytes;
+    S->max_units = cfg->max_tick_pixels / 256 + 64 * (int64_t)cfg->max_tick_requests;
+    if (S->max_units > (1 << 28)) S->max_units = 1 << 28;
+    S->o_req = aup(4 * sizeof(int));
+    S->o_units = S->o_req + aup((uint64_t)cfg->max_tick_requests * sizeof(BatchReq));
+    S->o_setup = S->o_units + aup((uint64_t)S->max_units * sizeof(int2));
+    S->ws_bytes = S->o_setup + aup((uint64_t)cfg->max_tick_requests * sizeof(SliceSetup));
+    const uint64_t ws_total = S->ws_bytes * cfg->n_streams;
+    if (arena_bytes <= ws_total + kAlignS) {
+        delete S;
+        return DARE_ERR_INVALID_ARG;
+    }
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return DARE_ERR_HIP;
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < cfg->n_streams && e == hipSuccess; ++k) {
+        Slot& sl = S->slots[k];
+        sl.ws = S->arena + k * S->ws_bytes;
+        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_kernels, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&sl.staging, S->o_setup, hipHostMallocDefault);
+    }
+    if (e != hipSuccess) {
+        dare_server_destroy(S);
+        return DARE_ERR_HIP;
+    }
+    S->outs.reset(ws_total, arena_bytes - ws_total, kAlignS);
+    S->th = std::thread(scheduler, S);
+    *out = S;
+    return DARE_OK;
+}
+
+dare_status dare_server_add_volume(dare_server* S, const dare_volume* v, int32_t* volume_id) {
+    if (!S || !v || !volume_id) return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (volume_device_id(v) != S->device) return DARE_ERR_INVALID_ARG;
+    const int dt = volume_dtype(v), R = volume_radius(v);
+    if (S->dtype < 0) {
+        S->dtype = dt;
+        S->radius = R;
+        for (int k = 0; k < S->cfg.n_streams; ++k) {
+            if (ensure_graph(S, S->slots[k]) != hipSuccess) {
+                S->dtype = -1;
+                S->radius = -1;
+                return DARE_ERR_HIP;
+            }
+        }
+    } else if (dt != S->dtype || R != S->radius) {
+        return DARE_ERR_INVALID_ARG;   // one storage dtype and radius per server (one graph per stream)
+    }
+    S->vols.push_back(v);
+    *volume_id = (int32_t)S->vols.size() - 1;
+    return DARE_OK;
+}
+
+dare_status dare_server_submit(dare_server* S, int32_t volume_id, const dare_slice_spec* spec, float* host_out,
+                               uint64_t* ticket) {
+    if (!S || !host_out || !ticket) return DARE_ERR_INVALID_ARG;
+    const dare_status st = check_slice_spec(spec);
+    if (st != DARE_OK) return st;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
+    Request r;
+    r.vol = volume_id;
+    r.spec = *spec;
+    r.host_out = host_out;
+    r.bytes = (uint64_t)spec->width * spec->height * sizeof(float);
+    r.units = units_of(S->radius, spec->width, spec->height);
+    if (!S->outs.fits_ever(r.bytes) || r.units > S->max_units ||
+        (int64_t)spec->width * spec->height > S->cfg.max_tick_pixels)
+        return DARE_ERR_INVALID_ARG;
+    if ((int32_t)S->queue.size() >= S->cfg.max_queue) {
+        S->stats.rejected += 1;
+        return DARE_ERR_QUEUE_FULL;
+    }
+    r.t.t_submit = now_s();
+    const uint64_t id = S->next_ticket++;
+    S->reqs.emplace(id, r);
+    S->queue.push_back(id);
+    S->stats.submitted += 1;
+    *ticket = id;
+    S->cv.notify_one();
+    return DARE_OK;
+}
+
+dare_status dare_server_poll(dare_server* S, uint64_t ticket, dare_request_times* times) {
+    if (!S) return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return DARE_ERR_INVALID_ARG;
+    const int state = it->second.state;
+    if (state == kWaiting || state == kInFlight) return DARE_ERR_NOT_READY;
+    if (times) *times = it->second.t;
+    S->reqs.erase(it);
+    return state == kDone ? DARE_OK : DARE_ERR_HIP;
+}
+
+dare_status dare_server_drain(dare_server* S) {
+    if (!S) return DARE_ERR_INVALID_ARG;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->queue.empty() && busy_slots(S) == 0) return S->failed ? DARE_ERR_HIP : DARE_OK;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+dare_status dare_server_get_stats(dare_server* S, dare_server_stats* out) {
+    if (!S || !out) return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    if (S->busy_since >= 0.0) out->busy_seconds += now_s() - S->busy_since;
+    return DARE_OK;
+}
+
+dare_status dare_server_destroy(dare_server* S) {
+    if (!S) return DARE_ERR_INVALID_ARG;
+    if (S->th.joinable()) {
+        (void)dare_server_drain(S);
+        S->stop.store(true);
+        S->cv.notify_all();
+        S->th.join();
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kMaxStreams; ++k) {
+        Slot& sl = S->slots[k];
+        if (sl.stream) {
+            const hipError_t q = hipStreamSynchronize(sl.stream);
+            if (q != hipSuccess) e = q;
+        }
+        if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+        if (sl.ev_kernels) (void)hipEventDestroy(sl.ev_kernels);
+        if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.staging) (void)hipHostFree(sl.staging);
+    }
+    delete S;
+    return e == hipSuccess ? DARE_OK : DARE_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+"""GPU tests of the serving form: continuous batching through the C ABI.
+
+Every request served inside a mix of requests (other consoles, sizes, poses,
+volumes) must equal the same request resliced alone with dare_reslice, bit for
+bit; a small result budget forces admission queueing without losing or
+duplicating requests.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import make_volume, note, oracle_grid, upload_grid
+from oracle.reslice import Params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2605_26325_amd as dare
+    wl = synth.config1()
+    wl.render("cpu")
+    g = oracle_grid(wl, wl.frames.numpy(), Params())
+    vols = []
+    for dt in ("bf16", "bf16"):
+        v = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params(), dtype=dt)
+        upload_grid(v, g.S, g.C, *g.codebook.arrays())
+        vols.append(v)
+    return dare, torch, wl, vols
+
+
+def _requests(wl, n, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(128, 128, (0.25, 0.25)), (37, 23, (0.6, 0.7)), (200, 90, (0.16, 0.3)), (64, 65, (0.5, 0.5)),
+             (16, 16, (1.0, 1.0)), (96, 160, (0.3, 0.2))]
+    out = []
+    for k in range(n):
+        W, H, pitch = sizes[int(rng.integers(len(sizes)))]
+        P = wl.slices.probe_poses[int(rng.integers(len(wl.slices.probe_poses)))]
+        out.append((int(rng.integers(2)), P, W, H, pitch))
+    return out
+
+
+def _alone(dare, torch, vols, reqs):
+    res = []
+    for vi, P, W, H, pitch in reqs:
+        o = torch.full((H, W), -3.0, device="cuda")
+        dare.dare_reslice(vols[vi], dare.make_spec(P, W, H, pitch), o)
+        res.append(o)
+    torch.cuda.synchronize()
+    return [r.cpu().numpy() for r in res]
+
+
+def _serve(dare, torch, vols, reqs, arena_bytes, **cfg):
+    srv = dare.Server(arena_bytes, **cfg)
+    ids = [srv.add_volume(v) for v in vols]
+    outs = [torch.full((H, W), -5.0, dtype=torch.float32, pin_memory=True) for (_, _, W, H, _) in reqs]
+    tickets = []
+    for (vi, P, W, H, pitch), o in zip(reqs, outs):
+        t = None
+        while t is None:                 # queue full: wait for the scheduler to admit some
+            t = srv.submit(ids[vi], P, W, H, pitch, o)
+        tickets.append(t)
+    srv.drain()
+    times = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    return [o.numpy() for o in outs], times, st
+
+
+@pytest.mark.parametrize("graphs,streams", [(1, 3), (0, 2), (1, 1)])
+def test_served_equals_alone(env, graphs, streams):
+    dare, torch, wl, vols = env
+    note(f"server graphs={graphs} streams={streams}")
+    reqs = _requests(wl, 48, seed=streams + 10 * graphs)
+    ref = _alone(dare, torch, vols, reqs)
+    got, times, st = _serve(dare, torch, vols, reqs, 64 << 20, use_graphs=graphs, n_streams=streams,
+                            max_tick_requests=8)
+    for k in range(len(reqs)):
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    assert all(t is not None for t in times)
+    for t in times:
+        assert t.t_submit <= t.t_admit <= t.t_launch <= t.t_host_done
+    assert st.completed == len(reqs) and st.submitted == len(reqs) and st.ticks >= len(reqs) // 8
+
+
+def test_small_budget_queues_and_completes(env):
+    dare, torch, wl, vols = env
+    note("server with room for about two results at a time")
+    reqs = _requests(wl, 30, seed=99)
+    ref = _alone(dare, torch, vols, reqs)
+    cfg = dict(n_streams=2, max_tick_requests=4, max_tick_pixels=1 << 16, max_queue=64)
+    largest = max(W * H for (_, _, W, H, _) in reqs) * 4
+    arena = _table_bytes(dare, cfg) + 2 * largest + 4096
+    got, times, st = _serve(dare, torch, vols, reqs, arena, **cfg)
+    for k in range(len(reqs)):
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    total = sum(W * H * 4 for (_, _, W, H, _) in reqs)
+    n_done, n_ticks = int(st.completed), int(st.ticks)
+    assert n_done == len(reqs)
+    # no more than the result budget can be in flight: at least total / budget ticks
+    assert n_ticks >= total // (2 * largest + 4096), (n_ticks, total, largest)
+
+
+def _table_bytes(dare, cfg):
+    """Smallest arena that the server accepts, found by bisection on creation."""
+    lo, hi = 1 << 12, 1 << 28
+    while lo < hi:
+        mid = (lo + hi) // 2
+        try:
+            s = dare.Server(mid, **cfg)
+            s.close()
+            hi = mid
+        except dare.DareError:
+            lo = mid + 1
+    return lo
+
+
+def test_submit_rejects_what_can_never_fit(env):
+    dare, torch, wl, vols = env
+    note("server rejects oversized requests")
+    cfg = dict(n_streams=1, max_tick_requests=2, max_tick_pixels=4096)
+    srv = dare.Server(_table_bytes(dare, cfg) + 64 * 64 * 4 + 1024, **cfg)
+    vid = srv.add_volume(vols[0])
+    big = torch.empty((128, 128), dtype=torch.float32, pin_memory=True)
+    with pytest.raises(dare.DareError) as e:
+        srv.submit(vid, wl.slices.probe_poses[0], 128, 128, (0.25, 0.25), big)
+    assert e.value.status == dare.ERR_INVALID_ARG
+    ok = torch.empty((32, 32), dtype=torch.float32, pin_memory=True)
+    t = srv.submit(vid, wl.slices.probe_poses[0], 32, 32, (1.0, 1.0), ok)
+    srv.drain()
+    assert srv.poll(t) is not None
+    # a second volume with another storage dtype cannot join this server
+    other = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params(), dtype="f32")
+    with pytest.raises(dare.DareError):
+        srv.add_volume(other)
+    srv.close()
