@@ -30,7 +30,7 @@ struct dare_volume {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kBatchGrid = 2048;   // workgroups of the batched radius-1 kernel (persistent)
+constexpr int kBatchGrid = 2048;   // workgroups of each batched pass (grid-stride)
 
 struct DeviceGuard {
     int prev = -1;
@@ -186,6 +186,82 @@ int volume_dtype(const dare_volume* v) { return v->dtype; }
 int volume_radius(const dare_volume* v) { return (int)v->p.radius_vox; }
 int volume_device_id(const dare_volume* v) { return v->device; }
 dare_status check_slice_spec(const dare_slice_spec* s) { return check_spec(s); }
+}  // namespace dare
+
+namespace {
+
+struct Group {
+    std::vector<BatchReq> reqs;
+    std::vector<int2> units;
+    int64_t vox = 0, pix = 0;     // flat totals (radius 1)
+};
+
+// Batch workspace of one launch group: [header] [requests] [units] [setup records] [slabs].
+// Header, requests and units are uploaded; setup records and slabs are written on the device.
+struct GroupLayout {
+    uint64_t o_req, o_units, o_setup, o_slab, upload, total;
+};
+
+GroupLayout group_layout(size_t nreq, size_t nunits, int64_t slab_floats_total) {
+    GroupLayout L;
+    L.o_req = align_up(sizeof(BatchHeader));
+    L.o_units = L.o_req + align_up(nreq * sizeof(BatchReq));
+    L.o_setup = L.o_units + align_up(nunits * sizeof(int2));
+    L.upload = L.o_setup;
+    L.o_slab = L.o_setup + align_up(nreq * sizeof(SliceSetup));
+    L.total = L.o_slab + align_up((uint64_t)slab_floats_total * sizeof(float));
+    return L;
+}
+
+struct GroupSize {
+    size_t nreq = 0, nunits = 0;
+    int64_t slab = 0;
+};
+
+std::map<std::pair<int, int>, GroupSize> group_sizes(const dare_volume* const* vols, const dare_slice_spec* specs,
+                                                     int32_t n) {
+    std::map<std::pair<int, int>, GroupSize> cnt;
+    for (int k = 0; k < n; ++k) {
+        const int R = (int)vols[k]->p.radius_vox;
+        GroupSize& c = cnt[{vols[k]->dtype, R}];
+        c.nreq += 1;
+        if (R <= 1) c.slab += slab_floats(vols[k], specs + k);
+        else c.nunits += (size_t)reslice_units(R, specs[k].width, specs[k].height);
+    }
+    return cnt;
+}
+
+}  // namespace
+
+namespace dare {
+
+int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec) {
+    double T[16];
+    compose_host(spec->probe_pose, v->g.calib, T);
+    const int W = spec->width, H = spec->height;
+    const double sx = spec->pitch_mm[0], sy = spec->pitch_mm[1], inv_h = 1.0 / v->g.spacing_mm;
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < 4; ++k) {
+        const double is = (double)((k & 1) ? W - 1 : 0) * sx, js = (double)((k & 2) ? H - 1 : 0) * sy;
+        for (int a = 0; a < 3; ++a) {
+            const double c = (((T[a * 4 + 3] + is * T[a * 4 + 0]) + js * T[a * 4 + 1]) - v->g.origin_mm[a]) * inv_h;
+            mn[a] = std::min(mn[a], c);
+            mx[a] = std::max(mx[a], c);
+        }
+    }
+    int64_t d[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(mn[a]) || !std::isfinite(mx[a])) return 0;
+        const double lo = std::max(floor(mn[a]) - 2.0, 0.0);
+        const double hi = std::min(floor(mx[a]) + 3.0, (double)v->g.dims[a] - 1.0);
+        if (lo > hi) return 0;
+        d[a] = (int64_t)(hi - lo) + 1;
+    }
+    const int64_t cols = std::max(d[0] * d[1], std::max(d[0] * d[2], d[1] * d[2]));
+    const int64_t cap = std::min(cols * kSlabDepthMax, (int64_t)kSlabPerPixel * W * H);
+    return (cap + 63) / 64 * 64;
+}
+
 }  // namespace dare
 
 extern "C" {
@@ -352,45 +428,15 @@ dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, floa
     return hip_status(launch_reslice(v->dev, v->dtype, (int)v->p.radius_vox, a, (hipStream_t)stream));
 }
 
-namespace {
 
-struct Group {
-    std::vector<BatchReq> reqs;
-    std::vector<int2> units;
-};
-
-// Batch workspace of one launch group: [counts: units, requests] [requests] [units] [setup records].
-// The first three parts are uploaded; the setup records are written by the device pre-pass.
-struct GroupLayout {
-    uint64_t o_req, o_units, o_setup, upload, total;
-};
-
-GroupLayout group_layout(size_t nreq, size_t nunits) {
-    GroupLayout L;
-    L.o_req = align_up(4 * sizeof(int));
-    L.o_units = L.o_req + align_up(nreq * sizeof(BatchReq));
-    L.o_setup = L.o_units + align_up(nunits * sizeof(int2));
-    L.upload = L.o_setup;
-    L.total = L.o_setup + align_up(nreq * sizeof(SliceSetup));
-    return L;
-}
-
-uint64_t group_bytes(size_t nreq, size_t nunits) { return group_layout(nreq, nunits).total; }
-
-}  // namespace
 
 uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, const dare_slice_spec* specs, int32_t n) {
     if (!vols || !specs || n <= 0) return 0;
-    std::map<std::pair<int, int>, std::pair<size_t, size_t>> cnt;
-    for (int k = 0; k < n; ++k) {
-        if (!vols[k]) return 0;
-        const int R = (int)vols[k]->p.radius_vox;
-        auto& c = cnt[{vols[k]->dtype, R}];
-        c.first += 1;
-        c.second += (size_t)reslice_units(R, specs[k].width, specs[k].height);
-    }
+    for (int k = 0; k < n; ++k)
+        if (!vols[k] || check_spec(specs + k) != DARE_OK) return 0;
     uint64_t total = 0;
-    for (auto& kv : cnt) total += group_bytes(kv.second.first, kv.second.second);
+    for (auto& kv : group_sizes(vols, specs, n))
+        total += group_layout(kv.second.nreq, kv.second.nunits, kv.second.slab).total;
     return total;
 }
 
@@ -416,30 +462,43 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         const int R = (int)vols[k]->p.radius_vox;
         Group& g = groups[{vols[k]->dtype, R}];
         const int r = (int)g.reqs.size();
-        BatchReq q;
+        BatchReq q{};
         q.vol = vols[k]->dev;
         q.s = make_args(specs + k, outs_dev[k]);
+        if (R <= 1) {
+            q.v_cap = slab_floats(vols[k], specs + k);
+            q.v_beg = g.vox;
+            q.v_off = g.vox;
+            q.p_beg = g.pix;
+            g.vox += q.v_cap;
+            g.pix += (int64_t)specs[k].width * specs[k].height;
+        } else {
+            const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
+            for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
+        }
         g.reqs.push_back(q);
-        const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
-        for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
     }
     char* ws = (char*)workspace_dev;
     for (auto& kv : groups) {
         Group& g = kv.second;
         const int nunits = (int)g.units.size();
         const int nreq = (int)g.reqs.size();
-        const GroupLayout L = group_layout(g.reqs.size(), g.units.size());
+        const GroupLayout L = group_layout(g.reqs.size(), g.units.size(), g.vox);
         std::vector<char> host(L.upload, 0);
-        const int counts[4] = {nunits, nreq, 0, 0};
-        memcpy(host.data(), counts, sizeof(counts));
+        BatchHeader hd{};
+        hd.counts[0] = nunits;
+        hd.counts[1] = nreq;
+        hd.totals[0] = g.vox;
+        hd.totals[1] = g.pix;
+        memcpy(host.data(), &hd, sizeof(hd));
         memcpy(host.data() + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
-        memcpy(host.data() + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
+        if (nunits) memcpy(host.data() + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
         HIP_TRY(hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream));
         const int R = kv.first.second;
-        const int grid = R <= 1 ? std::min(nunits, kBatchGrid) : std::min(nunits, 65535);
+        const int grid = R <= 1 ? kBatchGrid : std::min(nunits, 65535);
         HIP_TRY(launch_reslice_batch(kv.first.first, R, (const BatchReq*)(ws + L.o_req), (SliceSetup*)(ws + L.o_setup),
-                                     (const int2*)(ws + L.o_units), (const int*)ws, std::min(nreq, 1024), grid,
-                                     stream));
+                                     (const int2*)(ws + L.o_units), (const int*)ws, (float*)(ws + L.o_slab),
+                                     std::min(nreq, 1024), grid, stream));
         ws += L.total;
     }
     return DARE_OK;

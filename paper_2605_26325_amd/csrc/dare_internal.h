@@ -89,7 +89,22 @@ struct SliceArgs {                        // one reslice request, by value
 struct BatchReq {
     const VolDev* vol;
     SliceArgs s;
+    // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
+    // (v_beg: first index of this request's slab) and their pixels (p_beg).  The slab
+    // itself lives at float offset v_off of the scratch; v_cap floats, 0 for none.
+    int64_t v_beg, v_off, v_cap;
+    int64_t p_beg;
 };
+
+// Batch header at the start of a workspace: int32 {units, requests, 0, 0}, then int64
+// {slab index total, pixel total}.
+struct BatchHeader {
+    int32_t counts[4];
+    int64_t totals[2];
+};
+
+constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
+constexpr int kSlabPerPixel = 12;         // slab floats per output pixel beyond which pixels gather directly
 
 // Per-request reslice setup: composed pose, surviving bins and their Eq. 2
 // weights, and the plane frame used by the footprint tests.
@@ -101,6 +116,16 @@ struct SliceSetup {
     int kact;                             // surviving bins
     int act_bin[kMaxBins];
     float act_w[kMaxBins];
+    // slab of the whole slice (batched passes): voxels within the trilinear support of the
+    // plane, enumerated as runs of `depth` voxels along the dominant axis, one run per column
+    // of the other two axes (pax fastest) over the slice's bounding box
+    int pax, qax;
+    int lo_p, lo_q, dim_p, dim_q;
+    int depth;
+    int ncand;                            // dim_p * dim_q * depth, 0 when nothing to stage
+    int staged;                           // 1: slab staged; 0: gather per pixel
+    float c0[3];                          // voxel coordinates of pixel (0, 0)
+    float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
 };
 
 inline int pair_bytes(int dtype) {
@@ -136,7 +161,11 @@ hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float*
                                    int nz, hipStream_t stream);
 hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream);
 hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, int nreq_grid, int grid, hipStream_t stream);
+                                const int* counts, float* scratch, int nreq_grid, int grid, hipStream_t stream);
+// Slab floats to reserve for a radius-1 request (0 when its pixels should gather directly):
+// the slice's voxel bounding box, two voxels of margin, over the largest pair of axes,
+// times the deepest run, capped at kSlabPerPixel per pixel.  Defined with the C ABI.
+int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec);
 hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream);
 
 // Reslice work decomposition: lanes per output pixel (1 for radius 1) and the

@@ -280,8 +280,10 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
     tl.nlist = 0;
 }
 
-// Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).
-template <int DT>
+// Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).  UNI: the
+// whole wavefront works on one request, so bin ids and weights are broadcast as scalars;
+// the flat batched pass mixes requests within a wavefront and loads them per lane.
+template <int DT, bool UNI = true>
 __device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, const SetupLds& sh, int kact,
                                               const double c[3]) {
     using PT = Pair<DT>;
@@ -315,8 +317,9 @@ __device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, con
 #pragma unroll
     for (int k = 0; k < 8; ++k) { A[k] = 0.0f; B[k] = 0.0f; }
     for (int k = 0; k < kact; ++k) {
-        const int b = uniform_i32(sh.act_bin[k]);
-        const float wgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k])));
+        const int b = UNI ? uniform_i32(sh.act_bin[k]) : sh.act_bin[k];
+        const float wgt = UNI ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k])))
+                              : sh.act_w[k];
         const int32_t* __restrict__ tab = vd->table + (int64_t)b * nbricks;
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
@@ -331,10 +334,15 @@ __device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, con
                     if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
                     float a, cnt;
                     PT::decode(data[(size_t)slot * kBrickVox + (rowl[dz][dy] | lx[dx])], sc, a, cnt);
-                    const float wc = wgt * cnt;
                     const int v = (dz << 2) | (dy << 1) | dx;
-                    A[v] = __builtin_fmaf(wc, a, A[v]);
-                    B[v] = B[v] + wc;
+                    if (kact == 1) {              // a single direction: its weight cancels, V = a
+                        A[v] = a;
+                        B[v] = cnt;
+                    } else {
+                        const float wc = wgt * cnt;
+                        A[v] = __builtin_fmaf(wc, a, A[v]);
+                        B[v] = B[v] + wc;
+                    }
                 }
     }
     float num = 0.0f, den = 0.0f;
@@ -345,9 +353,9 @@ __device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, con
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
                 const int v = (dz << 2) | (dy << 1) | dx;
-                if (B[v] > 0.0f) {
-                    const float t = (wx[dx] * wy[dy]) * wz[dz];
-                    num = __builtin_fmaf(t, A[v] / B[v], num);
+                const float t = (wx[dx] * wy[dy]) * wz[dz];
+                if (B[v] > 0.0f && t > 0.0f) {
+                    num = __builtin_fmaf(t, kact == 1 ? A[v] : A[v] / B[v], num);
                     den = den + t;
                 }
             }
@@ -620,46 +628,274 @@ __global__ void __launch_bounds__(256) k_reslice_rn(const VolDev* __restrict__ v
     reslice_unit_rn<DT, G>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh);
 }
 
-// Batched form.  A pre-pass composes every request's pose and evaluates its
-// gates and weights once (one wave per request); the tile kernel then walks a
-// table of (request, unit) pairs.  Each workgroup takes a contiguous run of the
-// table, so consecutive units mostly share a request and its setup record is
-// copied into LDS only when the request changes.  Counts are read from device
-// memory so a fixed grid serves any batch (graph replay).
+// ---------------------------------------------------------------- batched passes (radius 1)
+//
+// A batch runs as three flat passes with no workgroup barriers:
+//   setup  one wave per request: pose, Eq. 1 / gates / Eq. 2, plane frame and the
+//          slab of the slice (the voxels within the trilinear support of the plane
+//          over the slice's bounding box, as runs along the normal's dominant axis);
+//   voxel  one thread per slab candidate: all surviving bins gathered at once and
+//          blended into V_v, written to the request's slab in the workspace;
+//   pixel  one thread per output pixel: FP64 position, the 8 cell values from the
+//          slab (mostly L2 hits), tent blend.
+// The per-voxel and per-pixel arithmetic and its order are those of the fused
+// kernel, so a batched request equals the same request resliced alone.
+
+// First voxel of the slab run of column (vp, vq): one below the slab or the grid floor.
+__device__ __forceinline__ int run_start(const SliceSetup& su, int vp, int vq) {
+    const float centre = su.c0[su.dax] - (su.fm[su.pax] * ((float)vp - su.c0[su.pax]) +
+                                          su.fm[su.qax] * ((float)vq - su.c0[su.qax])) * su.inv_md;
+    return max((int)floorf(centre - su.half), 0);
+}
+
+// Wave 0: the slab of the whole slice.  Lanes 0..3 place its corner pixels.
+__device__ __forceinline__ void slab_setup(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                           int kact, int64_t v_cap, SliceSetup& su) {
+    const int lane = threadIdx.x;
+    SlicePos q;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.t[a] = T[a * 4 + 3];
+        q.e0[a] = T[a * 4 + 0];
+        q.e1[a] = T[a * 4 + 1];
+        q.o[a] = vd->origin[a];
+    }
+    q.inv_h = vd->inv_h;
+    q.sx = s.sx;
+    q.sy = s.sy;
+    const int k = lane & 3;
+    double c[3];
+    pixel_coords(q, (k & 1) ? s.W - 1 : 0, (k & 2) ? s.H - 1 : 0, c);
+    int lo[3], hi[3];
+    const int n[3] = {vd->nx, vd->ny, vd->nz};
+    float c0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int f = (int)fmin(fmax(floor(c[a]), -1048576.0), 1048576.0);
+        int mn = f, mx = f;
+#pragma unroll
+        for (int o = 1; o < 4; ++o) {
+            const int g = __shfl(f, o, 4);
+            mn = min(mn, g);
+            mx = max(mx, g);
+        }
+        lo[a] = max(mn - 1, 0);
+        hi[a] = min(mx + 2, n[a] - 1);
+        c0[a] = (float)__shfl(c[a], 0, 4);
+    }
+    if (lane != 0) return;
+    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
+    bool empty = false;
+    for (int a = 0; a < 3; ++a) {
+        empty = empty || lo[a] > hi[a];
+        l1m += fabsf(su.fm[a]);
+        l1u += fabsf(su.fu[a]);
+        l1w += fabsf(su.fw[a]);
+        su.c0[a] = c0[a];
+    }
+    const int dax = su.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    su.pax = pax;
+    su.qax = qax;
+    su.lo_p = lo[pax];
+    su.lo_q = lo[qax];
+    su.dim_p = empty ? 0 : hi[pax] - lo[pax] + 1;
+    su.dim_q = empty ? 0 : hi[qax] - lo[qax] + 1;
+    su.len_u = (float)(s.W - 1) * su.lu;
+    su.len_v = (float)(s.H - 1) * su.lw;
+    // FP32 rounding of the tests grows with the coordinates' magnitude
+    const float span = fmaxf(fmaxf(fabsf(c0[0]), fabsf(c0[1])), fabsf(c0[2])) + su.len_u + su.len_v;
+    const float slop = 2e-3f + 1e-6f * span;
+    su.thr_n = l1m + slop;
+    su.thr_u = l1u + 0.02f + slop;
+    su.thr_v = l1w + 0.02f + slop;
+    su.inv_md = 1.0f / su.fm[dax];
+    su.half = su.thr_n * fabsf(su.inv_md);
+    const float dep = ceilf(2.0f * su.half) + 2.0f;
+    su.depth = dep <= (float)kSlabDepthMax ? (int)dep : kSlabDepthMax + 1;
+    const int64_t ncand = (int64_t)su.dim_p * su.dim_q * su.depth;
+    su.staged = (su.depth <= kSlabDepthMax && ncand <= v_cap) ? 1 : 0;
+    su.ncand = (kact > 0 && su.staged) ? (int)ncand : 0;
+}
+
 __global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__ reqs, SliceSetup* __restrict__ setups,
                                                      const int* __restrict__ counts) {
     const int nreq = counts[1];
     for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
         double T[12];
-        slice_setup(reqs[r].vol, reqs[r].s, setups[r], T);
+        const int ka = slice_setup(reqs[r].vol, reqs[r].s, setups[r], T);
+        slab_setup(reqs[r].vol, reqs[r].s, T, ka, reqs[r].v_cap, setups[r]);
+    }
+}
+
+// V_v of voxel (vx, vy, vz) over the surviving bins, straight from the brick pool.
+template <int DT>
+__device__ __forceinline__ float blend_at(const VolDev* __restrict__ vd, const SliceSetup& su, int kact, int vx, int vy,
+                                          int vz) {
+    using PT = Pair<DT>;
+    const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
+    const int64_t nbricks = vd->nbricks;
+    const int64_t brick = ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
+    const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+    if (kact == 1) {
+        const int slot = vd->table[(int64_t)su.act_bin[0] * nbricks + brick];
+        if (slot < 0) return __builtin_nanf("");
+        float2 sc = make_float2(0.0f, 0.0f);
+        if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
+        float a, cnt;
+        PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
+        return cnt > 0.0f ? a : __builtin_nanf("");
+    }
+    float A = 0.0f, B = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += kBinChunk) {
+        int sl[kBinChunk];
+        typename PT::T pr[kBinChunk];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u)
+            sl[u] = (k0 + u < kact) ? vd->table[(int64_t)su.act_bin[k0 + u] * nbricks + brick] : -1;
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u)
+            if (sl[u] >= 0) pr[u] = data[(size_t)sl[u] * kBrickVox + local];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u) {
+            if (sl[u] < 0) continue;
+            float2 sc = make_float2(0.0f, 0.0f);
+            if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[sl[u]];
+            float a, cnt;
+            PT::decode(pr[u], sc, a, cnt);
+            const float wc = su.act_w[k0 + u] * cnt;
+            A = __builtin_fmaf(wc, a, A);
+            B = B + wc;
+        }
+    }
+    return B > 0.0f ? A / B : __builtin_nanf("");
+}
+
+// Request owning flat index g: the last r with begin(r) <= g (begins ascending from 0).
+template <bool VOX>
+__device__ __forceinline__ int find_req(const BatchReq* __restrict__ reqs, int nreq, int64_t g) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t b = VOX ? reqs[mid].v_beg : reqs[mid].p_beg;
+        if (b <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t batch_total(const int* counts, int k) {
+    return reinterpret_cast<const int64_t*>(counts + 4)[k];
+}
+
+template <int DT>
+__global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__ reqs,
+                                                    const SliceSetup* __restrict__ setups, float* __restrict__ scratch,
+                                                    const int* __restrict__ counts) {
+    const int nreq = counts[1];
+    const int64_t total = batch_total(counts, 0);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        const int r = find_req<true>(reqs, nreq, g);
+        const SliceSetup& su = setups[r];
+        const int64_t e64 = g - reqs[r].v_beg;
+        if (e64 >= su.ncand) continue;
+        const int e = (int)e64;
+        const VolDev* __restrict__ vd = reqs[r].vol;
+        const int dax = su.dax, pax = su.pax;
+        const int dim_p = su.dim_p, ncols = su.dim_p * su.dim_q;
+        const int nd = dax == 0 ? vd->nx : (dax == 1 ? vd->ny : vd->nz);
+        const int col = e % ncols, k = e / ncols;
+        const int vp = su.lo_p + col % dim_p, vq = su.lo_q + col / dim_p;
+        const int vdd = run_start(su, vp, vq) + k;
+        float V = __builtin_nanf("");
+        if (vdd < nd) {
+            const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
+            const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
+            const int vz = dax == 2 ? vdd : (pax == 2 ? vp : vq);
+            const float d0 = (float)vx - su.c0[0], d1 = (float)vy - su.c0[1], d2 = (float)vz - su.c0[2];
+            const float dn = su.fm[0] * d0 + su.fm[1] * d1 + su.fm[2] * d2;
+            const float du = su.fu[0] * d0 + su.fu[1] * d1 + su.fu[2] * d2;
+            const float dv = su.fw[0] * d0 + su.fw[1] * d1 + su.fw[2] * d2;
+            if (fabsf(dn) < su.thr_n && du > -su.thr_u && du < su.len_u + su.thr_u && dv > -su.thr_v &&
+                dv < su.len_v + su.thr_v)
+                V = blend_at<DT>(vd, su, su.kact, vx, vy, vz);
+        }
+        scratch[reqs[r].v_off + e] = V;
     }
 }
 
 template <int DT>
-__global__ void __launch_bounds__(256) k_reslice_r1_batch(const BatchReq* __restrict__ reqs,
-                                                          const SliceSetup* __restrict__ setups,
-                                                          const int2* __restrict__ units,
-                                                          const int* __restrict__ counts) {
-    __shared__ SetupLds sh;
-    __shared__ TileLds<DT> tl;
-    const int n = counts[0];
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int u0 = xcd_remap(blockIdx.x, gridDim.x) * per;
-    const int u1 = min(n, u0 + per);
-    int cur = -1;
-    for (int u = u0; u < u1; ++u) {
-        const int r = __builtin_amdgcn_readfirstlane(units[u].x);
-        const int t = __builtin_amdgcn_readfirstlane(units[u].y);
-        if (r != cur) {
-            const int* src = (const int*)(setups + r);
-            int* dst = (int*)&sh;
-            for (int k = threadIdx.x; k < (int)(sizeof(SliceSetup) / 4); k += blockDim.x) dst[k] = src[k];
-            cur = r;
-            __syncthreads();
-        }
+__global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__ reqs,
+                                                    const SliceSetup* __restrict__ setups,
+                                                    const float* __restrict__ scratch, const int* __restrict__ counts) {
+    const int nreq = counts[1];
+    const int64_t total = batch_total(counts, 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        const int r = find_req<false>(reqs, nreq, g);
         const BatchReq& rq = reqs[r];
-        reslice_tile_r1<DT>(rq.vol, rq.s, t, sh, tl, true);
-        __syncthreads();
+        const SliceSetup& su = setups[r];
+        const VolDev* __restrict__ vd = rq.vol;
+        const int W = rq.s.W;
+        const int64_t p = g - rq.p_beg;
+        const int i = (int)(p % W), j = (int)(p / W);
+        float* out = rq.s.out + p;
+        const int kact = su.kact;
+        SlicePos q;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q.t[a] = su.T[a * 4 + 3];
+            q.e0[a] = su.T[a * 4 + 0];
+            q.e1[a] = su.T[a * 4 + 1];
+            q.o[a] = vd->origin[a];
+        }
+        q.inv_h = vd->inv_h;
+        q.sx = rq.s.sx;
+        q.sy = rq.s.sy;
+        const int n[3] = {vd->nx, vd->ny, vd->nz};
+        double c[3];
+        pixel_coords(q, i, j, c);
+        if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
+                           c[2] >= -1.0 && c[2] < (double)n[2])) {
+            *out = __builtin_nanf("");
+            continue;
+        }
+        if (!su.staged) {
+            *out = pixel_direct<DT, false>(vd, su, kact, c);
+            continue;
+        }
+        const float* __restrict__ slab = scratch + rq.v_off;
+        const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
+        const int b0[3] = {(int)f0, (int)f1, (int)f2};
+        const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
+        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+        const int pax = su.pax, qax = su.qax, dax = su.dax;
+        const int dim_p = su.dim_p, dim_q = su.dim_q, depth = su.depth, ncols = dim_p * dim_q;
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int ddz = 0; ddz < 2; ++ddz)
+#pragma unroll
+            for (int ddy = 0; ddy < 2; ++ddy)
+#pragma unroll
+                for (int ddx = 0; ddx < 2; ++ddx) {
+                    const float t = (wx[ddx] * wy[ddy]) * wz[ddz];
+                    if (!(t > 0.0f)) continue;
+                    const int v[3] = {b0[0] + ddx, b0[1] + ddy, b0[2] + ddz};
+                    if ((unsigned)v[0] >= (unsigned)n[0] || (unsigned)v[1] >= (unsigned)n[1] ||
+                        (unsigned)v[2] >= (unsigned)n[2])
+                        continue;
+                    const int vp = v[pax], vq = v[qax];
+                    const int cp = vp - su.lo_p, cq = vq - su.lo_q;
+                    const int kk = v[dax] - run_start(su, vp, vq);
+                    if ((unsigned)cp >= (unsigned)dim_p || (unsigned)cq >= (unsigned)dim_q ||
+                        (unsigned)kk >= (unsigned)depth)
+                        continue;   // unreachable: every cell voxel with weight lies in the slab
+                    const float V = slab[(int64_t)kk * ncols + cq * dim_p + cp];
+                    if (V == V) {
+                        num = __builtin_fmaf(t, V, num);
+                        den = den + t;
+                    }
+                }
+        *out = den > 0.0f ? num / den : __builtin_nanf("");
     }
 }
 
@@ -718,20 +954,23 @@ hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceAr
 }
 
 hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, int nreq_grid, int grid, hipStream_t stream) {
+                                const int* counts, float* scratch, int nreq_grid, int grid, hipStream_t stream) {
     const int G = reslice_lanes(radius);
-#define B1(D) hipLaunchKernelGGL(k_reslice_r1_batch<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, units, counts)
+#define V1(D) hipLaunchKernelGGL(k_voxel_pass<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, scratch, counts)
+#define P1(D) hipLaunchKernelGGL(k_pixel_pass<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, scratch, counts)
 #define B16(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 16>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
 #define B64(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 64>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
     if (G == 1) {
         hipLaunchKernelGGL(k_batch_setup, dim3(nreq_grid), dim3(64), 0, stream, reqs, setups, counts);
-        DARE_DISPATCH_DT(dtype, B1)
+        DARE_DISPATCH_DT(dtype, V1)
+        DARE_DISPATCH_DT(dtype, P1)
     } else if (G == 16) {
         DARE_DISPATCH_DT(dtype, B16)
     } else {
         DARE_DISPATCH_DT(dtype, B64)
     }
-#undef B1
+#undef V1
+#undef P1
 #undef B16
 #undef B64
     return hipGetLastError();

@@ -49,7 +49,8 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-int64_t units_of(int radius, int W, int H) { return reslice_units(radius, W, H); }
+// Workgroup units of a request: the radius-1 passes index pixels and slabs directly.
+int64_t units_of(int radius, int W, int H) { return radius <= 1 ? 0 : reslice_units(radius, W, H); }
 
 enum ReqState { kWaiting = 0, kInFlight = 1, kDone = 2, kFailed = 3 };
 
@@ -60,6 +61,8 @@ struct Request {
     uint64_t out_off = UINT64_MAX;
     uint64_t bytes = 0;
     int64_t units = 0;
+    int64_t slab = 0;                 // slab floats wanted (radius 1); granted only if the arena has room
+    uint64_t slab_off = UINT64_MAX;
     int state = kWaiting;
     dare_request_times t{};
 };
@@ -68,7 +71,7 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev_kernels = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
-    char* ws = nullptr;           // device workspace: counts, requests, units, setup records
+    char* ws = nullptr;           // device workspace: header, requests, units, setup records
     char* staging = nullptr;      // pinned host copy of the uploaded part
     bool busy = false;
     bool kernels_seen = false;
@@ -107,7 +110,7 @@ namespace {
 hipError_t enqueue_kernels(dare_server* S, Slot& sl) {
     return launch_reslice_batch(S->dtype, S->radius, (const BatchReq*)(sl.ws + S->o_req),
                                 (SliceSetup*)(sl.ws + S->o_setup), (const int2*)(sl.ws + S->o_units),
-                                (const int*)sl.ws, std::min(S->cfg.max_tick_requests, 1024),
+                                (const int*)sl.ws, (float*)S->arena, std::min(S->cfg.max_tick_requests, 1024),
                                 S->radius <= 1 ? kServerGrid : 4096, sl.stream);
 }
 
@@ -122,6 +125,12 @@ hipError_t ensure_graph(dare_server* S, Slot& sl) {
     if (e == hipSuccess) e = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     return e;
+}
+
+void release_request(dare_server* S, Request& r) {
+    S->outs.release(r.out_off, r.bytes);
+    if (r.slab_off != UINT64_MAX) S->outs.release(r.slab_off, (uint64_t)r.slab * sizeof(float));
+    r.slab_off = UINT64_MAX;
 }
 
 // Complete finished ticks.  Caller holds the lock.
@@ -142,7 +151,7 @@ void reap(dare_server* S) {
             if (r.t.t_device_done == 0.0) r.t.t_device_done = t;
             r.t.t_host_done = t;
             r.state = ok ? kDone : kFailed;
-            S->outs.release(r.out_off, r.bytes);
+            release_request(S, r);
             S->stats.completed += 1;
             S->stats.pixels += (int64_t)r.spec.width * r.spec.height;
         }
@@ -163,7 +172,7 @@ int busy_slots(dare_server* S) {
 bool launch_tick(dare_server* S, Slot& sl) {
     if (S->queue.empty()) return false;
     const double t_admit = now_s();
-    int64_t pixels = 0, units = 0;
+    int64_t pixels = 0, units = 0, vox = 0;
     int nreq = 0;
     std::vector<BatchReq> breqs;
     std::vector<int2> bunits;
@@ -186,6 +195,18 @@ bool launch_tick(dare_server* S, Slot& sl) {
         q.s.tiles_x = (r.spec.width + kTile - 1) / kTile;
         q.s.tiles = q.s.tiles_x * ((r.spec.height + kTile - 1) / kTile);
         q.s.out = (float*)(S->arena + off);
+        // the slab is optional: without room for it the request gathers per pixel, same result
+        if (r.slab > 0) {
+            const uint64_t so = S->outs.alloc((uint64_t)r.slab * sizeof(float));
+            if (so != UINT64_MAX) {
+                r.slab_off = so;
+                q.v_cap = r.slab;
+                q.v_off = (int64_t)(so / sizeof(float));
+            }
+        }
+        q.v_beg = vox;
+        q.p_beg = pixels;
+        vox += q.v_cap;
         breqs.push_back(q);
         for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
         sl.tickets.push_back(S->queue.front());
@@ -195,8 +216,12 @@ bool launch_tick(dare_server* S, Slot& sl) {
         ++nreq;
     }
     if (nreq == 0) return false;
-    const int counts[4] = {(int)units, nreq, 0, 0};
-    memcpy(sl.staging, counts, sizeof(counts));
+    BatchHeader hd{};
+    hd.counts[0] = (int)units;
+    hd.counts[1] = nreq;
+    hd.totals[0] = vox;
+    hd.totals[1] = pixels;
+    memcpy(sl.staging, &hd, sizeof(hd));
     memcpy(sl.staging + S->o_req, breqs.data(), breqs.size() * sizeof(BatchReq));
     memcpy(sl.staging + S->o_units, bunits.data(), bunits.size() * sizeof(int2));
     const uint64_t upload = S->o_units + bunits.size() * sizeof(int2);
@@ -219,7 +244,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
         for (uint64_t id : sl.tickets) {
             Request& r = S->reqs[id];
             r.state = kFailed;
-            S->outs.release(r.out_off, r.bytes);
+            release_request(S, r);
         }
         sl.tickets.clear();
         sl.busy = false;
@@ -285,7 +310,7 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
     S->arena_bytes = arena_bytes;
     S->max_units = cfg->max_tick_pixels / 256 + 64 * (int64_t)cfg->max_tick_requests;
     if (S->max_units > (1 << 28)) S->max_units = 1 << 28;
-    S->o_req = aup(4 * sizeof(int));
+    S->o_req = aup(sizeof(BatchHeader));
     S->o_units = S->o_req + aup((uint64_t)cfg->max_tick_requests * sizeof(BatchReq));
     S->o_setup = S->o_units + aup((uint64_t)S->max_units * sizeof(int2));
     S->ws_bytes = S->o_setup + aup((uint64_t)cfg->max_tick_requests * sizeof(SliceSetup));
@@ -353,6 +378,7 @@ dare_status dare_server_submit(dare_server* S, int32_t volume_id, const dare_sli
     r.host_out = host_out;
     r.bytes = (uint64_t)spec->width * spec->height * sizeof(float);
     r.units = units_of(S->radius, spec->width, spec->height);
+    r.slab = S->radius <= 1 ? slab_floats(S->vols[volume_id], spec) : 0;
     if (!S->outs.fits_ever(r.bytes) || r.units > S->max_units ||
         (int64_t)spec->width * spec->height > S->cfg.max_tick_pixels)
         return DARE_ERR_INVALID_ARG;

@@ -314,12 +314,17 @@ def test_batch_equals_alone(dare, torch_cuda, cfg1, cfg1_grid):
         vols.append(v)
     rng = np.random.default_rng(5)
     reqs = []
+    # oversampled, undersampled (slab larger than the per-pixel cap: direct gathers),
+    # thin, single-pixel and partly outside the grid
     sizes = [(128, 128, (0.25, 0.25)), (37, 23, (0.6, 0.7)), (200, 90, (0.16, 0.3)), (1, 1, (1, 1)),
-             (64, 65, (0.5, 0.5))]
-    for k in range(14):
+             (64, 65, (0.5, 0.5)), (48, 40, (1.5, 1.5)), (300, 3, (0.1, 0.4)), (17, 250, (0.2, 0.1)),
+             (40, 30, (4.0, 4.0))]
+    for k in range(41):
         v = vols[k % 3]
         W, H, pitch = sizes[k % len(sizes)]
-        P = cfg1.slices.probe_poses[int(rng.integers(len(cfg1.slices.probe_poses)))]
+        P = np.array(cfg1.slices.probe_poses[int(rng.integers(len(cfg1.slices.probe_poses)))])
+        if k % 5 == 4:
+            P[:3, 3] += rng.normal(0.0, 12.0, 3)
         reqs.append((v, dare.make_spec(P, W, H, pitch)))
     outs = [torch.full((s.height, s.width), -7.0, device="cuda") for _, s in reqs]
     ws_bytes = dare.dare_reslice_batch_workspace_bytes([v for v, _ in reqs], [s for _, s in reqs])
