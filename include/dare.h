@@ -116,8 +116,8 @@ uint64_t dare_volume_arena_bytes(const dare_geometry* g, const dare_params* p, d
  * arena [arena_dev, arena_dev + arena_bytes) on the current device; the
  * arena size is the volume's HBM budget.  The arena must stay allocated
  * until dare_volume_destroy.  Synchronous.  Errors: INVALID_ARG (null,
- * non-positive dims/spacing, bad params, arena smaller than the fixed
- * tables), BAD_POSE (calibration not rigid), HIP. */
+ * non-positive dims/spacing, bad params, arena without room for the fixed
+ * tables and one brick slot), BAD_POSE (calibration not rigid), HIP. */
 dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dare_dtype dtype,
                                void* arena_dev, uint64_t arena_bytes, dare_volume** out);
 
@@ -220,7 +220,9 @@ dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes
  * Serving: continuous batching of reslice requests from many consoles (the
  * expert consoles of Sec. 1 each reslice the shared volume at their own
  * pose).  A server owns a caller-supplied device arena (its HBM budget: one
- * request table per stream plus result slots), up to `n_streams` (1..4) HIP
+ * request table per stream, result slots and, at radius 1, the per-request
+ * slabs of blended voxels, which are taken only where room is left: a request
+ * without one gathers per pixel, with the same result), up to `n_streams` (1..4) HIP
  * streams of default priority, and a host thread that groups waiting
  * requests into ticks.  A request is admitted, first come first served, when
  * a result slot of its size can be allocated in the arena; each tick uploads
@@ -234,7 +236,7 @@ dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes
 typedef struct dare_server dare_server;
 
 typedef struct {
-    int64_t max_tick_pixels;  /* pixels per tick (bounds one launch); >= largest request    */
+    int64_t max_tick_pixels;  /* pixels per tick (bounds one launch); >= largest request, <= 2^32 */
     int32_t max_tick_requests;/* requests per tick, 1..4096                                 */
     int32_t n_streams;        /* 1..4                                                        */
     int32_t max_queue;        /* waiting requests before submit returns QUEUE_FULL          */
@@ -265,10 +267,27 @@ dare_status dare_server_add_volume(dare_server* s, const dare_volume* v, int32_t
  * can never fit the arena's result space or one tick. */
 dare_status dare_server_submit(dare_server* s, int32_t volume_id, const dare_slice_spec* spec,
                                float* host_out, uint64_t* ticket);
+/* Queue n requests in order under one lock (for gateways that receive
+ * requests in groups).  Arrays of n: volume_ids, specs, host_outs (each
+ * required); tickets receives one ticket per accepted request.  *accepted is
+ * the number queued, a prefix of the n; the return value is DARE_OK when all
+ * were, else the status of the first one refused (QUEUE_FULL, or INVALID_ARG
+ * as for dare_server_submit), which and whose successors are not queued. */
+dare_status dare_server_submit_many(dare_server* s, int32_t n, const int32_t* volume_ids,
+                                    const dare_slice_spec* specs, float* const* host_outs,
+                                    uint64_t* tickets, int32_t* accepted);
 /* DARE_OK with *times filled (may be NULL) once the result is in host
  * memory, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed.  A
  * ticket is forgotten once poll has returned DARE_OK or DARE_ERR_HIP. */
 dare_status dare_server_poll(dare_server* s, uint64_t ticket, dare_request_times* times);
+/* Poll n tickets at once: states[k] receives what dare_server_poll would
+ * return for tickets[k] (times[k] filled when DARE_OK; times may be NULL),
+ * and *n_done the number no longer NOT_READY (those tickets are forgotten).
+ * With wait_seconds > 0 the call blocks, up to that long, until at least one
+ * of the tickets has finished.  Returns INVALID_ARG only for bad arguments. */
+dare_status dare_server_poll_many(dare_server* s, int32_t n, const uint64_t* tickets,
+                                  dare_request_times* times, int32_t* states, double wait_seconds,
+                                  int32_t* n_done);
 /* Block until every submitted request has completed. */
 dare_status dare_server_drain(dare_server* s);
 dare_status dare_server_get_stats(dare_server* s, dare_server_stats* out);

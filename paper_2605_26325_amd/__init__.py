@@ -63,6 +63,24 @@ class RequestTimes(ct.Structure):
                 ("t_device_done", ct.c_double), ("t_host_done", ct.c_double)]
 
 
+# numpy views of the same layouts, for the grouped server calls
+SPEC_DTYPE = np.dtype([("probe_pose", "<f8", (16,)), ("width", "<i4"), ("height", "<i4"), ("pitch_mm", "<f8", (2,))],
+                      align=True)
+TIMES_DTYPE = np.dtype([(n, "<f8") for n, _ in RequestTimes._fields_])
+assert SPEC_DTYPE.itemsize == ct.sizeof(SliceSpec) and TIMES_DTYPE.itemsize == ct.sizeof(RequestTimes)
+
+
+def spec_array(poses, widths, heights, pitches) -> np.ndarray:
+    """SPEC_DTYPE array of n slice specs (poses (n, 4, 4), pitches (n, 2))."""
+    poses = np.asarray(poses, np.float64).reshape(-1, 16)
+    a = np.zeros(len(poses), SPEC_DTYPE)
+    a["probe_pose"] = poses
+    a["width"] = widths
+    a["height"] = heights
+    a["pitch_mm"] = np.asarray(pitches, np.float64).reshape(-1, 2)
+    return a
+
+
 class DareError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -101,6 +119,8 @@ def _load():
         "dare_server_add_volume": (ct.c_int, [V, V, ct.POINTER(I32)]),
         "dare_server_submit": (ct.c_int, [V, I32, ct.POINTER(SliceSpec), P, ct.POINTER(U64)]),
         "dare_server_poll": (ct.c_int, [V, U64, ct.POINTER(RequestTimes)]),
+        "dare_server_submit_many": (ct.c_int, [V, I32, P, P, P, P, ct.POINTER(I32)]),
+        "dare_server_poll_many": (ct.c_int, [V, I32, P, P, P, D, ct.POINTER(I32)]),
         "dare_server_drain": (ct.c_int, [V]),
         "dare_server_get_stats": (ct.c_int, [V, ct.POINTER(ServerStats)]),
         "dare_server_destroy": (ct.c_int, [V]),
@@ -356,6 +376,35 @@ class Server:
             return None
         _check(st, "dare_server_submit")
         return t.value
+
+    def submit_many(self, volume_ids, specs: np.ndarray, host_out_ptrs):
+        """Queue requests in order: volume_ids (n,), specs a SPEC_DTYPE array (n,), host_out_ptrs
+        (n,) addresses.  Returns (tickets of the accepted prefix, status of the first refused one
+        or OK); QUEUE_FULL is a status, other refusals raise."""
+        n = len(specs)
+        vid = np.ascontiguousarray(volume_ids, np.int32)
+        sp = np.ascontiguousarray(specs, SPEC_DTYPE)
+        outs = np.ascontiguousarray(host_out_ptrs, np.uint64)
+        if len(vid) != n or len(outs) != n:
+            raise ValueError("submit_many: arrays of different lengths")
+        tickets = np.zeros(n, np.uint64)
+        acc = ct.c_int32()
+        st = lib.dare_server_submit_many(self.handle, n, vid.ctypes.data, sp.ctypes.data, outs.ctypes.data,
+                                         tickets.ctypes.data, ct.byref(acc))
+        if st not in (OK, ERR_QUEUE_FULL):
+            _check(st, "dare_server_submit_many")
+        return tickets[:acc.value], st
+
+    def poll_many(self, tickets, wait_seconds: float = 0.0):
+        """(states (n,) int32, times (n,) TIMES_DTYPE) for the tickets; finished ones are retired."""
+        tk = np.ascontiguousarray(tickets, np.uint64)
+        n = len(tk)
+        states = np.zeros(n, np.int32)
+        times = np.zeros(n, TIMES_DTYPE)
+        nd = ct.c_int32()
+        _check(lib.dare_server_poll_many(self.handle, n, tk.ctypes.data, times.ctypes.data, states.ctypes.data,
+                                         float(wait_seconds), ct.byref(nd)), "dare_server_poll_many")
+        return states, times
 
     def poll(self, ticket: int):
         """RequestTimes once the result is in host memory, else None."""

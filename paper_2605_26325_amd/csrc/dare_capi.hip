@@ -259,7 +259,7 @@ int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec) {
     }
     const int64_t cols = std::max(d[0] * d[1], std::max(d[0] * d[2], d[1] * d[2]));
     const int64_t cap = std::min(cols * kSlabDepthMax, (int64_t)kSlabPerPixel * W * H);
-    return (cap + 63) / 64 * 64;
+    return (cap + 255) / 256 * 256;
 }
 
 }  // namespace dare
@@ -310,6 +310,7 @@ dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dar
     uint64_t cap = (arena_bytes - L0.off_new) / L0.per_slot;   // upper bound; alignment trims below
     if (cap > 0x7FFFFFFFull) cap = 0x7FFFFFFFull;
     while (cap > 0 && layout(g, p, dtype, cap).end > arena_bytes) --cap;
+    if (cap == 0) return DARE_ERR_INVALID_ARG;   // room for at least one brick slot
     const Layout L = layout(g, p, dtype, cap);
 
     dare_volume* v = new dare_volume();
@@ -466,18 +467,21 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         q.vol = vols[k]->dev;
         q.s = make_args(specs + k, outs_dev[k]);
         if (R <= 1) {
+            // flat ranges padded to whole 256-index blocks (slab capacities already are)
             q.v_cap = slab_floats(vols[k], specs + k);
             q.v_beg = g.vox;
             q.v_off = g.vox;
             q.p_beg = g.pix;
             g.vox += q.v_cap;
-            g.pix += (int64_t)specs[k].width * specs[k].height;
+            g.pix += ((int64_t)specs[k].width * specs[k].height + 255) / 256 * 256;
         } else {
             const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
             for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
         }
         g.reqs.push_back(q);
     }
+    for (auto& kv : groups)   // flat indices are counted in 32-bit blocks of 256 on the device
+        if (kv.second.vox / 256 >= INT32_MAX || kv.second.pix / 256 >= INT32_MAX) return DARE_ERR_INVALID_ARG;
     char* ws = (char*)workspace_dev;
     for (auto& kv : groups) {
         Group& g = kv.second;
@@ -497,8 +501,8 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         const int R = kv.first.second;
         const int grid = R <= 1 ? kBatchGrid : std::min(nunits, 65535);
         HIP_TRY(launch_reslice_batch(kv.first.first, R, (const BatchReq*)(ws + L.o_req), (SliceSetup*)(ws + L.o_setup),
-                                     (const int2*)(ws + L.o_units), (const int*)ws, (float*)(ws + L.o_slab),
-                                     std::min(nreq, 1024), grid, stream));
+                                     (const int2*)(ws + L.o_units), (const int*)ws, (float*)(ws + L.o_slab), nreq,
+                                     grid, stream));
         ws += L.total;
     }
     return DARE_OK;

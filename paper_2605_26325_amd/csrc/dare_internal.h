@@ -90,14 +90,15 @@ struct BatchReq {
     const VolDev* vol;
     SliceArgs s;
     // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
-    // (v_beg: first index of this request's slab) and their pixels (p_beg).  The slab
-    // itself lives at float offset v_off of the scratch; v_cap floats, 0 for none.
+    // (v_beg: first index of this request's slab) and their pixels (p_beg), each request's
+    // range padded to whole blocks of 256.  The slab itself lives at float offset v_off of
+    // the scratch; v_cap floats (a multiple of 256), 0 for none.
     int64_t v_beg, v_off, v_cap;
     int64_t p_beg;
 };
 
 // Batch header at the start of a workspace: int32 {units, requests, 0, 0}, then int64
-// {slab index total, pixel total}.
+// {slab index total, pixel index total}, both multiples of 256.
 struct BatchHeader {
     int32_t counts[4];
     int64_t totals[2];
@@ -105,6 +106,19 @@ struct BatchHeader {
 
 constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
 constexpr int kSlabPerPixel = 12;         // slab floats per output pixel beyond which pixels gather directly
+
+// What the reslice passes read of a volume header, copied next to the request's
+// setup so that a workgroup fetches everything it needs in one burst of loads.
+struct VolView {
+    const int32_t* table;
+    const void* data;
+    const float2* scales;
+    int64_t nbricks;
+    int32_t n[3];
+    int32_t nbx, nby;
+    double origin[3];
+    double inv_h;
+};
 
 // Per-request reslice setup: composed pose, surviving bins and their Eq. 2
 // weights, and the plane frame used by the footprint tests.
@@ -126,6 +140,12 @@ struct SliceSetup {
     int staged;                           // 1: slab staged; 0: gather per pixel
     float c0[3];                          // voxel coordinates of pixel (0, 0)
     float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
+    // copies of the request and its volume (batched passes)
+    VolView vol;
+    double sx, sy;
+    int32_t W, H;
+    float* out;
+    int64_t v_off;
 };
 
 inline int pair_bytes(int dtype) {
@@ -160,8 +180,10 @@ hipError_t launch_download_sums(const VolDev* vd, uint32_t* S, uint32_t* C, int 
 hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float* C, int K, int nx, int ny,
                                    int nz, hipStream_t stream);
 hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream);
+// nreq_max bounds the requests of any batch launched with these arguments (the count itself is
+// read from `counts` on the device, so a captured graph can be replayed with fewer).
 hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, float* scratch, int nreq_grid, int grid, hipStream_t stream);
+                                const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream);
 // Slab floats to reserve for a radius-1 request (0 when its pixels should gather directly):
 // the slice's voxel bounding box, two voxels of margin, over the largest pair of axes,
 // times the deepest run, capped at kSlabPerPixel per pixel.  Defined with the C ABI.

@@ -280,70 +280,89 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
     tl.nlist = 0;
 }
 
-// Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).  UNI: the
-// whole wavefront works on one request, so bin ids and weights are broadcast as scalars;
-// the flat batched pass mixes requests within a wavefront and loads them per lane.
-template <int DT, bool UNI = true>
-__device__ __forceinline__ float pixel_direct(const VolDev* __restrict__ vd, const SetupLds& sh, int kact,
-                                              const double c[3]) {
+__device__ __forceinline__ VolView view_of(const VolDev* __restrict__ vd) {
+    VolView v;
+    v.table = vd->table;
+    v.data = vd->data;
+    v.scales = vd->scales;
+    v.nbricks = vd->nbricks;
+    v.n[0] = vd->nx;
+    v.n[1] = vd->ny;
+    v.n[2] = vd->nz;
+    v.nbx = vd->nbx;
+    v.nby = vd->nby;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v.origin[a] = vd->origin[a];
+    v.inv_h = vd->inv_h;
+    return v;
+}
+
+// Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).  The whole
+// workgroup works on one request: bin ids and weights are broadcast as scalars.  All loads of
+// NB bins are issued before any is used (indices of absent voxels point at entry 0, which
+// exists, and their values are discarded), so NB bins cost two memory round trips.
+template <int DT, int NB>
+__device__ __forceinline__ float pixel_direct(const VolView& vv, const SetupLds& sh, int kact, const double c[3]) {
     using PT = Pair<DT>;
-    const int nx = vd->nx, ny = vd->ny, nz = vd->nz;
+    const int nx = vv.n[0], ny = vv.n[1], nz = vv.n[2];
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
     const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
     const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
     const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-    const int nbx = vd->nbx, nby = vd->nby;
-    int bx[2], lx[2], rowb[2][2], rowl[2][2];
-    bool inx[2], inyz[2][2];
+    const int nbx = vv.nbx, nby = vv.nby;
+    int tix[8], lix[8];
+    bool in[8];
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-        const int v = x0 + d;
-        inx[d] = (unsigned)v < (unsigned)nx;
-        bx[d] = v >> 3;
-        lx[d] = v & 7;
+    for (int v = 0; v < 8; ++v) {                  // v = (dz << 2) | (dy << 1) | dx
+        const int vx = x0 + (v & 1), vy = y0 + ((v >> 1) & 1), vz = z0 + (v >> 2);
+        in[v] = (unsigned)vx < (unsigned)nx && (unsigned)vy < (unsigned)ny && (unsigned)vz < (unsigned)nz;
+        tix[v] = in[v] ? ((vz >> 3) * nby + (vy >> 3)) * nbx + (vx >> 3) : 0;
+        lix[v] = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
     }
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-            const int vy = y0 + dy, vz = z0 + dz;
-            inyz[dz][dy] = (unsigned)vy < (unsigned)ny && (unsigned)vz < (unsigned)nz;
-            rowb[dz][dy] = ((vz >> 3) * nby + (vy >> 3)) * nbx;
-            rowl[dz][dy] = ((vz & 7) << 6) | ((vy & 7) << 3);
-        }
-    const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
-    const int64_t nbricks = vd->nbricks;
+    const typename PT::T* __restrict__ data = (const typename PT::T*)vv.data;
+    const int64_t nbricks = vv.nbricks;
     float A[8], B[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { A[k] = 0.0f; B[k] = 0.0f; }
-    for (int k = 0; k < kact; ++k) {
-        const int b = UNI ? uniform_i32(sh.act_bin[k]) : sh.act_bin[k];
-        const float wgt = UNI ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k])))
-                              : sh.act_w[k];
-        const int32_t* __restrict__ tab = vd->table + (int64_t)b * nbricks;
+    for (int v = 0; v < 8; ++v) { A[v] = 0.0f; B[v] = 0.0f; }
+    for (int k0 = 0; k0 < kact; k0 += NB) {
+        int sl[NB][8];
+        typename PT::T pr[NB][8];
+        float2 sc[NB][8];
 #pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
+        for (int h = 0; h < NB; ++h) {
+            const int b = uniform_i32(sh.act_bin[k0 + h < kact ? k0 + h : k0]);
+            const int32_t* __restrict__ tab = vv.table + (int64_t)b * nbricks;
 #pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
+            for (int v = 0; v < 8; ++v) sl[h][v] = tab[tix[v]];
+        }
 #pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    if (!(inx[dx] && inyz[dz][dy])) continue;
-                    const int slot = tab[rowb[dz][dy] + bx[dx]];
-                    if (slot < 0) continue;
-                    float2 sc = make_float2(0.0f, 0.0f);
-                    if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
-                    float a, cnt;
-                    PT::decode(data[(size_t)slot * kBrickVox + (rowl[dz][dy] | lx[dx])], sc, a, cnt);
-                    const int v = (dz << 2) | (dy << 1) | dx;
-                    if (kact == 1) {              // a single direction: its weight cancels, V = a
-                        A[v] = a;
-                        B[v] = cnt;
-                    } else {
-                        const float wc = wgt * cnt;
-                        A[v] = __builtin_fmaf(wc, a, A[v]);
-                        B[v] = B[v] + wc;
-                    }
+        for (int h = 0; h < NB; ++h)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int s0 = sl[h][v] >= 0 ? sl[h][v] : 0;
+                pr[h][v] = data[(size_t)s0 * kBrickVox + lix[v]];
+                sc[h][v] = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc[h][v] = vv.scales[s0];
+            }
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            if (k0 + h >= kact) break;
+            const float wgt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sh.act_w[k0 + h])));
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                if (!in[v] || sl[h][v] < 0) continue;
+                float a, cnt;
+                PT::decode(pr[h][v], sc[h][v], a, cnt);
+                if (kact == 1) {              // a single direction: its weight cancels, V = a
+                    A[v] = a;
+                    B[v] = cnt;
+                } else {
+                    const float wc = wgt * cnt;
+                    A[v] = __builtin_fmaf(wc, a, A[v]);
+                    B[v] = B[v] + wc;
                 }
+            }
+        }
     }
     float num = 0.0f, den = 0.0f;
 #pragma unroll
@@ -501,7 +520,7 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
         return;
     }
     if (mode == 2) {
-        *out = pixel_direct<DT>(vd, sh, kact, c);
+        *out = pixel_direct<DT, 2>(view_of(vd), sh, kact, c);
         return;
     }
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
@@ -509,27 +528,32 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
     const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
     const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
     const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2], dx = tl.dim[0], dy = tl.dim[1], dz = tl.dim[2];
+    // indices first, then all 8 LDS reads at once (absent corners read entry 0 and are discarded)
+    float tw[8], Vc[8];
+    int ix[8];
+    bool ok[8];
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) {                 // c8 = (dz << 2) | (dy << 1) | dx
+        const int ddx = c8 & 1, ddy = (c8 >> 1) & 1, ddz = c8 >> 2;
+        tw[c8] = (wx[ddx] * wy[ddy]) * wz[ddz];      // only voxels with weight were staged
+        const int vx = x0 + ddx, vy = y0 + ddy, vz = z0 + ddz;
+        const int ex = vx - lox, ey = vy - loy, ez = vz - loz;
+        // the box holds every in-grid cell voxel of the tile: its test only bounds the index
+        ok[c8] = tw[c8] > 0.0f && (unsigned)vx < (unsigned)nx && (unsigned)vy < (unsigned)ny &&
+                 (unsigned)vz < (unsigned)nz && (unsigned)ex < (unsigned)dx && (unsigned)ey < (unsigned)dy &&
+                 (unsigned)ez < (unsigned)dz;
+        ix[c8] = ok[c8] ? (ez * dy + ey) * dx + ex : 0;
+    }
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) Vc[c8] = tl.V[ix[c8]];
     float num = 0.0f, den = 0.0f;
 #pragma unroll
-    for (int ddz = 0; ddz < 2; ++ddz)
-#pragma unroll
-        for (int ddy = 0; ddy < 2; ++ddy)
-#pragma unroll
-            for (int ddx = 0; ddx < 2; ++ddx) {
-                const float t = (wx[ddx] * wy[ddy]) * wz[ddz];
-                if (!(t > 0.0f)) continue;   // only voxels with weight were staged
-                const int vx = x0 + ddx, vy = y0 + ddy, vz = z0 + ddz;
-                if ((unsigned)vx >= (unsigned)nx || (unsigned)vy >= (unsigned)ny || (unsigned)vz >= (unsigned)nz)
-                    continue;
-                const int ex = vx - lox, ey = vy - loy, ez = vz - loz;
-                if ((unsigned)ex >= (unsigned)dx || (unsigned)ey >= (unsigned)dy || (unsigned)ez >= (unsigned)dz)
-                    continue;   // unreachable: the box holds every in-grid cell voxel of the tile
-                const float V = tl.V[(ez * dy + ey) * dx + ex];
-                if (V == V) {
-                    num = __builtin_fmaf(t, V, num);
-                    den = den + t;
-                }
-            }
+    for (int c8 = 0; c8 < 8; ++c8) {
+        if (ok[c8] && Vc[c8] == Vc[c8]) {
+            num = __builtin_fmaf(tw[c8], Vc[c8], num);
+            den = den + tw[c8];
+        }
+    }
     *out = den > 0.0f ? num / den : __builtin_nanf("");
 }
 
@@ -721,26 +745,38 @@ __global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__
                                                      const int* __restrict__ counts) {
     const int nreq = counts[1];
     for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
+        const VolDev* vd = reqs[r].vol;
+        const SliceArgs& s = reqs[r].s;
+        SliceSetup& su = setups[r];
         double T[12];
-        const int ka = slice_setup(reqs[r].vol, reqs[r].s, setups[r], T);
-        slab_setup(reqs[r].vol, reqs[r].s, T, ka, reqs[r].v_cap, setups[r]);
+        const int ka = slice_setup(vd, s, su, T);
+        slab_setup(vd, s, T, ka, reqs[r].v_cap, su);
+        if (threadIdx.x == 0) {
+            su.vol = view_of(vd);
+            su.sx = s.sx;
+            su.sy = s.sy;
+            su.W = s.W;
+            su.H = s.H;
+            su.out = s.out;
+            su.v_off = reqs[r].v_off;
+        }
     }
 }
 
 // V_v of voxel (vx, vy, vz) over the surviving bins, straight from the brick pool.
 template <int DT>
-__device__ __forceinline__ float blend_at(const VolDev* __restrict__ vd, const SliceSetup& su, int kact, int vx, int vy,
-                                          int vz) {
+__device__ __forceinline__ float blend_at(const SliceSetup& su, int kact, int vx, int vy, int vz) {
     using PT = Pair<DT>;
-    const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
-    const int64_t nbricks = vd->nbricks;
-    const int64_t brick = ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
+    const VolView& vv = su.vol;
+    const typename PT::T* __restrict__ data = (const typename PT::T*)vv.data;
+    const int64_t nbricks = vv.nbricks;
+    const int64_t brick = ((int64_t)(vz >> 3) * vv.nby + (vy >> 3)) * vv.nbx + (vx >> 3);
     const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
     if (kact == 1) {
-        const int slot = vd->table[(int64_t)su.act_bin[0] * nbricks + brick];
+        const int slot = vv.table[(int64_t)su.act_bin[0] * nbricks + brick];
         if (slot < 0) return __builtin_nanf("");
         float2 sc = make_float2(0.0f, 0.0f);
-        if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
+        if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[slot];
         float a, cnt;
         PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
         return cnt > 0.0f ? a : __builtin_nanf("");
@@ -751,7 +787,7 @@ __device__ __forceinline__ float blend_at(const VolDev* __restrict__ vd, const S
         typename PT::T pr[kBinChunk];
 #pragma unroll
         for (int u = 0; u < kBinChunk; ++u)
-            sl[u] = (k0 + u < kact) ? vd->table[(int64_t)su.act_bin[k0 + u] * nbricks + brick] : -1;
+            sl[u] = (k0 + u < kact) ? vv.table[(int64_t)su.act_bin[k0 + u] * nbricks + brick] : -1;
 #pragma unroll
         for (int u = 0; u < kBinChunk; ++u)
             if (sl[u] >= 0) pr[u] = data[(size_t)sl[u] * kBrickVox + local];
@@ -759,7 +795,7 @@ __device__ __forceinline__ float blend_at(const VolDev* __restrict__ vd, const S
         for (int u = 0; u < kBinChunk; ++u) {
             if (sl[u] < 0) continue;
             float2 sc = make_float2(0.0f, 0.0f);
-            if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[sl[u]];
+            if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[sl[u]];
             float a, cnt;
             PT::decode(pr[u], sc, a, cnt);
             const float wc = su.act_w[k0 + u] * cnt;
@@ -770,39 +806,45 @@ __device__ __forceinline__ float blend_at(const VolDev* __restrict__ vd, const S
     return B > 0.0f ? A / B : __builtin_nanf("");
 }
 
-// Request owning flat index g: the last r with begin(r) <= g (begins ascending from 0).
+// The passes run over flat index spaces in blocks of 256: each request's range starts on a
+// block boundary, so a workgroup iteration belongs to one request and everything it reads of
+// that request (setup record, volume view) is uniform.  Each workgroup first copies the
+// requests' first blocks into LDS; the request of block b is then the last r with
+// first(r) <= b, found by a binary search in LDS.
 template <bool VOX>
-__device__ __forceinline__ int find_req(const BatchReq* __restrict__ reqs, int nreq, int64_t g) {
+__device__ __forceinline__ int load_begins(const BatchReq* __restrict__ reqs, const int* __restrict__ counts,
+                                           int* s_beg) {
+    const int nreq = counts[1];
+    for (int i = threadIdx.x; i < nreq; i += blockDim.x)
+        s_beg[i] = (int)((VOX ? reqs[i].v_beg : reqs[i].p_beg) >> 8);
+    __syncthreads();
+    return nreq;
+}
+
+__device__ __forceinline__ int find_req(const int* s_beg, int nreq, int blk) {
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t b = VOX ? reqs[mid].v_beg : reqs[mid].p_beg;
-        if (b <= g) lo = mid; else hi = mid - 1;
+        if (s_beg[mid] <= blk) lo = mid; else hi = mid - 1;
     }
-    return lo;
-}
-
-__device__ __forceinline__ int64_t batch_total(const int* counts, int k) {
-    return reinterpret_cast<const int64_t*>(counts + 4)[k];
+    return uniform_i32(lo);
 }
 
 template <int DT>
 __global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__ reqs,
                                                     const SliceSetup* __restrict__ setups, float* __restrict__ scratch,
                                                     const int* __restrict__ counts) {
-    const int nreq = counts[1];
-    const int64_t total = batch_total(counts, 0);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-        const int r = find_req<true>(reqs, nreq, g);
+    extern __shared__ int s_beg[];
+    const int nreq = load_begins<true>(reqs, counts, s_beg);
+    const int nblk = (int)(reinterpret_cast<const int64_t*>(counts + 4)[0] >> 8);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int r = find_req(s_beg, nreq, blk);
         const SliceSetup& su = setups[r];
-        const int64_t e64 = g - reqs[r].v_beg;
-        if (e64 >= su.ncand) continue;
-        const int e = (int)e64;
-        const VolDev* __restrict__ vd = reqs[r].vol;
+        const int e = ((blk - s_beg[r]) << 8) + (int)threadIdx.x;
+        if (e >= su.ncand) continue;
         const int dax = su.dax, pax = su.pax;
         const int dim_p = su.dim_p, ncols = su.dim_p * su.dim_q;
-        const int nd = dax == 0 ? vd->nx : (dax == 1 ? vd->ny : vd->nz);
+        const int nd = su.vol.n[dax];
         const int col = e % ncols, k = e / ncols;
         const int vp = su.lo_p + col % dim_p, vq = su.lo_q + col / dim_p;
         const int vdd = run_start(su, vp, vq) + k;
@@ -817,28 +859,36 @@ __global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__
             const float dv = su.fw[0] * d0 + su.fw[1] * d1 + su.fw[2] * d2;
             if (fabsf(dn) < su.thr_n && du > -su.thr_u && du < su.len_u + su.thr_u && dv > -su.thr_v &&
                 dv < su.len_v + su.thr_v)
-                V = blend_at<DT>(vd, su, su.kact, vx, vy, vz);
+                V = blend_at<DT>(su, su.kact, vx, vy, vz);
         }
-        scratch[reqs[r].v_off + e] = V;
+        scratch[su.v_off + e] = V;
     }
 }
 
-template <int DT>
+// Pixels of staged requests (STAGED) or of requests that gather per pixel (!STAGED): two
+// kernels, so that the staged one keeps the register budget of its 8 slab reads.  A kernel
+// skips the other kind's requests one whole range at a time.
+template <int DT, bool STAGED>
 __global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__ reqs,
                                                     const SliceSetup* __restrict__ setups,
                                                     const float* __restrict__ scratch, const int* __restrict__ counts) {
-    const int nreq = counts[1];
-    const int64_t total = batch_total(counts, 1);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-        const int r = find_req<false>(reqs, nreq, g);
-        const BatchReq& rq = reqs[r];
+    extern __shared__ int s_beg[];
+    const int nreq = load_begins<false>(reqs, counts, s_beg);
+    const int nblk = (int)(reinterpret_cast<const int64_t*>(counts + 4)[1] >> 8);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int r = find_req(s_beg, nreq, blk);
         const SliceSetup& su = setups[r];
-        const VolDev* __restrict__ vd = rq.vol;
-        const int W = rq.s.W;
-        const int64_t p = g - rq.p_beg;
-        const int i = (int)(p % W), j = (int)(p / W);
-        float* out = rq.s.out + p;
+        if ((su.staged != 0) != STAGED) {
+            if (r + 1 >= nreq) break;
+            const int next = s_beg[r + 1];            // first block of the next request
+            blk += (next - blk + (int)gridDim.x - 1) / (int)gridDim.x * (int)gridDim.x - (int)gridDim.x;
+            continue;
+        }
+        const int W = su.W;
+        const int p = ((blk - s_beg[r]) << 8) + (int)threadIdx.x;
+        if (p >= W * su.H) continue;
+        const int j = p / W, i = p - j * W;
+        float* out = su.out + p;
         const int kact = su.kact;
         SlicePos q;
 #pragma unroll
@@ -846,12 +896,12 @@ __global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__
             q.t[a] = su.T[a * 4 + 3];
             q.e0[a] = su.T[a * 4 + 0];
             q.e1[a] = su.T[a * 4 + 1];
-            q.o[a] = vd->origin[a];
+            q.o[a] = su.vol.origin[a];
         }
-        q.inv_h = vd->inv_h;
-        q.sx = rq.s.sx;
-        q.sy = rq.s.sy;
-        const int n[3] = {vd->nx, vd->ny, vd->nz};
+        q.inv_h = su.vol.inv_h;
+        q.sx = su.sx;
+        q.sy = su.sy;
+        const int n[3] = {su.vol.n[0], su.vol.n[1], su.vol.n[2]};
         double c[3];
         pixel_coords(q, i, j, c);
         if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
@@ -859,43 +909,48 @@ __global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__
             *out = __builtin_nanf("");
             continue;
         }
-        if (!su.staged) {
-            *out = pixel_direct<DT, false>(vd, su, kact, c);
+        if constexpr (!STAGED) {
+            *out = pixel_direct<DT, 2>(su.vol, su, kact, c);
             continue;
-        }
-        const float* __restrict__ slab = scratch + rq.v_off;
+        } else {
+        const float* __restrict__ slab = scratch + su.v_off;
         const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
         const int b0[3] = {(int)f0, (int)f1, (int)f2};
         const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
         const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
         const int pax = su.pax, qax = su.qax, dax = su.dax;
         const int dim_p = su.dim_p, dim_q = su.dim_q, depth = su.depth, ncols = dim_p * dim_q;
+        // indices first, then all 8 loads at once (absent corners read entry 0 and are discarded)
+        float tw[8], Vc[8];
+        int ix[8];
+        bool ok[8];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {                 // c8 = (dz << 2) | (dy << 1) | dx
+            const int ddx = c8 & 1, ddy = (c8 >> 1) & 1, ddz = c8 >> 2;
+            tw[c8] = (wx[ddx] * wy[ddy]) * wz[ddz];
+            const int v[3] = {b0[0] + ddx, b0[1] + ddy, b0[2] + ddz};
+            const int vp = v[pax], vq = v[qax];
+            const int cp = vp - su.lo_p, cq = vq - su.lo_q;
+            const int kk = v[dax] - run_start(su, vp, vq);
+            // a cell voxel with weight inside the grid always lies in the slab; the slab test
+            // only keeps the index in bounds
+            ok[c8] = tw[c8] > 0.0f && (unsigned)v[0] < (unsigned)n[0] && (unsigned)v[1] < (unsigned)n[1] &&
+                     (unsigned)v[2] < (unsigned)n[2] && (unsigned)cp < (unsigned)dim_p &&
+                     (unsigned)cq < (unsigned)dim_q && (unsigned)kk < (unsigned)depth;
+            ix[c8] = ok[c8] ? kk * ncols + cq * dim_p + cp : 0;
+        }
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) Vc[c8] = slab[ix[c8]];
         float num = 0.0f, den = 0.0f;
 #pragma unroll
-        for (int ddz = 0; ddz < 2; ++ddz)
-#pragma unroll
-            for (int ddy = 0; ddy < 2; ++ddy)
-#pragma unroll
-                for (int ddx = 0; ddx < 2; ++ddx) {
-                    const float t = (wx[ddx] * wy[ddy]) * wz[ddz];
-                    if (!(t > 0.0f)) continue;
-                    const int v[3] = {b0[0] + ddx, b0[1] + ddy, b0[2] + ddz};
-                    if ((unsigned)v[0] >= (unsigned)n[0] || (unsigned)v[1] >= (unsigned)n[1] ||
-                        (unsigned)v[2] >= (unsigned)n[2])
-                        continue;
-                    const int vp = v[pax], vq = v[qax];
-                    const int cp = vp - su.lo_p, cq = vq - su.lo_q;
-                    const int kk = v[dax] - run_start(su, vp, vq);
-                    if ((unsigned)cp >= (unsigned)dim_p || (unsigned)cq >= (unsigned)dim_q ||
-                        (unsigned)kk >= (unsigned)depth)
-                        continue;   // unreachable: every cell voxel with weight lies in the slab
-                    const float V = slab[(int64_t)kk * ncols + cq * dim_p + cp];
-                    if (V == V) {
-                        num = __builtin_fmaf(t, V, num);
-                        den = den + t;
-                    }
-                }
+        for (int c8 = 0; c8 < 8; ++c8) {
+            if (ok[c8] && Vc[c8] == Vc[c8]) {
+                num = __builtin_fmaf(tw[c8], Vc[c8], num);
+                den = den + tw[c8];
+            }
+        }
         *out = den > 0.0f ? num / den : __builtin_nanf("");
+        }
     }
 }
 
@@ -954,10 +1009,14 @@ hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceAr
 }
 
 hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, float* scratch, int nreq_grid, int grid, hipStream_t stream) {
+                                const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream) {
     const int G = reslice_lanes(radius);
-#define V1(D) hipLaunchKernelGGL(k_voxel_pass<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, scratch, counts)
-#define P1(D) hipLaunchKernelGGL(k_pixel_pass<D>, dim3(grid), dim3(256), 0, stream, reqs, setups, scratch, counts)
+    const int nreq_grid = nreq_max < 1024 ? nreq_max : 1024;
+    const size_t lds = (size_t)nreq_max * sizeof(int);
+#define V1(D) hipLaunchKernelGGL(k_voxel_pass<D>, dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts)
+#define P1(D)                                                                                                  \
+    hipLaunchKernelGGL((k_pixel_pass<D, true>), dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts); \
+    hipLaunchKernelGGL((k_pixel_pass<D, false>), dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts)
 #define B16(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 16>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
 #define B64(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 64>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
     if (G == 1) {

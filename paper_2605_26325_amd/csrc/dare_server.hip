@@ -93,7 +93,8 @@ struct dare_server {
     std::vector<const dare_volume*> vols;
     int dtype = -1, radius = -1;
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;       // scheduler: new work or stop
+    std::condition_variable done_cv;  // waiters: some request completed
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
@@ -110,7 +111,7 @@ namespace {
 hipError_t enqueue_kernels(dare_server* S, Slot& sl) {
     return launch_reslice_batch(S->dtype, S->radius, (const BatchReq*)(sl.ws + S->o_req),
                                 (SliceSetup*)(sl.ws + S->o_setup), (const int2*)(sl.ws + S->o_units),
-                                (const int*)sl.ws, (float*)S->arena, std::min(S->cfg.max_tick_requests, 1024),
+                                (const int*)sl.ws, (float*)S->arena, S->cfg.max_tick_requests,
                                 S->radius <= 1 ? kServerGrid : 4096, sl.stream);
 }
 
@@ -158,6 +159,7 @@ void reap(dare_server* S) {
         if (!ok) S->failed = true;
         sl.tickets.clear();
         sl.busy = false;
+        S->done_cv.notify_all();
     }
 }
 
@@ -172,7 +174,7 @@ int busy_slots(dare_server* S) {
 bool launch_tick(dare_server* S, Slot& sl) {
     if (S->queue.empty()) return false;
     const double t_admit = now_s();
-    int64_t pixels = 0, units = 0, vox = 0;
+    int64_t pixels = 0, units = 0, vox = 0, pflat = 0;
     int nreq = 0;
     std::vector<BatchReq> breqs;
     std::vector<int2> bunits;
@@ -205,8 +207,9 @@ bool launch_tick(dare_server* S, Slot& sl) {
             }
         }
         q.v_beg = vox;
-        q.p_beg = pixels;
+        q.p_beg = pflat;
         vox += q.v_cap;
+        pflat += (px + 255) / 256 * 256;          // flat ranges in whole 256-index blocks
         breqs.push_back(q);
         for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
         sl.tickets.push_back(S->queue.front());
@@ -220,7 +223,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
     hd.counts[0] = (int)units;
     hd.counts[1] = nreq;
     hd.totals[0] = vox;
-    hd.totals[1] = pixels;
+    hd.totals[1] = pflat;
     memcpy(sl.staging, &hd, sizeof(hd));
     memcpy(sl.staging + S->o_req, breqs.data(), breqs.size() * sizeof(BatchReq));
     memcpy(sl.staging + S->o_units, bunits.data(), bunits.size() * sizeof(int2));
@@ -249,6 +252,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
         sl.tickets.clear();
         sl.busy = false;
         S->failed = true;
+        S->done_cv.notify_all();
     }
     return true;
 }
@@ -281,6 +285,46 @@ void scheduler(dare_server* S) {
     }
 }
 
+// Validate and queue one request.  Caller holds the lock.
+dare_status submit_locked(dare_server* S, int32_t volume_id, const dare_slice_spec* spec, float* host_out,
+                          uint64_t* ticket) {
+    const dare_status st = check_slice_spec(spec);
+    if (st != DARE_OK) return st;
+    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
+    Request r;
+    r.vol = volume_id;
+    r.spec = *spec;
+    r.host_out = host_out;
+    r.bytes = (uint64_t)spec->width * spec->height * sizeof(float);
+    r.units = units_of(S->radius, spec->width, spec->height);
+    r.slab = S->radius <= 1 ? slab_floats(S->vols[volume_id], spec) : 0;
+    if (!S->outs.fits_ever(r.bytes) || r.units > S->max_units ||
+        (int64_t)spec->width * spec->height > S->cfg.max_tick_pixels)
+        return DARE_ERR_INVALID_ARG;
+    if ((int32_t)S->queue.size() >= S->cfg.max_queue) {
+        S->stats.rejected += 1;
+        return DARE_ERR_QUEUE_FULL;
+    }
+    r.t.t_submit = now_s();
+    const uint64_t id = S->next_ticket++;
+    S->reqs.emplace(id, r);
+    S->queue.push_back(id);
+    S->stats.submitted += 1;
+    *ticket = id;
+    return DARE_OK;
+}
+
+// State of one ticket; a finished ticket is retired.  Caller holds the lock.
+dare_status poll_locked(dare_server* S, uint64_t ticket, dare_request_times* times) {
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return DARE_ERR_INVALID_ARG;
+    const int state = it->second.state;
+    if (state == kWaiting || state == kInFlight) return DARE_ERR_NOT_READY;
+    if (times) *times = it->second.t;
+    S->reqs.erase(it);
+    return state == kDone ? DARE_OK : DARE_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -301,7 +345,8 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
     if (!cfg || !arena_dev || !out) return DARE_ERR_INVALID_ARG;
     *out = nullptr;
     if (cfg->n_streams < 1 || cfg->n_streams > kMaxStreams || cfg->max_tick_requests < 1 ||
-        cfg->max_tick_requests > 4096 || cfg->max_tick_pixels < 1 || cfg->max_queue < 1)
+        cfg->max_tick_requests > 4096 || cfg->max_tick_pixels < 1 || cfg->max_tick_pixels > ((int64_t)1 << 32) ||
+        cfg->max_queue < 1)
         return DARE_ERR_INVALID_ARG;
     if (((uintptr_t)arena_dev % kAlignS) != 0) return DARE_ERR_INVALID_ARG;
     dare_server* S = new dare_server();
@@ -368,44 +413,56 @@ dare_status dare_server_add_volume(dare_server* S, const dare_volume* v, int32_t
 dare_status dare_server_submit(dare_server* S, int32_t volume_id, const dare_slice_spec* spec, float* host_out,
                                uint64_t* ticket) {
     if (!S || !host_out || !ticket) return DARE_ERR_INVALID_ARG;
-    const dare_status st = check_slice_spec(spec);
-    if (st != DARE_OK) return st;
     std::lock_guard<std::mutex> lk(S->mu);
-    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
-    Request r;
-    r.vol = volume_id;
-    r.spec = *spec;
-    r.host_out = host_out;
-    r.bytes = (uint64_t)spec->width * spec->height * sizeof(float);
-    r.units = units_of(S->radius, spec->width, spec->height);
-    r.slab = S->radius <= 1 ? slab_floats(S->vols[volume_id], spec) : 0;
-    if (!S->outs.fits_ever(r.bytes) || r.units > S->max_units ||
-        (int64_t)spec->width * spec->height > S->cfg.max_tick_pixels)
+    const dare_status st = submit_locked(S, volume_id, spec, host_out, ticket);
+    if (st == DARE_OK) S->cv.notify_one();
+    return st;
+}
+
+dare_status dare_server_submit_many(dare_server* S, int32_t n, const int32_t* volume_ids, const dare_slice_spec* specs,
+                                    float* const* host_outs, uint64_t* tickets, int32_t* accepted) {
+    if (!S || n < 0 || !accepted || (n > 0 && (!volume_ids || !specs || !host_outs || !tickets)))
         return DARE_ERR_INVALID_ARG;
-    if ((int32_t)S->queue.size() >= S->cfg.max_queue) {
-        S->stats.rejected += 1;
-        return DARE_ERR_QUEUE_FULL;
+    *accepted = 0;
+    std::lock_guard<std::mutex> lk(S->mu);
+    dare_status st = DARE_OK;
+    int k = 0;
+    for (; k < n; ++k) {
+        st = host_outs[k] ? submit_locked(S, volume_ids[k], specs + k, host_outs[k], tickets + k)
+                          : DARE_ERR_INVALID_ARG;
+        if (st != DARE_OK) break;
     }
-    r.t.t_submit = now_s();
-    const uint64_t id = S->next_ticket++;
-    S->reqs.emplace(id, r);
-    S->queue.push_back(id);
-    S->stats.submitted += 1;
-    *ticket = id;
-    S->cv.notify_one();
-    return DARE_OK;
+    *accepted = k;
+    if (k > 0) S->cv.notify_one();
+    return st;
 }
 
 dare_status dare_server_poll(dare_server* S, uint64_t ticket, dare_request_times* times) {
     if (!S) return DARE_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
-    auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return DARE_ERR_INVALID_ARG;
-    const int state = it->second.state;
-    if (state == kWaiting || state == kInFlight) return DARE_ERR_NOT_READY;
-    if (times) *times = it->second.t;
-    S->reqs.erase(it);
-    return state == kDone ? DARE_OK : DARE_ERR_HIP;
+    return poll_locked(S, ticket, times);
+}
+
+dare_status dare_server_poll_many(dare_server* S, int32_t n, const uint64_t* tickets, dare_request_times* times,
+                                  int32_t* states, double wait_seconds, int32_t* n_done) {
+    if (!S || n < 0 || !n_done || (n > 0 && (!tickets || !states))) return DARE_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(wait_seconds > 0.0 ? std::min(wait_seconds, 3600.0) : 0.0));
+    for (;;) {
+        int done = 0;
+        for (int k = 0; k < n; ++k) {
+            states[k] = (int32_t)poll_locked(S, tickets[k], times ? times + k : nullptr);
+            done += states[k] != DARE_ERR_NOT_READY;
+        }
+        *n_done = done;
+        if (done > 0 || n == 0 || !(wait_seconds > 0.0)) return DARE_OK;
+        if (S->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            *n_done = 0;
+            return DARE_OK;
+        }
+    }
 }
 
 dare_status dare_server_drain(dare_server* S) {

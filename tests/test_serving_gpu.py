@@ -139,3 +139,41 @@ def test_submit_rejects_what_can_never_fit(env):
     with pytest.raises(dare.DareError):
         srv.add_volume(other)
     srv.close()
+
+
+def test_grouped_submit_and_poll(env):
+    dare, torch, wl, vols = env
+    note("server grouped submit_many / poll_many with waiting")
+    reqs = _requests(wl, 40, seed=7)
+    ref = _alone(dare, torch, vols, reqs)
+    srv = dare.Server(64 << 20, n_streams=2, max_tick_requests=16, max_queue=24)
+    ids = [srv.add_volume(v) for v in vols]
+    outs = [torch.full((H, W), -5.0, dtype=torch.float32, pin_memory=True) for (_, _, W, H, _) in reqs]
+    specs = dare.spec_array([P for (_, P, _, _, _) in reqs], [W for (_, _, W, _, _) in reqs],
+                            [H for (_, _, _, H, _) in reqs], [p for (_, _, _, _, p) in reqs])
+    vid = np.array([ids[vi] for (vi, _, _, _, _) in reqs], np.int32)
+    ptrs = np.array([o.data_ptr() for o in outs], np.uint64)
+    tickets, k = [], 0
+    while k < len(reqs):               # max_queue 24 < 40: some groups come back partly accepted
+        t, st = srv.submit_many(vid[k:], specs[k:], ptrs[k:])
+        assert st in (dare.OK, dare.ERR_QUEUE_FULL)
+        tickets.extend(int(x) for x in t)
+        k += len(t)
+    assert len(tickets) == len(reqs) and len(set(tickets)) == len(reqs)
+    left = np.array(tickets, np.uint64)
+    seen = 0
+    while len(left):
+        states, times = srv.poll_many(left, wait_seconds=5.0)
+        done = states != dare.ERR_NOT_READY
+        assert done.any()              # the wait returns only once something finished
+        assert (states[done] == dare.OK).all()
+        assert (times["t_submit"][done] <= times["t_host_done"][done]).all()
+        seen += int(done.sum())
+        left = left[~done]
+    assert seen == len(reqs)
+    # retired tickets are unknown afterwards
+    states, _ = srv.poll_many(np.array(tickets[:3], np.uint64))
+    assert (states == dare.ERR_INVALID_ARG).all()
+    srv.close()
+    for k in range(len(reqs)):
+        assert np.array_equal(outs[k].numpy(), ref[k], equal_nan=True), k
