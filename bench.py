@@ -44,7 +44,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dare_reslice.hip", "dare_codec.h", "dare_internal.h"):
+    for f in ("dare_reslice.hip", "dare_reslice_dev.h", "dare_codec.h", "dare_internal.h"):
         with open(os.path.join(ROOT, "paper_2605_26325_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

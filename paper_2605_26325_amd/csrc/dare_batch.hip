@@ -1,0 +1,388 @@
+// Batched reslice: many requests (volumes, poses, sizes) in a fixed set of launches whose
+// counts are read from device memory, so that a captured graph can replay any batch.
+// Radius 1 runs as three passes (setup, voxel slab, pixel); radius >= 2 runs one
+// (request, unit) table through the lane-split neighbourhood kernel.
+#include "dare_reslice_dev.h"
+
+namespace dare {
+
+// ---------------------------------------------------------------- batched passes (radius 1)
+//
+// A batch runs as three flat passes with no workgroup barriers:
+//   setup  one wave per request: pose, Eq. 1 / gates / Eq. 2, plane frame and the
+//          slab of the slice (the voxels within the trilinear support of the plane
+//          over the slice's bounding box, as runs along the normal's dominant axis);
+//   voxel  one thread per slab candidate: all surviving bins gathered at once and
+//          blended into V_v, written to the request's slab in the workspace;
+//   pixel  one thread per output pixel: FP64 position, the 8 cell values from the
+//          slab (mostly L2 hits), tent blend.
+// The per-voxel and per-pixel arithmetic and its order are those of the fused
+// kernel, so a batched request equals the same request resliced alone.
+
+// First voxel of the slab run of column (vp, vq): one below the slab or the grid floor.
+__device__ __forceinline__ int run_start(const SliceSetup& su, int vp, int vq) {
+    const float centre = su.c0[su.dax] - (su.fm[su.pax] * ((float)vp - su.c0[su.pax]) +
+                                          su.fm[su.qax] * ((float)vq - su.c0[su.qax])) * su.inv_md;
+    return max((int)floorf(centre - su.half), 0);
+}
+
+static_assert(kSlabTileP == 8 && kSlabTileQ == 4, "slab tile indexing uses shifts by 3 and 5");
+
+// Position of slab voxel (cp, cq, kk) in the request's slab (the voxel pass writes in this order).
+__device__ __forceinline__ int slab_index(int cp, int cq, int kk, int ntp, int depth) {
+    const int tile = (cq >> 2) * ntp + (cp >> 3);
+    return ((tile * depth + kk) << 5) + ((cq & 3) << 3) + (cp & 7);
+}
+
+// Wave 0: the slab of the whole slice.  Lanes 0..3 place its corner pixels.
+__device__ __forceinline__ void slab_setup(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                           int kact, int64_t v_cap, SliceSetup& su) {
+    const int lane = threadIdx.x;
+    SlicePos q;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.t[a] = T[a * 4 + 3];
+        q.e0[a] = T[a * 4 + 0];
+        q.e1[a] = T[a * 4 + 1];
+        q.o[a] = vd->origin[a];
+    }
+    q.inv_h = vd->inv_h;
+    q.sx = s.sx;
+    q.sy = s.sy;
+    const int k = lane & 3;
+    double c[3];
+    pixel_coords(q, (k & 1) ? s.W - 1 : 0, (k & 2) ? s.H - 1 : 0, c);
+    int lo[3], hi[3];
+    const int n[3] = {vd->nx, vd->ny, vd->nz};
+    float c0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int f = (int)fmin(fmax(floor(c[a]), -1048576.0), 1048576.0);
+        int mn = f, mx = f;
+#pragma unroll
+        for (int o = 1; o < 4; ++o) {
+            const int g = __shfl(f, o, 4);
+            mn = min(mn, g);
+            mx = max(mx, g);
+        }
+        lo[a] = max(mn - 1, 0);
+        hi[a] = min(mx + 2, n[a] - 1);
+        c0[a] = (float)__shfl(c[a], 0, 4);
+    }
+    if (lane != 0) return;
+    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
+    bool empty = false;
+    for (int a = 0; a < 3; ++a) {
+        empty = empty || lo[a] > hi[a];
+        l1m += fabsf(su.fm[a]);
+        l1u += fabsf(su.fu[a]);
+        l1w += fabsf(su.fw[a]);
+        su.c0[a] = c0[a];
+    }
+    const int dax = su.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    su.pax = pax;
+    su.qax = qax;
+    su.lo_p = lo[pax];
+    su.lo_q = lo[qax];
+    su.dim_p = empty ? 0 : hi[pax] - lo[pax] + 1;
+    su.dim_q = empty ? 0 : hi[qax] - lo[qax] + 1;
+    su.len_u = (float)(s.W - 1) * su.lu;
+    su.len_v = (float)(s.H - 1) * su.lw;
+    // FP32 rounding of the tests grows with the coordinates' magnitude
+    const float span = fmaxf(fmaxf(fabsf(c0[0]), fabsf(c0[1])), fabsf(c0[2])) + su.len_u + su.len_v;
+    const float slop = 2e-3f + 1e-6f * span;
+    su.thr_n = l1m + slop;
+    su.thr_u = l1u + 0.02f + slop;
+    su.thr_v = l1w + 0.02f + slop;
+    su.inv_md = 1.0f / su.fm[dax];
+    su.half = su.thr_n * fabsf(su.inv_md);
+    const float dep = ceilf(2.0f * su.half) + 2.0f;
+    su.depth = dep <= (float)kSlabDepthMax ? (int)dep : kSlabDepthMax + 1;
+    su.ntp = (su.dim_p + kSlabTileP - 1) / kSlabTileP;
+    const int ntq = (su.dim_q + kSlabTileQ - 1) / kSlabTileQ;
+    const int64_t ncand = (int64_t)su.ntp * ntq * su.depth * (kSlabTileP * kSlabTileQ);
+    su.staged = (su.depth <= kSlabDepthMax && ncand <= v_cap) ? 1 : 0;
+    su.ncand = (kact > 0 && su.staged) ? (int)ncand : 0;
+}
+
+__global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__ reqs, SliceSetup* __restrict__ setups,
+                                                     int* __restrict__ counts) {
+    const int nreq = counts[1];
+    for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
+        const VolDev* vd = reqs[r].vol;
+        const SliceArgs& s = reqs[r].s;
+        SliceSetup& su = setups[r];
+        double T[12];
+        const int ka = slice_setup(vd, s, su, T);
+        slab_setup(vd, s, T, ka, reqs[r].v_cap, su);
+        if (threadIdx.x == 0) {
+            su.vol = view_of(vd);
+            su.sx = s.sx;
+            su.sy = s.sy;
+            su.W = s.W;
+            su.H = s.H;
+            su.out = s.out;
+            su.v_off = reqs[r].v_off;
+            if (!su.staged) atomicAdd(counts + 2, 1);    // requests left to the per-pixel gather kernel
+        }
+    }
+}
+
+// V_v of voxel (vx, vy, vz) over the surviving bins, straight from the brick pool.
+template <int DT>
+__device__ __forceinline__ float blend_at(const SliceSetup& su, int kact, int vx, int vy, int vz) {
+    using PT = Pair<DT>;
+    const VolView& vv = su.vol;
+    const typename PT::T* __restrict__ data = (const typename PT::T*)vv.data;
+    const int64_t nbricks = vv.nbricks;
+    const int64_t brick = ((int64_t)(vz >> 3) * vv.nby + (vy >> 3)) * vv.nbx + (vx >> 3);
+    const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+    if (kact == 1) {
+        const int slot = vv.table[(int64_t)su.act_bin[0] * nbricks + brick];
+        if (slot < 0) return __builtin_nanf("");
+        float2 sc = make_float2(0.0f, 0.0f);
+        if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[slot];
+        float a, cnt;
+        PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
+        return cnt > 0.0f ? a : __builtin_nanf("");
+    }
+    float A = 0.0f, B = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += kBinChunk) {
+        int sl[kBinChunk];
+        typename PT::T pr[kBinChunk];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u)
+            sl[u] = (k0 + u < kact) ? vv.table[(int64_t)su.act_bin[k0 + u] * nbricks + brick] : -1;
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u)
+            if (sl[u] >= 0) pr[u] = data[(size_t)sl[u] * kBrickVox + local];
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u) {
+            if (sl[u] < 0) continue;
+            float2 sc = make_float2(0.0f, 0.0f);
+            if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[sl[u]];
+            float a, cnt;
+            PT::decode(pr[u], sc, a, cnt);
+            const float wc = su.act_w[k0 + u] * cnt;
+            A = __builtin_fmaf(wc, a, A);
+            B = B + wc;
+        }
+    }
+    return B > 0.0f ? A / B : __builtin_nanf("");
+}
+
+// The passes run over flat index spaces in blocks of kFlatBlock: each request's range starts on
+// a block boundary, so a workgroup iteration belongs to one request and everything it reads of
+// that request (setup record, volume view) is uniform; each thread takes kFlatBlock / 256
+// elements of the block, so that this uniform work is shared by as many.  Each workgroup
+// first copies the requests' first blocks into LDS; the request of block b is then the last r
+// with first(r) <= b, found by a binary search in LDS.
+template <bool VOX>
+__device__ __forceinline__ int load_begins(const BatchReq* __restrict__ reqs, const int* __restrict__ counts,
+                                           int* s_beg) {
+    const int nreq = counts[1];
+    for (int i = threadIdx.x; i < nreq; i += blockDim.x)
+        s_beg[i] = (int)((VOX ? reqs[i].v_beg : reqs[i].p_beg) >> kFlatShift);
+    __syncthreads();
+    return nreq;
+}
+
+__device__ __forceinline__ int find_req(const int* s_beg, int nreq, int blk) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_beg[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    return uniform_i32(lo);
+}
+
+// One slab candidate: the plane-slab and lateral tests, then V_v over the surviving bins.
+template <int DT>
+__device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* __restrict__ scratch) {
+    const int dax = su.dax, pax = su.pax;
+    const int nd = su.vol.n[dax];
+    // slab order: column tiles of kSlabTileP x kSlabTileQ (p fastest), each with all its
+    // depth layers, so that a workgroup consumes whole brick rows and a pixel's 8 cell
+    // values share a few cache lines
+    const int w = e & (kSlabTileP * kSlabTileQ - 1), rest = e >> 5;
+    const int k = rest % su.depth, tile = rest / su.depth;
+    const int cp = (tile % su.ntp) * kSlabTileP + (w & (kSlabTileP - 1));
+    const int cq = (tile / su.ntp) * kSlabTileQ + (w >> 3);
+    const int vp = su.lo_p + cp, vq = su.lo_q + cq;
+    const int vdd = run_start(su, vp, vq) + k;
+    float V = __builtin_nanf("");
+    if (cp < su.dim_p && cq < su.dim_q && vdd < nd) {
+        const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
+        const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
+        const int vz = dax == 2 ? vdd : (pax == 2 ? vp : vq);
+        const float d0 = (float)vx - su.c0[0], d1 = (float)vy - su.c0[1], d2 = (float)vz - su.c0[2];
+        const float dn = su.fm[0] * d0 + su.fm[1] * d1 + su.fm[2] * d2;
+        const float du = su.fu[0] * d0 + su.fu[1] * d1 + su.fu[2] * d2;
+        const float dv = su.fw[0] * d0 + su.fw[1] * d1 + su.fw[2] * d2;
+        if (fabsf(dn) < su.thr_n && du > -su.thr_u && du < su.len_u + su.thr_u && dv > -su.thr_v &&
+            dv < su.len_v + su.thr_v)
+            V = blend_at<DT>(su, su.kact, vx, vy, vz);
+    }
+    scratch[su.v_off + e] = V;
+}
+
+template <int DT>
+__global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__ reqs,
+                                                    const SliceSetup* __restrict__ setups, float* __restrict__ scratch,
+                                                    const int* __restrict__ counts) {
+    extern __shared__ int s_beg[];
+    const int nreq = load_begins<true>(reqs, counts, s_beg);
+    const int nblk = (int)(reinterpret_cast<const int64_t*>(counts + 4)[0] >> kFlatShift);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int r = find_req(s_beg, nreq, blk);
+        const SliceSetup& su = setups[r];
+        const int e0 = ((blk - s_beg[r]) << kFlatShift) + (int)threadIdx.x;
+        for (int u = 0; u < kFlatBlock; u += 256)
+            if (e0 + u < su.ncand) voxel_elem<DT>(su, e0 + u, scratch);
+    }
+}
+
+// Pixels of staged requests (STAGED) or of requests that gather per pixel (!STAGED): two
+// kernels, so that the staged one keeps the register budget of its 8 slab reads.  A kernel
+// skips the other kind's requests one whole range at a time.
+template <int DT, bool STAGED>
+__global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__ reqs,
+                                                    const SliceSetup* __restrict__ setups,
+                                                    const float* __restrict__ scratch, const int* __restrict__ counts) {
+    if (!STAGED && counts[2] == 0) return;             // every request of the batch is staged
+    extern __shared__ int s_beg[];
+    const int nreq = load_begins<false>(reqs, counts, s_beg);
+    const int nblk = (int)(reinterpret_cast<const int64_t*>(counts + 4)[1] >> kFlatShift);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int r = find_req(s_beg, nreq, blk);
+        const SliceSetup& su = setups[r];
+        if ((su.staged != 0) != STAGED) {
+            if (r + 1 >= nreq) break;
+            const int next = s_beg[r + 1];            // first block of the next request
+            blk += (next - blk + (int)gridDim.x - 1) / (int)gridDim.x * (int)gridDim.x - (int)gridDim.x;
+            continue;
+        }
+        const int W = su.W;
+        const int p0 = ((blk - s_beg[r]) << kFlatShift) + (int)threadIdx.x;
+        for (int p = p0; p < p0 + kFlatBlock; p += 256) {
+        if (p >= W * su.H) break;
+        const int j = p / W, i = p - j * W;
+        float* out = su.out + p;
+        const int kact = su.kact;
+        SlicePos q;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q.t[a] = su.T[a * 4 + 3];
+            q.e0[a] = su.T[a * 4 + 0];
+            q.e1[a] = su.T[a * 4 + 1];
+            q.o[a] = su.vol.origin[a];
+        }
+        q.inv_h = su.vol.inv_h;
+        q.sx = su.sx;
+        q.sy = su.sy;
+        const int n[3] = {su.vol.n[0], su.vol.n[1], su.vol.n[2]};
+        double c[3];
+        pixel_coords(q, i, j, c);
+        if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
+                           c[2] >= -1.0 && c[2] < (double)n[2])) {
+            *out = __builtin_nanf("");
+            continue;
+        }
+        if constexpr (!STAGED) {
+            *out = pixel_direct<DT, 2>(su.vol, su, kact, c);
+            continue;
+        } else {
+        if (su.ncand == 0) {        // unreachable: a pixel inside the grid implies a non-empty slab
+            *out = __builtin_nanf("");
+            continue;
+        }
+        const float* __restrict__ slab = scratch + su.v_off;
+        const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
+        const int b0[3] = {(int)f0, (int)f1, (int)f2};
+        const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
+        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+        const int pax = su.pax, qax = su.qax, dax = su.dax;
+        const int depth = su.depth, ntp = su.ntp, last = su.ncand - 1;
+        // corners inside the grid, as a bit mask over c8 = (dz << 2) | (dy << 1) | dx
+        const unsigned mx = ((unsigned)b0[0] < (unsigned)n[0] ? 0x55u : 0u) |
+                            ((unsigned)(b0[0] + 1) < (unsigned)n[0] ? 0xAAu : 0u);
+        const unsigned my = ((unsigned)b0[1] < (unsigned)n[1] ? 0x33u : 0u) |
+                            ((unsigned)(b0[1] + 1) < (unsigned)n[1] ? 0xCCu : 0u);
+        const unsigned mz = ((unsigned)b0[2] < (unsigned)n[2] ? 0x0Fu : 0u) |
+                            ((unsigned)(b0[2] + 1) < (unsigned)n[2] ? 0xF0u : 0u);
+        const unsigned inside = mx & my & mz;
+        // the cell's 4 columns (offsets along p, q): slab index of layer b0[dax]; the next layer
+        // along the dominant axis is 32 floats further.  A voxel with weight inside the grid
+        // always lies in the slab, so only a clamp keeps the other corners' reads in bounds.
+        const int bp = b0[pax], bq = b0[qax], bd = b0[dax];
+        int base[4];
+#pragma unroll
+        for (int col = 0; col < 4; ++col) {
+            const int vp = bp + (col & 1), vq = bq + (col >> 1);
+            base[col] = slab_index(vp - su.lo_p, vq - su.lo_q, bd - run_start(su, vp, vq), ntp, depth);
+        }
+        float tw[8], Vc[8];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {
+            const int od = (c8 >> dax) & 1, col = ((c8 >> pax) & 1) | (((c8 >> qax) & 1) << 1);
+            const int ix = min(max(base[col] + (od << 5), 0), last);
+            Vc[c8] = slab[ix];
+            // absent corners get weight 0 and are skipped like the fused kernel's
+            tw[c8] = ((inside >> c8) & 1u) ? (wx[c8 & 1] * wy[(c8 >> 1) & 1]) * wz[c8 >> 2] : 0.0f;
+        }
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {
+            const bool use = tw[c8] > 0.0f && Vc[c8] == Vc[c8];
+            num = use ? __builtin_fmaf(tw[c8], Vc[c8], num) : num;
+            den = use ? den + tw[c8] : den;
+        }
+        *out = den > 0.0f ? num / den : __builtin_nanf("");
+        }
+        }
+    }
+}
+
+template <int DT, int G>
+__global__ void __launch_bounds__(256) k_reslice_rn_batch(const BatchReq* __restrict__ reqs,
+                                                          const int2* __restrict__ units,
+                                                          const int* __restrict__ counts) {
+    __shared__ SetupLds sh;
+    const int n = counts[0];
+    for (int u = blockIdx.x; u < n; u += gridDim.x) {
+        const int r = __builtin_amdgcn_readfirstlane(units[u].x);
+        const int t = __builtin_amdgcn_readfirstlane(units[u].y);
+        const BatchReq& rq = reqs[r];
+        reslice_unit_rn<DT, G>(rq.vol, rq.s, t, sh);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
+                                const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream) {
+    const int G = reslice_lanes(radius);
+    const int nreq_grid = nreq_max < 1024 ? nreq_max : 1024;
+    const size_t lds = (size_t)nreq_max * sizeof(int);
+#define V1(D) hipLaunchKernelGGL(k_voxel_pass<D>, dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts)
+#define P1(D)                                                                                                  \
+    hipLaunchKernelGGL((k_pixel_pass<D, true>), dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts); \
+    hipLaunchKernelGGL((k_pixel_pass<D, false>), dim3(grid), dim3(256), lds, stream, reqs, setups, scratch, counts)
+#define B16(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 16>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
+#define B64(D) hipLaunchKernelGGL((k_reslice_rn_batch<D, 64>), dim3(grid), dim3(256), 0, stream, reqs, units, counts)
+    if (G == 1) {
+        hipLaunchKernelGGL(k_batch_setup, dim3(nreq_grid), dim3(64), 0, stream, reqs, setups, const_cast<int*>(counts));
+        DARE_DISPATCH_DT(dtype, V1)
+        DARE_DISPATCH_DT(dtype, P1)
+    } else if (G == 16) {
+        DARE_DISPATCH_DT(dtype, B16)
+    } else {
+        DARE_DISPATCH_DT(dtype, B64)
+    }
+#undef V1
+#undef P1
+#undef B16
+#undef B64
+    return hipGetLastError();
+}
+
+}  // namespace dare

@@ -257,9 +257,12 @@ int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec) {
         if (lo > hi) return 0;
         d[a] = (int64_t)(hi - lo) + 1;
     }
-    const int64_t cols = std::max(d[0] * d[1], std::max(d[0] * d[2], d[1] * d[2]));
+    // either axis of a pair may be the tile's p (8) or q (4): pad both by 7
+    const int64_t e[3] = {d[0] + kSlabTileP - 1, d[1] + kSlabTileP - 1, d[2] + kSlabTileP - 1};
+    const int64_t cols = std::max(e[0] * e[1], std::max(e[0] * e[2], e[1] * e[2]));
     const int64_t cap = std::min(cols * kSlabDepthMax, (int64_t)kSlabPerPixel * W * H);
-    return (cap + 255) / 256 * 256;
+    // within a request, slab elements are indexed in 32 bits
+    return std::min((cap + kFlatBlock - 1) / kFlatBlock * kFlatBlock, (int64_t)1 << 30);
 }
 
 }  // namespace dare
@@ -467,21 +470,22 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         q.vol = vols[k]->dev;
         q.s = make_args(specs + k, outs_dev[k]);
         if (R <= 1) {
-            // flat ranges padded to whole 256-index blocks (slab capacities already are)
+            // flat ranges padded to whole blocks (slab capacities already are)
             q.v_cap = slab_floats(vols[k], specs + k);
             q.v_beg = g.vox;
             q.v_off = g.vox;
             q.p_beg = g.pix;
             g.vox += q.v_cap;
-            g.pix += ((int64_t)specs[k].width * specs[k].height + 255) / 256 * 256;
+            g.pix += ((int64_t)specs[k].width * specs[k].height + kFlatBlock - 1) / kFlatBlock * kFlatBlock;
         } else {
             const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
             for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
         }
         g.reqs.push_back(q);
     }
-    for (auto& kv : groups)   // flat indices are counted in 32-bit blocks of 256 on the device
-        if (kv.second.vox / 256 >= INT32_MAX || kv.second.pix / 256 >= INT32_MAX) return DARE_ERR_INVALID_ARG;
+    for (auto& kv : groups)   // flat blocks are indexed in 32 bits on the device
+        if ((kv.second.vox >> kFlatShift) >= INT32_MAX || (kv.second.pix >> kFlatShift) >= INT32_MAX)
+            return DARE_ERR_INVALID_ARG;
     char* ws = (char*)workspace_dev;
     for (auto& kv : groups) {
         Group& g = kv.second;

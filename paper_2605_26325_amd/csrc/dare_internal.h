@@ -91,20 +91,25 @@ struct BatchReq {
     SliceArgs s;
     // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
     // (v_beg: first index of this request's slab) and their pixels (p_beg), each request's
-    // range padded to whole blocks of 256.  The slab itself lives at float offset v_off of
-    // the scratch; v_cap floats (a multiple of 256), 0 for none.
+    // range padded to whole blocks of kFlatBlock.  The slab itself lives at float offset v_off
+    // of the scratch; v_cap floats (a multiple of kFlatBlock), 0 for none.
     int64_t v_beg, v_off, v_cap;
     int64_t p_beg;
 };
 
 // Batch header at the start of a workspace: int32 {units, requests, 0, 0}, then int64
-// {slab index total, pixel index total}, both multiples of 256.
+// {slab index total, pixel index total}, both multiples of kFlatBlock.  counts[2] must be uploaded
+// as 0: the setup pass counts there the requests that gather per pixel.
 struct BatchHeader {
     int32_t counts[4];
     int64_t totals[2];
 };
 
+constexpr int kFlatShift = 10;            // batched passes: elements per workgroup iteration ...
+constexpr int kFlatBlock = 1 << kFlatShift;   // ... (4 per thread)
 constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
+constexpr int kSlabTileP = 8;             // slab column tile: 8 along p (a brick row when p is x) ...
+constexpr int kSlabTileQ = 4;             // ... by 4 along q
 constexpr int kSlabPerPixel = 12;         // slab floats per output pixel beyond which pixels gather directly
 
 // What the reslice passes read of a volume header, copied next to the request's
@@ -136,7 +141,8 @@ struct SliceSetup {
     int pax, qax;
     int lo_p, lo_q, dim_p, dim_q;
     int depth;
-    int ncand;                            // dim_p * dim_q * depth, 0 when nothing to stage
+    int ntp;                              // column tiles along p
+    int ncand;                            // tiles * depth * tile columns, 0 when nothing to stage
     int staged;                           // 1: slab staged; 0: gather per pixel
     float c0[3];                          // voxel coordinates of pixel (0, 0)
     float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
@@ -185,8 +191,9 @@ hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceAr
 hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
                                 const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream);
 // Slab floats to reserve for a radius-1 request (0 when its pixels should gather directly):
-// the slice's voxel bounding box, two voxels of margin, over the largest pair of axes,
-// times the deepest run, capped at kSlabPerPixel per pixel.  Defined with the C ABI.
+// the slice's voxel bounding box, two voxels of margin, padded to whole column tiles, over
+// the largest pair of axes, times the deepest run, capped at kSlabPerPixel per pixel.
+// Defined with the C ABI.
 int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec);
 hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream);
 

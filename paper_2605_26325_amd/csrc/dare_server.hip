@@ -209,7 +209,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
         q.v_beg = vox;
         q.p_beg = pflat;
         vox += q.v_cap;
-        pflat += (px + 255) / 256 * 256;          // flat ranges in whole 256-index blocks
+        pflat += (px + kFlatBlock - 1) / kFlatBlock * kFlatBlock;   // flat ranges in whole blocks
         breqs.push_back(q);
         for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
         sl.tickets.push_back(S->queue.front());
