@@ -306,7 +306,6 @@ def main():
     ap.add_argument("--cpu-slices", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--roofline-sample", type=int, default=100)
     ap.add_argument("--latency-sample", type=int, default=200)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "reslice_traffic.json"))
     ap.add_argument("--no-serving", action="store_true")
@@ -394,24 +393,21 @@ def main():
         f"device), {value:.0f} Mpixel/s")
     nan_frac = float(torch.isnan(outs).float().mean().item())
 
-    # ---- roofline of the reslice kernel: per-launch HIP events, algorithmic bytes per launch
-    nroof = min(args.roofline_sample, len(specs))
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nroof)]
-    for k in range(nroof):
-        evs[k][0].record(stream)
-        reslice(vol.handle, spec_refs[k], out_ptrs[k], sh)
-        evs[k][1].record(stream)
-    torch.cuda.synchronize()
-    durs = np.array([a.elapsed_time(b) * 1e-3 for a, b in evs])    # seconds
+    # ---- roofline of the reslice kernel over the timed launches: their average duration is the
+    # event-timed device span of the timed steps divided by the launches in it (back to back on
+    # one stream), and the algorithmic bytes are counted per slice by an untimed pass
+    dev_s = ev0.elapsed_time(ev1) * 1e-3
+    launches = args.steps * len(specs)
+    avg_launch = dev_s / launches
     algo = []
     kacts = []
-    for k in range(nroof):
+    for k in range(len(specs)):
         kact = len(vol.active_bins(sl.probe_poses[k], W, H, pitch)[0])
         nvox = footprint_voxels(torch, sl.probe_poses[k], wl.calib, wl.origin, wl.spacing, wl.dims, W, H, pitch)
         algo.append(4 * W * H + nvox * kact * PAIR_BYTES["f32"])
         kacts.append(kact)
     algo = np.array(algo, dtype=np.float64)
-    achieved = float(algo.sum() / durs.sum() / 1e9)
+    achieved = float(algo.mean() / avg_launch / 1e9)
     traffic = None
     try:
         with open(args.traffic) as fh:
@@ -422,11 +418,11 @@ def main():
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_reslice_r1<fp32>", "avg_launch_us": round(1e6 * float(durs.mean()), 2),
-                "algo_bytes_per_launch": round(float(algo.mean())), "sample_launches": nroof,
+                "kernel": "k_reslice_r1<fp32>", "avg_launch_us": round(1e6 * avg_launch, 2),
+                "algo_bytes_per_launch": round(float(algo.mean())), "launches": launches,
                 "mean_active_bins": round(float(np.mean(kacts)), 2),
                 "bytes_per_px": round(float(algo.mean()) / (W * H), 2)}
-    log(f"roofline: {achieved:.0f} GB/s algorithmic over {nroof} launches, mean {1e6 * durs.mean():.1f} us, "
+    log(f"roofline: {achieved:.0f} GB/s algorithmic over {launches} launches, mean {1e6 * avg_launch:.1f} us, "
         f"{algo.mean() / 1e6:.2f} MB/launch, active bins {np.mean(kacts):.2f}")
 
     # ---- copy bandwidth on this machine (calibrates the roofline and the byte counters)
@@ -452,6 +448,8 @@ def main():
     lat_ptr = ct.c_void_p(lat_out.data_ptr())
 
     def latencies(v, n):
+        if n <= 0:
+            return None
         host = torch.empty((H, W), dtype=torch.float32, pin_memory=True)
         lat, dlat = [], []
         for k in range(n):
@@ -468,7 +466,8 @@ def main():
                 "device_p50": round(percentile(dlat, 50), 4), "device_p99": round(percentile(dlat, 99), 4)}
 
     lat32 = latencies(vol, args.latency_sample)
-    log(f"fp32 latency submit->host p50 {lat32['p50']:.3f} ms p99 {lat32['p99']:.3f} ms")
+    if lat32:
+        log(f"fp32 latency submit->host p50 {lat32['p50']:.3f} ms p99 {lat32['p99']:.3f} ms")
 
     # ---- precision forms and the batched entry point on the same slices
     forms = {}

@@ -2,6 +2,7 @@
 // counts are read from device memory, so that a captured graph can replay any batch.
 // Radius 1 runs as three passes (setup, voxel slab, pixel); radius >= 2 runs one
 // (request, unit) table through the lane-split neighbourhood kernel.
+#include "dare_batch.h"
 #include "dare_reslice_dev.h"
 
 namespace dare {
@@ -115,7 +116,13 @@ __global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__
         double T[12];
         const int ka = slice_setup(vd, s, su, T);
         slab_setup(vd, s, T, ka, reqs[r].v_cap, su);
+        // table offset of every bin slot (0 beyond the survivors: read, then ignored); the
+        // survivors' ids were written by other lanes of this wave
+        __syncthreads();
+        su.act_off[threadIdx.x] = threadIdx.x < ka ? (int64_t)su.act_bin[threadIdx.x] * vd->nbricks : 0;
         if (threadIdx.x == 0) {
+            su.inv_depth = 1.0 / (double)su.depth;
+            su.inv_ntp = 1.0 / (double)(su.ntp > 0 ? su.ntp : 1);
             su.vol = view_of(vd);
             su.sx = s.sx;
             su.sy = s.sy;
@@ -146,26 +153,36 @@ __device__ __forceinline__ float blend_at(const SliceSetup& su, int kact, int vx
         PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
         return cnt > 0.0f ? a : __builtin_nanf("");
     }
+    // chunk entries beyond the survivors are skipped by uniform branches; a surviving bin with
+    // no brick here still loads (slot 0, which exists) and then adds exactly zero to A and B,
+    // so the sums equal those over the present bins in bin order
     float A = 0.0f, B = 0.0f;
     for (int k0 = 0; k0 < kact; k0 += kBinChunk) {
         int sl[kBinChunk];
         typename PT::T pr[kBinChunk];
+        float2 sc[kBinChunk];
 #pragma unroll
         for (int u = 0; u < kBinChunk; ++u)
-            sl[u] = (k0 + u < kact) ? vv.table[(int64_t)su.act_bin[k0 + u] * nbricks + brick] : -1;
-#pragma unroll
-        for (int u = 0; u < kBinChunk; ++u)
-            if (sl[u] >= 0) pr[u] = data[(size_t)sl[u] * kBrickVox + local];
+            if (k0 + u < kact) sl[u] = vv.table[su.act_off[k0 + u] + brick];
 #pragma unroll
         for (int u = 0; u < kBinChunk; ++u) {
-            if (sl[u] < 0) continue;
-            float2 sc = make_float2(0.0f, 0.0f);
-            if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[sl[u]];
-            float a, cnt;
-            PT::decode(pr[u], sc, a, cnt);
-            const float wc = su.act_w[k0 + u] * cnt;
-            A = __builtin_fmaf(wc, a, A);
-            B = B + wc;
+            if (k0 + u < kact) {
+                const int s0 = max(sl[u], 0);
+                pr[u] = data[(size_t)s0 * kBrickVox + local];
+                sc[u] = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc[u] = vv.scales[s0];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBinChunk; ++u) {
+            if (k0 + u < kact) {
+                float a, cnt;
+                PT::decode(pr[u], sc[u], a, cnt);
+                const bool present = sl[u] >= 0;
+                const float wc = present ? su.act_w[k0 + u] * cnt : 0.0f;
+                A = __builtin_fmaf(wc, present ? a : 0.0f, A);
+                B = B + wc;
+            }
         }
     }
     return B > 0.0f ? A / B : __builtin_nanf("");
@@ -196,6 +213,20 @@ __device__ __forceinline__ int find_req(const int* s_beg, int nreq, int blk) {
     return uniform_i32(lo);
 }
 
+// x = q d + r for 0 <= x < 2^31 and d >= 1, from an FP64 reciprocal of d: the product is within
+// one of the quotient, and one correction step makes it exact.
+__device__ __forceinline__ void divmod(int x, int d, double inv_d, int& q, int& r) {
+    q = (int)((double)x * inv_d);
+    r = x - q * d;
+    if (r < 0) {
+        q -= 1;
+        r += d;
+    } else if (r >= d) {
+        q += 1;
+        r -= d;
+    }
+}
+
 // One slab candidate: the plane-slab and lateral tests, then V_v over the surviving bins.
 template <int DT>
 __device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* __restrict__ scratch) {
@@ -205,9 +236,11 @@ __device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* _
     // depth layers, so that a workgroup consumes whole brick rows and a pixel's 8 cell
     // values share a few cache lines
     const int w = e & (kSlabTileP * kSlabTileQ - 1), rest = e >> 5;
-    const int k = rest % su.depth, tile = rest / su.depth;
-    const int cp = (tile % su.ntp) * kSlabTileP + (w & (kSlabTileP - 1));
-    const int cq = (tile / su.ntp) * kSlabTileQ + (w >> 3);
+    int tile, k, tq, tp;
+    divmod(rest, su.depth, su.inv_depth, tile, k);
+    divmod(tile, su.ntp, su.inv_ntp, tq, tp);
+    const int cp = tp * kSlabTileP + (w & (kSlabTileP - 1));
+    const int cq = tq * kSlabTileQ + (w >> 3);
     const int vp = su.lo_p + cp, vq = su.lo_q + cq;
     const int vdd = run_start(su, vp, vq) + k;
     float V = __builtin_nanf("");

@@ -8,7 +8,7 @@
 #include <map>
 #include <vector>
 
-#include "dare_internal.h"
+#include "dare_batch.h"
 
 using namespace dare;
 

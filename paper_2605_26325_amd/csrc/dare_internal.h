@@ -86,32 +86,6 @@ struct SliceArgs {                        // one reslice request, by value
     float* out;
 };
 
-struct BatchReq {
-    const VolDev* vol;
-    SliceArgs s;
-    // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
-    // (v_beg: first index of this request's slab) and their pixels (p_beg), each request's
-    // range padded to whole blocks of kFlatBlock.  The slab itself lives at float offset v_off
-    // of the scratch; v_cap floats (a multiple of kFlatBlock), 0 for none.
-    int64_t v_beg, v_off, v_cap;
-    int64_t p_beg;
-};
-
-// Batch header at the start of a workspace: int32 {units, requests, 0, 0}, then int64
-// {slab index total, pixel index total}, both multiples of kFlatBlock.  counts[2] must be uploaded
-// as 0: the setup pass counts there the requests that gather per pixel.
-struct BatchHeader {
-    int32_t counts[4];
-    int64_t totals[2];
-};
-
-constexpr int kFlatShift = 10;            // batched passes: elements per workgroup iteration ...
-constexpr int kFlatBlock = 1 << kFlatShift;   // ... (4 per thread)
-constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
-constexpr int kSlabTileP = 8;             // slab column tile: 8 along p (a brick row when p is x) ...
-constexpr int kSlabTileQ = 4;             // ... by 4 along q
-constexpr int kSlabPerPixel = 12;         // slab floats per output pixel beyond which pixels gather directly
-
 // What the reslice passes read of a volume header, copied next to the request's
 // setup so that a workgroup fetches everything it needs in one burst of loads.
 struct VolView {
@@ -125,9 +99,9 @@ struct VolView {
     double inv_h;
 };
 
-// Per-request reslice setup: composed pose, surviving bins and their Eq. 2
-// weights, and the plane frame used by the footprint tests.
-struct SliceSetup {
+// Per-slice reslice setup: composed pose, surviving bins and their Eq. 2 weights, and the
+// plane frame used by the footprint tests.
+struct SliceCore {
     double T[12];                         // rows 0..2 of the image pose T = P . C
     float fm[3], fu[3], fw[3];            // unit normal and in-plane unit axes, voxel units
     float lu, lw;                         // voxels per pixel step along the two in-plane axes
@@ -135,23 +109,6 @@ struct SliceSetup {
     int kact;                             // surviving bins
     int act_bin[kMaxBins];
     float act_w[kMaxBins];
-    // slab of the whole slice (batched passes): voxels within the trilinear support of the
-    // plane, enumerated as runs of `depth` voxels along the dominant axis, one run per column
-    // of the other two axes (pax fastest) over the slice's bounding box
-    int pax, qax;
-    int lo_p, lo_q, dim_p, dim_q;
-    int depth;
-    int ntp;                              // column tiles along p
-    int ncand;                            // tiles * depth * tile columns, 0 when nothing to stage
-    int staged;                           // 1: slab staged; 0: gather per pixel
-    float c0[3];                          // voxel coordinates of pixel (0, 0)
-    float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
-    // copies of the request and its volume (batched passes)
-    VolView vol;
-    double sx, sy;
-    int32_t W, H;
-    float* out;
-    int64_t v_off;
 };
 
 inline int pair_bytes(int dtype) {
@@ -186,15 +143,6 @@ hipError_t launch_download_sums(const VolDev* vd, uint32_t* S, uint32_t* C, int 
 hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float* C, int K, int nx, int ny,
                                    int nz, hipStream_t stream);
 hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream);
-// nreq_max bounds the requests of any batch launched with these arguments (the count itself is
-// read from `counts` on the device, so a captured graph can be replayed with fewer).
-hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream);
-// Slab floats to reserve for a radius-1 request (0 when its pixels should gather directly):
-// the slice's voxel bounding box, two voxels of margin, padded to whole column tiles, over
-// the largest pair of axes, times the deepest run, capped at kSlabPerPixel per pixel.
-// Defined with the C ABI.
-int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec);
 hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream);
 
 // Reslice work decomposition: lanes per output pixel (1 for radius 1) and the

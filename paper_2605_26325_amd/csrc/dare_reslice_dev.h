@@ -15,7 +15,7 @@ namespace dare {
 namespace {
 
 
-using SetupLds = SliceSetup;
+using SetupLds = SliceCore;
 
 __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];

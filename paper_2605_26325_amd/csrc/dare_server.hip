@@ -24,7 +24,7 @@
 #include <vector>
 
 #include "dare_alloc.h"
-#include "dare_internal.h"
+#include "dare_batch.h"
 
 using namespace dare;
 
