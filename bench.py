@@ -208,6 +208,8 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
         nb = ((N + 7) // 8) ** 3
         v = dare.Volume(geom, dare.default_params(), dtype="bf16", bricks=nb * 40)
         v.reconstruct(fr, poses, wl.sweep.pitch)
+        if not vols:
+            frames0 = fr.cpu().numpy()          # the oracle checks a sample of this volume's results
         del fr, poses
         vols.append(v)
         wls.append(wl)
@@ -229,7 +231,11 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
             srv.drain()
             srv.poll(t)
 
-    def run(duration):
+    sample_rng = np.random.default_rng(7)
+    served_sample = []                          # (pose, n, pitch, result) of requests on volume 0
+    sampled = {}
+
+    def run(duration, keep_sample=False):
         """Open loop: each console submits at Poisson arrivals of `rate` per second."""
         rate = 30.0
         next_t = [time.perf_counter() + rng.exponential(1.0 / rate) for _ in range(64)]
@@ -248,6 +254,9 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
                 k, n = pending.pop(int(tk[j]))
                 if states[j] != dare.OK:
                     raise dare.DareError(int(states[j]), "served request")
+                if int(tk[j]) in sampled:
+                    P_s, pitch_s, buf_s = sampled.pop(int(tk[j]))
+                    served_sample.append((P_s, n, pitch_s, buf_s[:n * n].numpy().reshape(n, n).copy()))
                 lat[n].append(1e3 * (times["t_host_done"][j] - times["t_submit"][j]))
                 dev_lat.append(1e3 * (times["t_device_done"][j] - times["t_submit"][j]))
                 px += n * n
@@ -267,6 +276,9 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
                 t = srv.submit(c.vol_id, P, n, n, pitch, buf)
                 if t is not None:
                     pending[t] = (k, n)
+                    if (keep_sample and c.vol_id == ids[0] and len(served_sample) + len(sampled) < 4
+                            and sample_rng.random() < 0.02):
+                        sampled[t] = (P, pitch, buf)
                 next_t[k] += rng.exponential(1.0 / rate)
             if pending:
                 tk = np.fromiter(pending.keys(), np.uint64, len(pending))
@@ -288,13 +300,14 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
                 "mean_requests_per_tick": round(len(alll) / max(1, st1.ticks - st0.ticks), 2),
                 "busy_fraction": round((st1.busy_seconds - st0.busy_seconds) / el, 3)}
 
-    offered = run(seconds)
+    offered = run(seconds, keep_sample=True)
     log(f"serving at 64 x 30 Hz: {offered}")
     sat = run_closed(srv, consoles, bufs, ring, sizes, sat_seconds, synth)
     log(f"serving saturated (closed loop, 2 in flight per console, grouped submit/poll): {sat}")
     srv.close()
-    return {"volumes": [list(w.dims) for w in wls], "dtype": "bf16", "consoles": 64, "rate_hz_per_console": 30,
-            "sizes": list(sizes), "offered": offered, "saturation": sat}
+    res = {"volumes": [list(w.dims) for w in wls], "dtype": "bf16", "consoles": 64, "rate_hz_per_console": 30,
+           "sizes": list(sizes), "offered": offered, "saturation": sat}
+    return res, {"workload": wls[0], "frames": frames0, "items": served_sample}
 
 
 def main():
@@ -525,19 +538,80 @@ def main():
             log(f"{dt} batched x64: {mpx:.0f} Mpixel/s")
             del outs_b, wss
 
-    # ---- the FP64 oracle on the host cores: bounded sample of the same workload
+    # ---- radius sweep: one launch per slice at R = 1, 2, 4 voxels (0.125, 0.25, 0.5 mm), first 100 slices
+    radius = None
+    if not args.no_forms:
+        radius = {}
+        nr = min(100, len(specs))
+        rad_out = torch.empty((H, W), dtype=torch.float32, device=dev)    # the sweep's own output
+        rad_ptr = ct.c_void_p(rad_out.data_ptr())
+        for R in (1, 2, 4):
+            vR = dare.Volume(geom, dare.default_params(radius_vox=float(R)), dtype="f32", bricks=nb * 40)
+            vR.reconstruct(frames, poses, pitch_f)
+            for k in range(nr):
+                reslice(vR.handle, spec_refs[k], rad_ptr, sh)
+            torch.cuda.synchronize()
+            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e_a.record(stream)
+            for k in range(nr):
+                reslice(vR.handle, spec_refs[k], rad_ptr, sh)
+            e_b.record(stream)
+            torch.cuda.synchronize()
+            ms = e_a.elapsed_time(e_b) / nr
+            radius[f"R{R}"] = {"radius_mm": R * wl.spacing, "neighbourhood_voxels": (2 * R) ** 3,
+                               "ms_per_slice": round(ms, 4), "Mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1)}
+            log(f"radius {R} ({R * wl.spacing} mm): {ms * 1e3:.1f} us per 512^2 slice")
+            del vR
+        torch.cuda.synchronize()
+        del rad_out
+
+    # GPU results on the oracle's sample, kept before the serving form frees the volumes
+    ncs = min(args.cpu_slices, len(specs))
+    sample_out = {}
+    if not args.no_cpu_baseline:
+        sample_out["fp32"] = outs[:ncs].cpu().numpy().astype(np.float64)
+        for name, v in form_vols.items():
+            o = torch.empty((ncs, H, W), dtype=torch.float32, device=dev)
+            for k in range(ncs):
+                reslice(v.handle, spec_refs[k], ct.c_void_p(o[k].data_ptr()), sh)
+            torch.cuda.synchronize()
+            sample_out[name] = o.cpu().numpy().astype(np.float64)
+
+    # ---- serving form: continuous batching under console load
+    serving, served_sample = None, None
+    if not args.no_serving:
+        form_vols.clear()
+        del outs
+        torch.cuda.empty_cache()
+        serving, served_sample = run_serving(dare, torch, synth, args.serving_seconds, args.saturation_seconds, log)
+
+    # ---- the FP64 oracle on the host cores: bounded samples of the same workloads
     cpu_baseline = None
     if not args.no_cpu_baseline:
         from oracle import compound, reslice as oreslice
         from oracle.reslice import Params as OParams
         oprm = OParams()
+
+        def err_stats(got_list, ref_list):
+            worst, acc, cnt, mask_ok = 0.0, 0.0, 0, True
+            for got, ref in zip(got_list, ref_list):
+                m = ~np.isnan(ref)
+                mask_ok &= bool(np.array_equal(np.isnan(got), np.isnan(ref)))
+                if m.any():
+                    d = np.abs(got[m] - ref[m])
+                    worst = max(worst, float(d.max()))
+                    acc += float(d.sum())
+                    cnt += int(m.sum())
+            return {"max_abs_grey": round(worst, 5), "mean_abs_grey": round(acc / max(cnt, 1), 6),
+                    "nan_mask_equal": mask_ok, "pixels": cnt}
+
+        # config 2: compounding of every frame, then the timed sample of slices
         fr_host = frames.cpu().numpy()
         t = time.perf_counter()
         g = compound.empty_grid(wl.origin, wl.spacing, wl.dims, oprm.bin_tol_deg, oprm.max_bins)
         compound.compound(g, fr_host, wl.sweep.probe_poses, wl.calib, pitch_f)
         t_comp = time.perf_counter() - t
         log(f"oracle compounding of {F} frames: {t_comp:.1f} s, {g.K} bins")
-        ncs = min(args.cpu_slices, len(specs))
         t = time.perf_counter()
         a64, c64 = g.mean_count()
         rep_n, rep_x = g.codebook.arrays()
@@ -545,41 +619,66 @@ def main():
                                  pitch, oprm) for k in range(ncs)]
         t_res = time.perf_counter() - t
         cpu_mpx = ncs * W * H / t_res / 1e6
-        errs = {}
-        for name, o in (("fp32", outs), *((k, None) for k in form_vols)):
-            if o is None:
-                o = torch.empty((ncs, H, W), dtype=torch.float32, device=dev)
-                for k in range(ncs):
-                    reslice(form_vols[name].handle, spec_refs[k], ct.c_void_p(o[k].data_ptr()), sh)
-                torch.cuda.synchronize()
-            worst, mean_acc, cnt, mask_ok = 0.0, 0.0, 0, True
-            for k in range(ncs):
-                got = o[k].cpu().numpy().astype(np.float64)
-                m = ~np.isnan(refs[k])
-                mask_ok &= bool(np.array_equal(np.isnan(got), np.isnan(refs[k])))
-                if m.any():
-                    d = np.abs(got[m] - refs[k][m])
-                    worst = max(worst, float(d.max()))
-                    mean_acc += float(d.sum())
-                    cnt += int(m.sum())
-            errs[name] = {"max_abs_grey": round(worst, 5), "mean_abs_grey": round(mean_acc / max(cnt, 1), 6),
-                          "nan_mask_equal": mask_ok}
+        errs = {name: err_stats(list(o), refs) for name, o in sample_out.items()}
+        del g, a64, c64, fr_host
+        log(f"oracle: {cpu_mpx:.3f} Mpixel/s ({t_res / ncs:.2f} s per slice); errors {errs}")
+
+        # config 3: the config-1 volume in every storage form, 512^2 slices at 0.0625 mm
+        wl1 = synth.config1()
+        fr1 = wl1.render(dev)
+        poses1 = torch.from_numpy(np.ascontiguousarray(wl1.sweep.probe_poses, np.float32)).to(dev)
+        geom1 = dare.make_geometry(wl1.origin, wl1.spacing, wl1.dims, wl1.calib)
+        nb1 = 1
+        for d in wl1.dims:
+            nb1 *= (d + 7) // 8
+        sl3 = synth.config3_slices(wl1)
+        n3 = 16
+        t = time.perf_counter()
+        g1 = compound.empty_grid(wl1.origin, wl1.spacing, wl1.dims, oprm.bin_tol_deg, oprm.max_bins)
+        compound.compound(g1, fr1.cpu().numpy(), wl1.sweep.probe_poses, wl1.calib, wl1.sweep.pitch)
+        a1, c1 = g1.mean_count()
+        rn1, rx1 = g1.codebook.arrays()
+        refs3 = [oreslice.reslice(a1, c1, g1.origin, g1.spacing, rn1, rx1, wl1.calib, sl3.probe_poses[k],
+                                  sl3.width, sl3.height, sl3.pitch, oprm) for k in range(n3)]
+        t3 = time.perf_counter() - t
+        prec = {}
+        for dt in ("f32", "bf16", "f16", "fp8"):
+            v1 = dare.Volume(geom1, dare.default_params(), dtype=dt, bricks=nb1 * 8)
+            v1.reconstruct(fr1, poses1, wl1.sweep.pitch)
+            got = [v1.reslice(sl3.probe_poses[k], sl3.width, sl3.height, sl3.pitch).cpu().numpy().astype(np.float64)
+                   for k in range(n3)]
+            prec["fp32" if dt == "f32" else dt] = err_stats(got, refs3)
+            del v1
+        log(f"config-3 precision ({n3} slices 512^2 @0.0625 mm on the config-1 volume): {prec}")
+
+        # served BF16 results (a seeded sample of requests on the 128^3 volume) against the oracle
+        served_err = None
+        if served_sample and served_sample["items"]:
+            ws = served_sample["workload"]
+            gs = compound.empty_grid(ws.origin, ws.spacing, ws.dims, oprm.bin_tol_deg, oprm.max_bins)
+            compound.compound(gs, served_sample["frames"], ws.sweep.probe_poses, ws.calib, ws.sweep.pitch)
+            a_s, c_s = gs.mean_count()
+            rn_s, rx_s = gs.codebook.arrays()
+            got_s, ref_s = [], []
+            for P_s, n_s, pitch_s, res in served_sample["items"]:
+                ref_s.append(oreslice.reslice(a_s, c_s, gs.origin, gs.spacing, rn_s, rx_s, ws.calib, P_s, n_s, n_s,
+                                              pitch_s, oprm))
+                got_s.append(res.astype(np.float64))
+            served_err = err_stats(got_s, ref_s)
+            served_err["requests"] = [int(it[1]) for it in served_sample["items"]]
+            log(f"served BF16 vs FP64 oracle ({len(got_s)} sampled requests, 128^3 volume): {served_err}")
+
         cpu_baseline = {"value": round(cpu_mpx, 4), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
                         "sample": f"FP64 NumPy oracle reslicing {ncs} of the {len(specs)} 512x512 slices "
                                   f"({ncs * W * H} pixels, {t_res:.1f} s) on its own grid; compounding all {F} "
                                   f"frames took {t_comp:.1f} s and is not in the rate",
                         "seconds_per_slice": round(t_res / ncs, 3),
                         "compound_seconds": round(t_comp, 2),
-                        "gpu_error_vs_fp64_on_sample": errs}
-        log(f"oracle: {cpu_mpx:.3f} Mpixel/s ({t_res / ncs:.2f} s per slice); errors {errs}")
-
-    # ---- serving form: continuous batching under console load
-    serving = None
-    if not args.no_serving:
-        form_vols.clear()
-        del outs
-        torch.cuda.empty_cache()
-        serving = run_serving(dare, torch, synth, args.serving_seconds, args.saturation_seconds, log)
+                        "gpu_error_vs_fp64_on_sample": errs,
+                        "config3_precision": {"slices": n3, "slice_px": [sl3.width, sl3.height],
+                                              "pitch_mm": list(sl3.pitch), "oracle_seconds": round(t3, 1),
+                                              "per_dtype": prec},
+                        "served_bf16_vs_fp64": served_err}
 
     result = {
         "metric": "reslice Mpixel/s + p50/p99 latency, served BF16 vs plain FP32; % HBM roofline",
@@ -605,6 +704,7 @@ def main():
                         "frames_per_s": round(F / float(np.median(recon_times)), 1),
                         "input_Mpx_s": round(F * Wf * Hf / float(np.median(recon_times)) / 1e6, 1)},
         "forms": forms,
+        "radius_sweep": radius,
         "serving": serving,
         "cpu_baseline": cpu_baseline,
     }
