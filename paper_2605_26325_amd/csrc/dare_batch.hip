@@ -2,7 +2,7 @@
 // counts are read from device memory, so that a captured graph can replay any batch.
 // Radius 1 runs as three passes (setup, voxel slab, pixel); radius >= 2 runs one
 // (request, unit) table through the lane-split neighbourhood kernel.
-#include "dare_batch.h"
+#include "dare_staged.h"
 #include "dare_reslice_dev.h"
 
 namespace dare {
@@ -406,6 +406,8 @@ hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, Sli
         hipLaunchKernelGGL(k_batch_setup, dim3(nreq_grid), dim3(64), 0, stream, reqs, setups, const_cast<int*>(counts));
         DARE_DISPATCH_DT(dtype, V1)
         DARE_DISPATCH_DT(dtype, P1)
+    } else if (staged_radius(radius)) {
+        return launch_reslice_staged_batch(dtype, radius, reqs, units, counts, grid, stream);
     } else if (G == 16) {
         DARE_DISPATCH_DT(dtype, B16)
     } else {

@@ -8,7 +8,7 @@
 #include <map>
 #include <vector>
 
-#include "dare_batch.h"
+#include "dare_staged.h"
 
 using namespace dare;
 
@@ -226,7 +226,7 @@ std::map<std::pair<int, int>, GroupSize> group_sizes(const dare_volume* const* v
         GroupSize& c = cnt[{vols[k]->dtype, R}];
         c.nreq += 1;
         if (R <= 1) c.slab += slab_floats(vols[k], specs + k);
-        else c.nunits += (size_t)reslice_units(R, specs[k].width, specs[k].height);
+        else c.nunits += (size_t)batch_units(R, specs[k].width, specs[k].height);
     }
     return cnt;
 }
@@ -429,7 +429,9 @@ dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, floa
     if (st != DARE_OK) return st;
     DeviceGuard dg(v->device);
     const SliceArgs a = make_args(spec, out_dev);
-    return hip_status(launch_reslice(v->dev, v->dtype, (int)v->p.radius_vox, a, (hipStream_t)stream));
+    const int R = (int)v->p.radius_vox;
+    if (staged_radius(R)) return hip_status(launch_reslice_staged(v->dev, v->dtype, R, a, (hipStream_t)stream));
+    return hip_status(launch_reslice(v->dev, v->dtype, R, a, (hipStream_t)stream));
 }
 
 
@@ -478,7 +480,7 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
             g.vox += q.v_cap;
             g.pix += ((int64_t)specs[k].width * specs[k].height + kFlatBlock - 1) / kFlatBlock * kFlatBlock;
         } else {
-            const int64_t u = reslice_units(R, specs[k].width, specs[k].height);
+            const int64_t u = batch_units(R, specs[k].width, specs[k].height);
             for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
         }
         g.reqs.push_back(q);

@@ -24,7 +24,7 @@
 #include <vector>
 
 #include "dare_alloc.h"
-#include "dare_batch.h"
+#include "dare_staged.h"
 
 using namespace dare;
 
@@ -50,7 +50,7 @@ double now_s() {
 }
 
 // Workgroup units of a request: the radius-1 passes index pixels and slabs directly.
-int64_t units_of(int radius, int W, int H) { return radius <= 1 ? 0 : reslice_units(radius, W, H); }
+int64_t units_of(int radius, int W, int H) { return radius <= 1 ? 0 : batch_units(radius, W, H); }
 
 enum ReqState { kWaiting = 0, kInFlight = 1, kDone = 2, kFailed = 3 };
 

@@ -259,6 +259,50 @@ def test_reslice_larger_radius(dare, torch_cuda, R):
         assert_parity(out, ref, what=f"R={R} {W}x{H}")
 
 
+@pytest.mark.parametrize("R", [2, 4])
+def test_larger_radius_config1_staged_and_coarse(dare, torch_cuda, cfg1, cfg1_grid, R):
+    """Radius 2 and 4 on the config-1 grid: a fine slice (tiles staged in LDS, several tiles and
+    a ragged edge) and a coarse one (tiles too wide to stage gather per pixel)."""
+    note(f"config-1 radius {R}, staged and per-pixel tiles")
+    prm = Params(radius_vox=R)
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, prm)
+    upload_grid(vol, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+    a, c = quant.storage(cfg1_grid.S, cfg1_grid.C, "fp32")
+    rn, rx = cfg1_grid.codebook.arrays()
+    for k, (W, H, pitch) in enumerate(((37, 21, (0.25, 0.25)), (12, 10, (2.0, 2.0)))):
+        P = cfg1.slices.probe_poses[k]
+        out = vol.reslice(P, W, H, pitch).cpu().numpy()
+        ref = reslice.reslice(a, c, cfg1.origin, cfg1.spacing, rn, rx, cfg1.calib, P, W, H, pitch, prm)
+        assert_parity(out, ref, what=f"R={R} {W}x{H} pitch {pitch[0]}")
+
+
+def test_batch_equals_alone_larger_radius(dare, torch_cuda, cfg1, cfg1_grid):
+    torch = torch_cuda
+    note("batched reslice at radius 2 and 4 vs one by one")
+    vols = []
+    for R, dt in ((2, "f32"), (4, "bf16"), (2, "fp8")):
+        v = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(radius_vox=R), dtype=dt)
+        upload_grid(v, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+        vols.append(v)
+    sizes = [(48, 40, (0.25, 0.25)), (17, 33, (0.5, 0.4)), (12, 10, (2.0, 2.0)), (1, 1, (1, 1))]
+    reqs = []
+    for k in range(9):
+        W, H, pitch = sizes[k % len(sizes)]
+        reqs.append((vols[k % 3], dare.make_spec(cfg1.slices.probe_poses[k % len(cfg1.slices.probe_poses)], W, H, pitch)))
+    outs = [torch.full((s.height, s.width), -7.0, device="cuda") for _, s in reqs]
+    ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([v for v, _ in reqs], [s for _, s in reqs]),
+                     dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([v for v, _ in reqs], [s for _, s in reqs], outs, ws)
+    alone = []
+    for v, s in reqs:
+        o = torch.full((s.height, s.width), -9.0, device="cuda")
+        dare.dare_reslice(v, s, o)
+        alone.append(o)
+    torch.cuda.synchronize()
+    for k in range(len(reqs)):
+        assert np.array_equal(outs[k].cpu().numpy(), alone[k].cpu().numpy(), equal_nan=True), k
+
+
 def test_empty_volume_reslices_to_nan(dare, torch_cuda, cfg1):
     note("empty volume")
     vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params())
