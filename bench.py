@@ -195,6 +195,105 @@ def run_closed(srv, consoles, bufs, ring, sizes, duration, synth, depth=2, seq_l
             "busy_fraction": round((st1.busy_seconds - st0.busy_seconds) / el, 3)}
 
 
+def run_streaming(dare, torch, synth, seconds, log):
+    """Streaming form: a 512^3 FP16 volume filled through the server from a 30 Hz probe stream
+    of 512^2 frames on a random walk, while 32 consoles request 512^2 slices at 30 Hz each."""
+    dev = torch.device("cuda:0")
+    rate = 30.0
+    wl = synth.config5(seconds=seconds, rate_hz=rate)
+    t0 = time.perf_counter()
+    frames = wl.render(dev)
+    poses = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).to(dev)
+    torch.cuda.synchronize()
+    F, Hf, Wf = frames.shape
+    log(f"streaming: rendered {F} frames {Wf}x{Hf} in {time.perf_counter() - t0:.1f} s")
+    geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+    vol = dare.Volume(geom, dare.default_params(), dtype="f16", bricks=2_000_000)
+    srv = dare.Server(4 << 30, n_streams=3, max_tick_requests=64, max_tick_pixels=16 << 20, max_queue=8192)
+    vid = srv.add_volume(vol)
+    rng = np.random.default_rng(55)
+    consoles = [Console(rng, wl, vid, (512,)) for _ in range(32)]
+    ring = 6
+    bufs = [[torch.empty((512 * 512,), dtype=torch.float32, pin_memory=True) for _ in range(ring)]
+            for _ in range(32)]
+    fr_views = [(frames[f:f + 1], poses[f:f + 1]) for f in range(F)]
+    pending, fpend = {}, {}
+    lat, flat = [], []
+    slot = [0] * 32
+    st0 = srv.stats()
+    t_start = time.perf_counter()
+    next_t = [t_start + rng.exponential(1.0 / rate) for _ in range(32)]
+    last = [t_start] * 32
+    nf = 0
+    while nf < F or pending or fpend:
+        now = time.perf_counter()
+        if nf < F and now >= t_start + nf / rate:
+            t = srv.submit_frames(vid, fr_views[nf][0], fr_views[nf][1], wl.sweep.pitch)
+            if t is not None:
+                fpend[t] = nf
+                nf += 1
+        if nf < F:
+            for k in range(32):
+                if now < next_t[k]:
+                    continue
+                c = consoles[k]
+                P, n, pitch = c.step(max(1e-3, now - last[k]), synth)
+                last[k] = now
+                buf = bufs[k][slot[k] % ring]
+                slot[k] += 1
+                t = srv.submit(vid, P, n, n, pitch, buf)
+                if t is not None:
+                    pending[t] = k
+                next_t[k] += rng.exponential(1.0 / rate)
+        if pending:
+            tk = np.fromiter(pending.keys(), np.uint64, len(pending))
+            states, times = srv.poll_many(tk)
+            for j in np.nonzero(states != dare.ERR_NOT_READY)[0]:
+                pending.pop(int(tk[j]))
+                if states[j] != dare.OK:
+                    raise dare.DareError(int(states[j]), "streamed reslice")
+                lat.append(1e3 * (times["t_host_done"][j] - times["t_submit"][j]))
+        for t in list(fpend):
+            r = srv.poll_frames(t)
+            if r is not None:
+                st, tm = r
+                if st not in (dare.OK, dare.WARN_BINS_SATURATED):
+                    raise dare.DareError(int(st), "streamed frames")
+                fpend.pop(t)
+                flat.append(1e3 * (tm.t_host_done - tm.t_submit))
+    el = time.perf_counter() - t_start
+    st1 = srv.stats()
+    nfr = int(st1.frames - st0.frames)
+    comp_s = float(st1.compound_seconds - st0.compound_seconds)
+    info = vol.info()
+    # flat out: the same stream again into a fresh volume, one job of 30 frames at a time, no consoles
+    vol2 = dare.Volume(geom, dare.default_params(), dtype="f16", bricks=2_000_000)
+    vid2 = srv.add_volume(vol2)
+    t1 = time.perf_counter()
+    jobs = [srv.submit_frames(vid2, frames[a:a + 30].contiguous(), poses[a:a + 30].contiguous(), wl.sweep.pitch)
+            for a in range(0, F, 30)]
+    srv.drain()
+    for t in jobs:
+        srv.poll_frames(t)
+    el2 = time.perf_counter() - t1
+    srv.close()
+    # algorithmic bytes of compounding per input pixel when the pixel pitch equals the voxel size
+    # (FP16 storage): 1 B read, 16 B accumulator read-modify-write, finalize 8 B read + 4 B pair
+    bpp = 1 + 16 + 8 + 4
+    res = {"grid": list(wl.dims), "dtype": "f16", "frame_px": [Wf, Hf], "rate_hz": rate, "seconds": round(el, 2),
+           "frames": nfr, "frames_per_s": round(nfr / el, 1), "bins": int(info.bins),
+           "bricks_used": int(info.bricks_used), "consoles": 32,
+           "reslice_latency_ms": {"p50": round(percentile(lat, 50), 3), "p99": round(percentile(lat, 99), 3),
+                                  "requests": len(lat)},
+           "frame_latency_ms": {"p50": round(percentile(flat, 50), 3), "p99": round(percentile(flat, 99), 3)},
+           "compound_ms_per_frame": round(1e3 * comp_s / max(nfr, 1), 3),
+           "flat_out_frames_per_s": round(F / el2, 1),
+           "compound_algorithmic_GBps": round(F * Wf * Hf * bpp / el2 / 1e9, 1)}
+    del frames, poses, vol, vol2
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_serving(dare, torch, synth, seconds, sat_seconds, log):
     """Serving form: 4 resident BF16 volumes, 64 consoles, Poisson arrivals at 30 Hz each."""
     dev = torch.device("cuda:0")
@@ -324,6 +423,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--saturation-seconds", type=float, default=4.0)
+    ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--streaming-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures one GPU's share of the work "
@@ -585,6 +686,12 @@ def main():
         torch.cuda.empty_cache()
         serving, served_sample = run_serving(dare, torch, synth, args.serving_seconds, args.saturation_seconds, log)
 
+    # ---- streaming form: compounding through the server while consoles reslice
+    streaming = None
+    if not args.no_streaming:
+        streaming = run_streaming(dare, torch, synth, args.streaming_seconds, log)
+        log(f"streaming: {streaming}")
+
     # ---- the FP64 oracle on the host cores: bounded samples of the same workloads
     cpu_baseline = None
     if not args.no_cpu_baseline:
@@ -706,6 +813,7 @@ def main():
         "forms": forms,
         "radius_sweep": radius,
         "serving": serving,
+        "streaming": streaming,
         "cpu_baseline": cpu_baseline,
     }
     print(json.dumps(result), flush=True)

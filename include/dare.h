@@ -248,6 +248,8 @@ typedef struct {
     int64_t ticks;
     int64_t pixels;
     double busy_seconds;      /* host-measured time with at least one tick in flight         */
+    int64_t frames;           /* frames compounded through dare_server_submit_frames         */
+    double compound_seconds;  /* host-measured time spent compounding them                   */
 } dare_server_stats;
 
 typedef struct {
@@ -259,14 +261,29 @@ void dare_default_server_config(dare_server_config* c);
 /* arena_dev: 256-byte aligned device memory, kept allocated until destroy. */
 dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, uint64_t arena_bytes,
                                dare_server** out);
-/* Register a volume; INVALID_ARG if its dtype or radius differs from the first one's. */
-dare_status dare_server_add_volume(dare_server* s, const dare_volume* v, int32_t* volume_id);
+/* Register a volume; INVALID_ARG if its dtype or radius differs from the first one's.  The
+ * server may compound frames into it (dare_server_submit_frames); outside the server the
+ * volume must not be reconstructed while the server can reslice it. */
+dare_status dare_server_add_volume(dare_server* s, dare_volume* v, int32_t* volume_id);
 /* Queue a request.  host_out (required) receives height*width float32,
  * row-major, NaN where unassigned, once the request completes.  Returns
  * QUEUE_FULL when max_queue requests wait, and INVALID_ARG when the request
  * can never fit the arena's result space or one tick. */
 dare_status dare_server_submit(dare_server* s, int32_t volume_id, const dare_slice_spec* spec,
                                float* host_out, uint64_t* ticket);
+/* Queue a batch of tracked frames to compound into served volume `volume_id` (Sec. 2.1
+ * "Volume reconstruction"; the streaming case: a probe keeps scanning while consoles reslice).
+ * It takes its place in the request queue: requests submitted before it never see these
+ * frames, requests submitted after it always do.  When it reaches the head of the queue the
+ * scheduler lets the ticks in flight finish, compounds (dare_reconstruct_frames on one of the
+ * server's streams) and resumes.  frames_dev (n*h*w uint8, row-major) and probe_poses_dev
+ * (n*16 FP32, row-major) are device memory that must stay valid until the ticket completes;
+ * pitch_mm is read before the call returns.  The ticket completes with the compounding status
+ * (OK, WARN_BINS_SATURATED, BUDGET or BAD_POSE with the batch rolled back, HIP), which
+ * dare_server_poll returns.  QUEUE_FULL as for dare_server_submit. */
+dare_status dare_server_submit_frames(dare_server* s, int32_t volume_id, const uint8_t* frames_dev, int32_t n,
+                                      int32_t w, int32_t h, const double pitch_mm[2], const float* probe_poses_dev,
+                                      uint64_t* ticket);
 /* Queue n requests in order under one lock (for gateways that receive
  * requests in groups).  Arrays of n: volume_ids, specs, host_outs (each
  * required); tickets receives one ticket per accepted request.  *accepted is
@@ -277,8 +294,9 @@ dare_status dare_server_submit_many(dare_server* s, int32_t n, const int32_t* vo
                                     const dare_slice_spec* specs, float* const* host_outs,
                                     uint64_t* tickets, int32_t* accepted);
 /* DARE_OK with *times filled (may be NULL) once the result is in host
- * memory, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed.  A
- * ticket is forgotten once poll has returned DARE_OK or DARE_ERR_HIP. */
+ * memory, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed; for a
+ * frames ticket, its compounding status once compounded.  A ticket is
+ * forgotten once poll has returned anything but NOT_READY. */
 dare_status dare_server_poll(dare_server* s, uint64_t ticket, dare_request_times* times);
 /* Poll n tickets at once: states[k] receives what dare_server_poll would
  * return for tickets[k] (times[k] filled when DARE_OK; times may be NULL),

@@ -55,7 +55,8 @@ class ServerConfig(ct.Structure):
 
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("rejected", ct.c_int64),
-                ("ticks", ct.c_int64), ("pixels", ct.c_int64), ("busy_seconds", ct.c_double)]
+                ("ticks", ct.c_int64), ("pixels", ct.c_int64), ("busy_seconds", ct.c_double),
+                ("frames", ct.c_int64), ("compound_seconds", ct.c_double)]
 
 
 class RequestTimes(ct.Structure):
@@ -120,6 +121,7 @@ def _load():
         "dare_server_submit": (ct.c_int, [V, I32, ct.POINTER(SliceSpec), P, ct.POINTER(U64)]),
         "dare_server_poll": (ct.c_int, [V, U64, ct.POINTER(RequestTimes)]),
         "dare_server_submit_many": (ct.c_int, [V, I32, P, P, P, P, ct.POINTER(I32)]),
+        "dare_server_submit_frames": (ct.c_int, [V, I32, P, I32, I32, I32, ct.POINTER(D), P, ct.POINTER(U64)]),
         "dare_server_poll_many": (ct.c_int, [V, I32, P, P, P, D, ct.POINTER(I32)]),
         "dare_server_drain": (ct.c_int, [V]),
         "dare_server_get_stats": (ct.c_int, [V, ct.POINTER(ServerStats)]),
@@ -157,6 +159,11 @@ def _stream(stream):
 
 def _ptr(t) -> ct.c_void_p:
     return ct.c_void_p(t.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
 
 
 def default_params(**over) -> Params:
@@ -376,6 +383,37 @@ class Server:
             return None
         _check(st, "dare_server_submit")
         return t.value
+
+    def submit_frames(self, volume_id: int, frames, probe_poses, pitch):
+        """Queue frames (uint8 (n, h, w), device) with their probe poses (float32 (n, 4, 4),
+        device) for compounding in request order; returns the ticket, or None when the queue is
+        full.  Both tensors must stay alive until the ticket completes (poll returns the
+        compounding status)."""
+        if frames.dtype != _torch().uint8 or not frames.is_cuda or not frames.is_contiguous():
+            raise ValueError("frames: contiguous uint8 device tensor (n, h, w)")
+        if probe_poses.dtype != _torch().float32 or not probe_poses.is_cuda or not probe_poses.is_contiguous():
+            raise ValueError("probe_poses: contiguous float32 device tensor (n, 4, 4)")
+        n, h, w = (int(x) for x in frames.shape)
+        if tuple(probe_poses.shape) != (n, 4, 4):
+            raise ValueError("probe_poses: one 4x4 pose per frame")
+        t = ct.c_uint64()
+        pit = (ct.c_double * 2)(float(pitch[0]), float(pitch[1]))
+        st = lib.dare_server_submit_frames(self.handle, int(volume_id), _ptr(frames), n, w, h, pit,
+                                           _ptr(probe_poses), ct.byref(t))
+        if st == ERR_QUEUE_FULL:
+            return None
+        _check(st, "dare_server_submit_frames")
+        return t.value
+
+    def poll_frames(self, ticket: int):
+        """(status, RequestTimes) once the frames are compounded, else None."""
+        tm = RequestTimes()
+        st = lib.dare_server_poll(self.handle, ct.c_uint64(ticket), ct.byref(tm))
+        if st == ERR_NOT_READY:
+            return None
+        if st == ERR_INVALID_ARG:
+            _check(st, "dare_server_poll")
+        return st, tm
 
     def submit_many(self, volume_ids, specs: np.ndarray, host_out_ptrs):
         """Queue requests in order: volume_ids (n,), specs a SPEC_DTYPE array (n,), host_out_ptrs

@@ -55,6 +55,7 @@ int64_t units_of(int radius, int W, int H) { return radius <= 1 ? 0 : batch_unit
 enum ReqState { kWaiting = 0, kInFlight = 1, kDone = 2, kFailed = 3 };
 
 struct Request {
+    bool frames_job = false;          // a batch of frames to compound, not a reslice
     int vol = 0;
     dare_slice_spec spec{};
     float* host_out = nullptr;
@@ -65,6 +66,12 @@ struct Request {
     uint64_t slab_off = UINT64_MAX;
     int state = kWaiting;
     dare_request_times t{};
+    // frames job: dare_reconstruct_frames arguments and its status
+    const uint8_t* frames = nullptr;
+    const float* poses = nullptr;
+    int32_t nframes = 0, fw = 0, fh = 0;
+    double fpitch[2] = {0.0, 0.0};
+    dare_status status = DARE_OK;
 };
 
 struct Slot {
@@ -90,7 +97,7 @@ struct dare_server {
     int64_t max_units = 0;
     Slot slots[kMaxStreams];
     RangeAlloc outs;
-    std::vector<const dare_volume*> vols;
+    std::vector<dare_volume*> vols;
     int dtype = -1, radius = -1;
     std::mutex mu;
     std::condition_variable cv;       // scheduler: new work or stop
@@ -180,6 +187,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
     std::vector<int2> bunits;
     while (!S->queue.empty() && nreq < S->cfg.max_tick_requests) {
         Request& r = S->reqs[S->queue.front()];
+        if (r.frames_job) break;               // later requests must see the frames: wait for them
         const int64_t px = (int64_t)r.spec.width * r.spec.height;
         if (nreq > 0 && (pixels + px > S->cfg.max_tick_pixels || units + r.units > S->max_units)) break;
         const uint64_t off = S->outs.alloc(r.bytes);
@@ -257,11 +265,47 @@ bool launch_tick(dare_server* S, Slot& sl) {
     return true;
 }
 
+// Compound the frames job at the head of the queue once no tick is in flight (ticks read the
+// volumes; compounding rewrites them).  Caller holds the lock; it is released while the
+// frames are compounded.  Returns true when a job ran.
+bool run_frames_job(dare_server* S, std::unique_lock<std::mutex>& lk) {
+    if (S->queue.empty() || busy_slots(S) > 0) return false;
+    const uint64_t id = S->queue.front();
+    Request& r = S->reqs[id];
+    if (!r.frames_job) return false;
+    r.state = kInFlight;
+    r.t.t_admit = r.t.t_launch = now_s();
+    dare_volume* v = S->vols[r.vol];
+    const uint8_t* frames = r.frames;
+    const float* poses = r.poses;
+    const int32_t n = r.nframes, w = r.fw, h = r.fh;
+    const double pitch[2] = {r.fpitch[0], r.fpitch[1]};
+    hipStream_t stream = S->slots[0].stream;
+    lk.unlock();
+    const double t0 = now_s();
+    dare_status st = dare_reconstruct_frames(v, frames, n, w, h, pitch, poses, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess && (st == DARE_OK || st == DARE_WARN_BINS_SATURATED))
+        st = DARE_ERR_HIP;
+    const double t1 = now_s();
+    lk.lock();
+    Request& rr = S->reqs[id];        // the map may have grown meanwhile
+    rr.status = st;
+    rr.state = (st == DARE_OK || st == DARE_WARN_BINS_SATURATED) ? kDone : kFailed;
+    rr.t.t_device_done = rr.t.t_host_done = t1;
+    S->stats.compound_seconds += t1 - t0;
+    if (rr.state == kDone) S->stats.frames += n;
+    S->stats.completed += 1;
+    S->queue.pop_front();
+    S->done_cv.notify_all();
+    return true;
+}
+
 void scheduler(dare_server* S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     while (!S->stop.load()) {
         reap(S);
+        while (run_frames_job(S, lk)) reap(S);
         for (int k = 0; k < S->cfg.n_streams; ++k) {
             Slot& sl = S->slots[k];
             if (sl.busy) continue;
@@ -321,7 +365,10 @@ dare_status poll_locked(dare_server* S, uint64_t ticket, dare_request_times* tim
     const int state = it->second.state;
     if (state == kWaiting || state == kInFlight) return DARE_ERR_NOT_READY;
     if (times) *times = it->second.t;
+    const bool frames = it->second.frames_job;
+    const dare_status fst = it->second.status;
     S->reqs.erase(it);
+    if (frames) return fst;
     return state == kDone ? DARE_OK : DARE_ERR_HIP;
 }
 
@@ -387,7 +434,7 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
     return DARE_OK;
 }
 
-dare_status dare_server_add_volume(dare_server* S, const dare_volume* v, int32_t* volume_id) {
+dare_status dare_server_add_volume(dare_server* S, dare_volume* v, int32_t* volume_id) {
     if (!S || !v || !volume_id) return DARE_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     if (volume_device_id(v) != S->device) return DARE_ERR_INVALID_ARG;
@@ -417,6 +464,39 @@ dare_status dare_server_submit(dare_server* S, int32_t volume_id, const dare_sli
     const dare_status st = submit_locked(S, volume_id, spec, host_out, ticket);
     if (st == DARE_OK) S->cv.notify_one();
     return st;
+}
+
+dare_status dare_server_submit_frames(dare_server* S, int32_t volume_id, const uint8_t* frames_dev, int32_t n,
+                                      int32_t w, int32_t h, const double pitch_mm[2], const float* probe_poses_dev,
+                                      uint64_t* ticket) {
+    if (!S || !ticket || !pitch_mm || n <= 0 || w <= 0 || h <= 0 || !frames_dev || !probe_poses_dev)
+        return DARE_ERR_INVALID_ARG;
+    if ((int64_t)w * h > (int64_t)1 << 30 || !(pitch_mm[0] > 0.0) || !(pitch_mm[1] > 0.0))
+        return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
+    if ((int32_t)S->queue.size() >= S->cfg.max_queue) {
+        S->stats.rejected += 1;
+        return DARE_ERR_QUEUE_FULL;
+    }
+    Request r;
+    r.frames_job = true;
+    r.vol = volume_id;
+    r.frames = frames_dev;
+    r.poses = probe_poses_dev;
+    r.nframes = n;
+    r.fw = w;
+    r.fh = h;
+    r.fpitch[0] = pitch_mm[0];
+    r.fpitch[1] = pitch_mm[1];
+    r.t.t_submit = now_s();
+    const uint64_t id = S->next_ticket++;
+    S->reqs.emplace(id, r);
+    S->queue.push_back(id);
+    S->stats.submitted += 1;
+    *ticket = id;
+    S->cv.notify_one();
+    return DARE_OK;
 }
 
 dare_status dare_server_submit_many(dare_server* S, int32_t n, const int32_t* volume_ids, const dare_slice_spec* specs,

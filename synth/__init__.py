@@ -17,9 +17,9 @@ from .poses import (  # noqa: F401
 )
 from .phantom import Phantom, make_phantom  # noqa: F401
 from .sweeps import (  # noqa: F401
-    Sweep, linear_tilted_sweeps, azimuth_sweeps, slice_poses, SliceSet,
+    Sweep, linear_tilted_sweeps, azimuth_sweeps, random_walk_sweep, slice_poses, SliceSet,
 )
 from .render import render_frames  # noqa: F401
 from .configs import (  # noqa: F401
-    Workload, config1, config2, config3_slices, serving_volume, tiny_workload,
+    Workload, config1, config2, config3_slices, config5, serving_volume, tiny_workload,
 )

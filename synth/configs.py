@@ -20,7 +20,7 @@ import numpy as np
 from .phantom import Phantom, make_phantom
 from .poses import WORLD_OFFSET_MM, make_calibration
 from .render import render_frames
-from .sweeps import SliceSet, Sweep, azimuth_sweeps, linear_tilted_sweeps, slice_poses
+from .sweeps import SliceSet, Sweep, azimuth_sweeps, linear_tilted_sweeps, random_walk_sweep, slice_poses
 
 
 @dataclass
@@ -84,6 +84,19 @@ def serving_volume(N: int, seed: int, n_frames: int = 600, n_slices: int = 64) -
                      (N * h / 512, N * h / 512), N, h, C)
     return Workload(f"serving volume {N}^3 @0.125mm", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph,
                     sw, sl, frame_seed=seed, params=dict(DEFAULT_PARAMS))
+
+
+def config5(seconds: float = 6.0, rate_hz: float = 30.0, N: int = 512) -> Workload:
+    """The streaming case: an N^3 grid at 0.125 mm filled from a 512^2 probe stream at rate_hz on
+    a random-walk trajectory (5 mm/s, 20 deg/s); consoles reslice 512^2 slices meanwhile."""
+    h, w = 0.125, 512
+    pitch = (N * h / w, N * h / w)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=5, L=N * h, n_sph=30, n_pl=10, shell_mm=h)
+    sw = random_walk_sweep(N, h, int(round(seconds * rate_hz)), w, w, pitch, rate_hz, seed=501, calib=C)
+    sl = slice_poses(502, sw, 64, 51, 512, 512, pitch, N, h, C)
+    return Workload(f"config5: {N}^3 @0.125mm streamed from {w}^2 frames at {rate_hz:g} Hz", (N, N, N), h,
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=5, params=dict(DEFAULT_PARAMS))
 
 
 def tiny_workload(seed: int, N: int = 8, n_frames: int = 6, w: int = 6, n_slices: int = 4,

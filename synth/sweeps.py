@@ -78,6 +78,45 @@ def azimuth_sweeps(N: int, h: float, n_frames: int, width: int, height: int, pit
     return _concat(parts, width, height, pitch)
 
 
+def random_walk_sweep(N: int, h: float, n_frames: int, width: int, height: int, pitch, rate_hz: float,
+                      seed: int, calib: np.ndarray, speed_mm_s: float = 5.0, turn_deg_s: float = 20.0,
+                      tau_s: float = 1.0) -> Sweep:
+    """A freehand probe stream: frames at ``rate_hz`` along a smooth random walk (Ornstein-
+    Uhlenbeck velocity and angular velocity with time constant ``tau_s`` and scales
+    ``speed_mm_s`` / ``turn_deg_s``), starting at the grid centre with the beam along +z and
+    reflected at the grid's inner 70 %."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = (N - 1) * h
+    lo = WORLD_OFFSET_MM + 0.15 * L
+    hi = WORLD_OFFSET_MM + 0.85 * L
+    c = WORLD_OFFSET_MM + 0.5 * L
+    R = np.eye(3)                      # columns: lateral, elevation, beam
+    v = np.zeros(3)
+    w = np.zeros(3)
+    dt = 1.0 / rate_hz
+    a = np.exp(-dt / tau_s)
+    b = np.sqrt(max(0.0, 1.0 - a * a))
+    sw_rad = np.deg2rad(turn_deg_s)
+    Ps, Ts, Cs = [], [], []
+    for _ in range(n_frames):
+        T = image_pose(c, R[:, 0], R[:, 2], width, height, pitch)
+        Ps.append(probe_pose_from_image_pose(T, calib))
+        Ts.append(T)
+        Cs.append(c.copy())
+        v = a * v + b * speed_mm_s * rng.standard_normal(3)
+        w = a * w + b * sw_rad * rng.standard_normal(3)
+        c = c + v * dt
+        for k in range(3):
+            if c[k] < lo[k]:
+                c[k] = 2 * lo[k] - c[k]
+                v[k] = -v[k]
+            if c[k] > hi[k]:
+                c[k] = 2 * hi[k] - c[k]
+                v[k] = -v[k]
+        R = rotvec_to_matrix(w * dt) @ R
+    return _concat([(np.stack(Ps), np.stack(Ts), np.stack(Cs))], width, height, pitch)
+
+
 @dataclass
 class SliceSet:
     probe_poses: np.ndarray     # (n,4,4) float64

@@ -177,3 +177,53 @@ def test_grouped_submit_and_poll(env):
     srv.close()
     for k in range(len(reqs)):
         assert np.array_equal(outs[k].numpy(), ref[k], equal_nan=True), k
+
+
+def test_frames_compounded_in_request_order(env):
+    """Frames submitted to the server are compounded between the requests around them: every
+    request equals the same request resliced alone on a volume compounded with exactly the
+    frame batches submitted before it."""
+    dare, torch, wl, _ = env
+    note("server compounding frame batches between requests")
+    frames = wl.frames.to("cuda").contiguous()
+    poses = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).to("cuda")
+    nb = 4
+    edges = np.linspace(0, frames.shape[0], nb + 1).astype(int)
+    batches = [(frames[a:b].contiguous(), poses[a:b].contiguous()) for a, b in zip(edges[:-1], edges[1:])]
+    groups = [_requests(wl, 6, seed=50 + k) for k in range(nb + 1)]
+    served = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params(), dtype="bf16")
+    srv = dare.Server(64 << 20, n_streams=2, max_tick_requests=4)
+    vid = srv.add_volume(served)
+    outs, tickets, ftickets = [], [], []
+    for k in range(nb + 1):
+        row = []
+        for (_, P, W, H, pitch) in groups[k]:
+            o = torch.full((H, W), -5.0, dtype=torch.float32, pin_memory=True)
+            t = srv.submit(vid, P, W, H, pitch, o)
+            assert t is not None
+            row.append(o)
+            tickets.append(t)
+        outs.append(row)
+        if k < nb:
+            ft = srv.submit_frames(vid, batches[k][0], batches[k][1], wl.sweep.pitch)
+            assert ft is not None
+            ftickets.append(ft)
+    srv.drain()
+    for ft in ftickets:
+        st, tm = srv.poll_frames(ft)
+        assert st == dare.OK and tm.t_submit <= tm.t_admit <= tm.t_host_done
+    assert all(srv.poll(t) is not None for t in tickets)
+    stats = srv.stats()
+    assert stats.frames == frames.shape[0]
+    srv.close()
+    ref_vol = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params(), dtype="bf16")
+    for k in range(nb + 1):
+        if k > 0:
+            ref_vol.reconstruct(batches[k - 1][0], batches[k - 1][1], wl.sweep.pitch)
+        for (_, P, W, H, pitch), o in zip(groups[k], outs[k]):
+            ref = torch.full((H, W), -9.0, device="cuda")
+            dare.dare_reslice(ref_vol, dare.make_spec(P, W, H, pitch), ref)
+            torch.cuda.synchronize()
+            assert np.array_equal(o.numpy(), ref.cpu().numpy(), equal_nan=True), k
+    # before any frame every result is unassigned
+    assert all(np.isnan(o.numpy()).all() for o in outs[0])
