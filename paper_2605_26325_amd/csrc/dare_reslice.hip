@@ -179,6 +179,82 @@ __device__ __forceinline__ float blend_voxel(const typename Pair<DT>::T* __restr
     return B > 0.0f ? A / B : __builtin_nanf("");
 }
 
+// Two staged voxels at once (a tile listing more voxels than threads): the pair loads of both
+// are issued before either is accumulated, so the pair costs one memory round trip per chunk
+// of kPairChunk bins instead of one per voxel.  Per voxel the arithmetic and its order are
+// blend_voxel's.
+constexpr int kPairChunk = 8;
+
+template <int DT>
+__device__ __forceinline__ void blend_voxel_pair(const typename Pair<DT>::T* __restrict__ data, const SetupLds& sh,
+                                                 const TileLds<DT>& tl, int kact, int bbA, int locA, int bbB,
+                                                 int locB, bool two, float& VA, float& VB) {
+    using PT = Pair<DT>;
+    const int nbb = tl.nbb;
+    if (kact == 1) {
+        const int sA = tl.slot[bbA], sB = two ? tl.slot[bbB] : -1;
+        typename PT::T pA, pB;
+        if (sA >= 0) pA = data[(size_t)sA * kBrickVox + locA];
+        if (sB >= 0) pB = data[(size_t)sB * kBrickVox + locB];
+        float2 scA = make_float2(0.0f, 0.0f), scB = make_float2(0.0f, 0.0f);
+        if constexpr (DT == DARE_FP8_E4M3) {
+            scA = tl.scale[bbA];
+            if (two) scB = tl.scale[bbB];
+        }
+        float a, cnt;
+        VA = __builtin_nanf("");
+        VB = __builtin_nanf("");
+        if (sA >= 0) {
+            PT::decode(pA, scA, a, cnt);
+            VA = cnt > 0.0f ? a : __builtin_nanf("");
+        }
+        if (sB >= 0) {
+            PT::decode(pB, scB, a, cnt);
+            VB = cnt > 0.0f ? a : __builtin_nanf("");
+        }
+        return;
+    }
+    float A0 = 0.0f, B0 = 0.0f, A1 = 0.0f, B1 = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += kPairChunk) {
+        int slA[kPairChunk], slB[kPairChunk];
+        typename PT::T pA[kPairChunk], pB[kPairChunk];
+#pragma unroll
+        for (int u = 0; u < kPairChunk; ++u) {
+            slA[u] = (k0 + u < kact) ? tl.slot[(k0 + u) * nbb + bbA] : -1;
+            slB[u] = (two && k0 + u < kact) ? tl.slot[(k0 + u) * nbb + bbB] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPairChunk; ++u) {
+            if (slA[u] >= 0) pA[u] = data[(size_t)slA[u] * kBrickVox + locA];
+            if (slB[u] >= 0) pB[u] = data[(size_t)slB[u] * kBrickVox + locB];
+        }
+#pragma unroll
+        for (int u = 0; u < kPairChunk; ++u) {
+            const float w = sh.act_w[k0 + u < kact ? k0 + u : 0];
+            if (slA[u] >= 0) {
+                float2 sc = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc = tl.scale[(k0 + u) * nbb + bbA];
+                float a, cnt;
+                PT::decode(pA[u], sc, a, cnt);
+                const float wc = w * cnt;
+                A0 = __builtin_fmaf(wc, a, A0);
+                B0 = B0 + wc;
+            }
+            if (slB[u] >= 0) {
+                float2 sc = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc = tl.scale[(k0 + u) * nbb + bbB];
+                float a, cnt;
+                PT::decode(pB[u], sc, a, cnt);
+                const float wc = w * cnt;
+                A1 = __builtin_fmaf(wc, a, A1);
+                B1 = B1 + wc;
+            }
+        }
+    }
+    VA = B0 > 0.0f ? A0 / B0 : __builtin_nanf("");
+    VB = B1 > 0.0f ? A1 / B1 : __builtin_nanf("");
+}
+
 // One 16x16 tile.  With have_setup the slice setup is already in `sh` (batched
 // requests share one record computed by a pre-pass); otherwise wave 0 computes it.
 template <int DT>
@@ -244,19 +320,39 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
             }
         }
         __syncthreads();
-        // (c) one thread per listed voxel: all its bins' gathers in flight at once, then the blend
+        // (c) one thread per listed voxel (two when the list is longer than the workgroup): all
+        // bins' gathers in flight at once, then the blend
         const typename Pair<DT>::T* __restrict__ data = (const typename Pair<DT>::T*)vd->data;
-        const int nlist = tl.nlist;
+        const int nlist = uniform_i32(tl.nlist);
         const int dxb = tl.dim[0], dyb = tl.dim[1];
         const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2];
         const int bx0 = tl.blo[0], by0 = tl.blo[1], bz0 = tl.blo[2], bdx = tl.bdim[0], bdy = tl.bdim[1];
-        for (int e = threadIdx.x; e < nlist; e += blockDim.x) {
-            const int bi = tl.list[e];
+        auto locate = [&](int bi, int& bb, int& local) {
             const int ex = bi % dxb, eyz = bi / dxb;
             const int vx = lox + ex, vy = loy + eyz % dyb, vz = loz + eyz / dyb;
-            const int bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
-            const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
-            tl.V[bi] = blend_voxel<DT>(data, sh, tl, kact, bb, local);
+            bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
+            local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+        };
+        if (nlist <= (int)blockDim.x) {
+            for (int e = threadIdx.x; e < nlist; e += blockDim.x) {
+                const int bi = tl.list[e];
+                int bb, local;
+                locate(bi, bb, local);
+                tl.V[bi] = blend_voxel<DT>(data, sh, tl, kact, bb, local);
+            }
+        } else {
+            for (int e = threadIdx.x; e < nlist; e += 2 * blockDim.x) {
+                const int e2 = e + blockDim.x;
+                const bool two = e2 < nlist;
+                const int biA = tl.list[e], biB = two ? tl.list[e2] : biA;
+                int bbA, locA, bbB, locB;
+                locate(biA, bbA, locA);
+                locate(biB, bbB, locB);
+                float VA, VB;
+                blend_voxel_pair<DT>(data, sh, tl, kact, bbA, locA, bbB, locB, two, VA, VB);
+                tl.V[biA] = VA;
+                if (two) tl.V[biB] = VB;
+            }
         }
         __syncthreads();
     }
