@@ -9,6 +9,7 @@ namespace dare {
 struct BatchReq {
     const VolDev* vol;
     SliceArgs s;
+    SliceCore core;                       // radius 1: the per-slice setup, computed on the host
     // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
     // (v_beg: first index of this request's slab) and their pixels (p_beg), each request's
     // range padded to whole blocks of kFlatBlock.  The slab itself lives at float offset v_off
@@ -64,5 +65,8 @@ hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, Sli
 // the largest pair of axes, times the deepest run, capped at kSlabPerPixel per pixel.
 // Defined with the C ABI.
 int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec);
+// The per-slice setup of a radius-1 reslice (pose, surviving bins and weights, plane frame),
+// computed on the host from its copy of the volume's codebook.  Defined with the C ABI.
+void host_core(const dare_volume* v, const dare_slice_spec* spec, SliceCore* core);
 
 }  // namespace dare

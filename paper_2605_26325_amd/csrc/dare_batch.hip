@@ -112,9 +112,29 @@ __global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__
     for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
         const VolDev* vd = reqs[r].vol;
         const SliceArgs& s = reqs[r].s;
+        const SliceCore& cr = reqs[r].core;      // computed on the host, as for a single reslice
         SliceSetup& su = setups[r];
+        const int lane = threadIdx.x;
+        su.act_bin[lane] = cr.act_bin[lane];
+        su.act_w[lane] = cr.act_w[lane];
         double T[12];
-        const int ka = slice_setup(vd, s, su, T);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) T[k] = cr.T[k];
+        const int ka = cr.kact;
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) su.T[k] = T[k];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                su.fm[a] = cr.fm[a];
+                su.fu[a] = cr.fu[a];
+                su.fw[a] = cr.fw[a];
+            }
+            su.lu = cr.lu;
+            su.lw = cr.lw;
+            su.dax = cr.dax;
+            su.kact = ka;
+        }
         slab_setup(vd, s, T, ka, reqs[r].v_cap, su);
         // table offset of every bin slot (0 beyond the survivors: read, then ignored); the
         // survivors' ids were written by other lanes of this wave

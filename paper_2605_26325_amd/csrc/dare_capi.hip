@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "dare_staged.h"
@@ -21,7 +22,7 @@ struct dare_volume {
     uint64_t arena_bytes = 0;
     VolDev host{};              // host mirror of the device header (pointers, geometry, codebook)
     VolDev* dev = nullptr;      // device header at the start of the arena
-    VolState* st_pinned = nullptr;
+    VolDev* hdr_pinned = nullptr;   // pinned copy of the device header, read at sync points
     int K = 0;
     int saturated = 0;
     uint32_t used = 0;
@@ -147,10 +148,14 @@ dare_status hip_status(hipError_t e) { return e == hipSuccess ? DARE_OK : DARE_E
         if (_e != hipSuccess) return DARE_ERR_HIP;    \
     } while (0)
 
+// Device header at a sync point: the state, and the codebook the host keeps a copy of (the
+// per-slice setup is computed on the host from it).
 dare_status read_state(dare_volume* v, hipStream_t stream, VolState* out) {
-    HIP_TRY(hipMemcpyAsync(v->st_pinned, &v->dev->st, sizeof(VolState), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(v->hdr_pinned, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    *out = *v->st_pinned;
+    *out = v->hdr_pinned->st;
+    memcpy(v->host.rep_n, v->hdr_pinned->rep_n, sizeof(v->host.rep_n));
+    memcpy(v->host.rep_x, v->hdr_pinned->rep_x, sizeof(v->host.rep_x));
     return DARE_OK;
 }
 
@@ -163,6 +168,30 @@ void compose_host(const double* P, const double* C, double* T) {
             acc = acc + P[r * 4 + 3] * C[3 * 4 + c];
             T[r * 4 + c] = acc;
         }
+}
+
+// Eq. 1 for every direction bin, the angular gates and Eq. 2 (Sec. 2.1 "Reslicing"), in FP64 on
+// the host copy of the codebook: surviving bins in increasing order with their weights.
+int gate_bins(const dare_volume* v, const double T[16], int32_t* bins, double* w) {
+    const VolDev& h = v->host;
+    const int ax = v->p.normal_axis;
+    const double e0[3] = {T[0], T[4], T[8]}, en[3] = {T[ax], T[4 + ax], T[8 + ax]};
+    const double l0 = sqrt((e0[0] * e0[0] + e0[1] * e0[1]) + e0[2] * e0[2]);
+    const double ln = sqrt((en[0] * en[0] + en[1] * en[1]) + en[2] * en[2]);
+    const double xr[3] = {e0[0] / l0, e0[1] / l0, e0[2] / l0}, nr[3] = {en[0] / ln, en[1] / ln, en[2] / ln};
+    int n = 0;
+    for (int b = 0; b < v->K; ++b) {
+        const double* rn = h.rep_n[b];
+        const double* rx = h.rep_x[b];
+        const double dn = (rn[0] * nr[0] + rn[1] * nr[1]) + rn[2] * nr[2];
+        const double di = fabs((rx[0] * xr[0] + rx[1] * xr[1]) + rx[2] * xr[2]);
+        if (dn >= h.cos_normal && di >= h.cos_inplane) {
+            bins[n] = b;
+            w[n] = exp(h.k_normal * (dn - 1.0) + h.k_inplane * (di - 1.0));
+            ++n;
+        }
+    }
+    return n;
 }
 
 SliceArgs make_args(const dare_slice_spec* s, float* out) {
@@ -179,6 +208,49 @@ SliceArgs make_args(const dare_slice_spec* s, float* out) {
 }
 
 }  // namespace
+
+namespace dare {
+
+// The per-slice part of a radius-1 reslice, computed once per request: FP64 pose, surviving bins
+// and FP32 weights, and the FP32 plane frame (unit normal, in-plane axes and steps in voxel units,
+// dominant normal axis) that drives the footprint tests.
+void host_core(const dare_volume* v, const dare_slice_spec* spec, SliceCore* c) {
+    double T[16];
+    compose_host(spec->probe_pose, v->g.calib, T);
+    for (int k = 0; k < 12; ++k) c->T[k] = T[k];
+    int32_t bins[kMaxBins];
+    double w[kMaxBins];
+    const int n = gate_bins(v, T, bins, w);
+    c->kact = n;
+    for (int k = 0; k < kMaxBins; ++k) {
+        c->act_bin[k] = k < n ? bins[k] : 0;
+        c->act_w[k] = k < n ? (float)w[k] : 0.0f;
+    }
+    const double inv_h = v->host.inv_h;
+    float u[3], vv[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (float)(T[a * 4 + 0] * spec->pitch_mm[0] * inv_h);
+        vv[a] = (float)(T[a * 4 + 1] * spec->pitch_mm[1] * inv_h);
+    }
+    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const float lv = sqrtf(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+    float nm[3] = {u[1] * vv[2] - u[2] * vv[1], u[2] * vv[0] - u[0] * vv[2], u[0] * vv[1] - u[1] * vv[0]};
+    const float rm = 1.0f / sqrtf(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
+    int dax = 0;
+    for (int a = 0; a < 3; ++a) nm[a] *= rm;
+    if (fabsf(nm[1]) > fabsf(nm[dax])) dax = 1;
+    if (fabsf(nm[2]) > fabsf(nm[dax])) dax = 2;
+    for (int a = 0; a < 3; ++a) {
+        c->fm[a] = nm[a];
+        c->fu[a] = u[a] / lu;
+        c->fw[a] = vv[a] / lv;
+    }
+    c->lu = lu;
+    c->lw = lv;
+    c->dax = dax;
+}
+
+}  // namespace dare
 
 namespace dare {
 const VolDev* volume_device(const dare_volume* v) { return v->dev; }
@@ -211,6 +283,92 @@ GroupLayout group_layout(size_t nreq, size_t nunits, int64_t slab_floats_total) 
     L.o_slab = L.o_setup + align_up(nreq * sizeof(SliceSetup));
     L.total = L.o_slab + align_up((uint64_t)slab_floats_total * sizeof(float));
     return L;
+}
+
+// Pinned staging for batch request tables.  An upload from pageable memory would make the call
+// wait for the stream; from pinned memory it is asynchronous, and a buffer is reused only once
+// the event recorded after its copy has completed.  Buffers are kept per device until the
+// process ends.
+class StagingPool {
+public:
+    // A pinned buffer of at least `bytes` not read by any pending copy; `release` records the
+    // copy that reads it on `stream`.
+    struct Lease {
+        char* p = nullptr;
+        int idx = -1;
+    };
+    Lease acquire(uint64_t bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (;;) {
+            int oldest = -1;
+            for (int k = 0; k < (int)bufs_.size(); ++k) {
+                Buf& b = bufs_[k];
+                if (b.leased) continue;
+                if (b.pending && hipEventQuery(b.ev) != hipSuccess) {
+                    if (oldest < 0 || b.seq < bufs_[oldest].seq) oldest = k;
+                    continue;
+                }
+                b.pending = false;
+                if (b.cap < bytes && !grow(b, bytes)) return Lease{};
+                b.leased = true;
+                return Lease{b.p, k};
+            }
+            if ((int)bufs_.size() < kMaxBufs) {
+                Buf b;
+                if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) return Lease{};
+                if (!grow(b, bytes)) {
+                    (void)hipEventDestroy(b.ev);
+                    return Lease{};
+                }
+                b.leased = true;
+                bufs_.push_back(b);
+                return Lease{b.p, (int)bufs_.size() - 1};
+            }
+            if (oldest < 0) return Lease{};                  // every buffer leased by other threads
+            if (hipEventSynchronize(bufs_[oldest].ev) != hipSuccess) return Lease{};
+            bufs_[oldest].pending = false;
+        }
+    }
+    hipError_t release(const Lease& l, hipStream_t stream) {
+        std::lock_guard<std::mutex> lk(mu_);
+        Buf& b = bufs_[l.idx];
+        b.leased = false;
+        b.pending = true;
+        b.seq = ++seq_;
+        return hipEventRecord(b.ev, stream);
+    }
+
+private:
+    struct Buf {
+        char* p = nullptr;
+        uint64_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool leased = false, pending = false;
+        uint64_t seq = 0;
+    };
+    static constexpr int kMaxBufs = 8;
+    static bool grow(Buf& b, uint64_t bytes) {
+        if (b.cap >= bytes) return true;
+        if (b.p) (void)hipHostFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        const uint64_t cap = std::max<uint64_t>(bytes, 1 << 20);
+        if (hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault) != hipSuccess) return false;
+        b.cap = cap;
+        return true;
+    }
+    std::mutex mu_;
+    std::vector<Buf> bufs_;
+    uint64_t seq_ = 0;
+};
+
+StagingPool& staging_pool(int device) {
+    static std::mutex mu;
+    static std::map<int, StagingPool*> pools;
+    std::lock_guard<std::mutex> lk(mu);
+    StagingPool*& p = pools[device];
+    if (!p) p = new StagingPool();
+    return *p;
 }
 
 struct GroupSize {
@@ -357,7 +515,7 @@ dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dar
     h.data = (void*)(base + L.off_data);
     h.scales = (float2*)(base + L.off_scales);
     v->dev = (VolDev*)base;
-    if (hipHostMalloc((void**)&v->st_pinned, sizeof(VolState), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&v->hdr_pinned, sizeof(VolDev), hipHostMallocDefault) != hipSuccess) {
         delete v;
         return DARE_ERR_HIP;
     }
@@ -366,7 +524,7 @@ dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dar
     if (e == hipSuccess && cap > 0) e = hipMemset(h.dirty_flags, 0, cap * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        (void)hipHostFree(v->st_pinned);
+        (void)hipHostFree(v->hdr_pinned);
         delete v;
         return DARE_ERR_HIP;
     }
@@ -378,7 +536,7 @@ dare_status dare_volume_destroy(dare_volume* v) {
     if (!v) return DARE_ERR_INVALID_ARG;
     DeviceGuard dg(v->device);
     hipError_t e = hipDeviceSynchronize();
-    (void)hipHostFree(v->st_pinned);
+    (void)hipHostFree(v->hdr_pinned);
     delete v;
     return hip_status(e);
 }
@@ -431,7 +589,24 @@ dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, floa
     const SliceArgs a = make_args(spec, out_dev);
     const int R = (int)v->p.radius_vox;
     if (staged_radius(R)) return hip_status(launch_reslice_staged(v->dev, v->dtype, R, a, (hipStream_t)stream));
-    return hip_status(launch_reslice(v->dev, v->dtype, R, a, (hipStream_t)stream));
+    SliceCore core;
+    VolView view{};
+    if (R <= 1) {
+        host_core(v, spec, &core);
+        const VolDev& h = v->host;
+        view.table = h.table;
+        view.data = h.data;
+        view.scales = h.scales;
+        view.nbricks = h.nbricks;
+        view.n[0] = h.nx;
+        view.n[1] = h.ny;
+        view.n[2] = h.nz;
+        view.nbx = h.nbx;
+        view.nby = h.nby;
+        for (int k = 0; k < 3; ++k) view.origin[k] = h.origin[k];
+        view.inv_h = h.inv_h;
+    }
+    return hip_status(launch_reslice(v->dev, v->dtype, R, a, core, view, (hipStream_t)stream));
 }
 
 
@@ -472,6 +647,7 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         q.vol = vols[k]->dev;
         q.s = make_args(specs + k, outs_dev[k]);
         if (R <= 1) {
+            host_core(vols[k], specs + k, &q.core);
             // flat ranges padded to whole blocks (slab capacities already are)
             q.v_cap = slab_floats(vols[k], specs + k);
             q.v_beg = g.vox;
@@ -494,16 +670,22 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         const int nunits = (int)g.units.size();
         const int nreq = (int)g.reqs.size();
         const GroupLayout L = group_layout(g.reqs.size(), g.units.size(), g.vox);
-        std::vector<char> host(L.upload, 0);
+        StagingPool& pool = staging_pool(device);
+        const StagingPool::Lease lease = pool.acquire(L.upload);
+        if (!lease.p) return DARE_ERR_HIP;
+        char* host = lease.p;
+        memset(host, 0, L.o_req);
         BatchHeader hd{};
         hd.counts[0] = nunits;
         hd.counts[1] = nreq;
         hd.totals[0] = g.vox;
         hd.totals[1] = g.pix;
-        memcpy(host.data(), &hd, sizeof(hd));
-        memcpy(host.data() + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
-        if (nunits) memcpy(host.data() + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
-        HIP_TRY(hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+        memcpy(host, &hd, sizeof(hd));
+        memcpy(host + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
+        if (nunits) memcpy(host + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
+        const hipError_t ce = hipMemcpyAsync(ws, host, L.upload, hipMemcpyHostToDevice, stream);
+        const hipError_t re = pool.release(lease, stream);
+        if (ce != hipSuccess || re != hipSuccess) return DARE_ERR_HIP;
         const int R = kv.first.second;
         const int grid = R <= 1 ? kBatchGrid : std::min(nunits, 65535);
         HIP_TRY(launch_reslice_batch(kv.first.first, R, (const BatchReq*)(ws + L.o_req), (SliceSetup*)(ws + L.o_setup),
@@ -642,28 +824,14 @@ dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* 
     if (!v || !count) return DARE_ERR_INVALID_ARG;
     const dare_status st = check_spec(spec);
     if (st != DARE_OK) return st;
-    DeviceGuard dg(v->device);
-    HIP_TRY(hipDeviceSynchronize());
-    VolDev tmp;
-    HIP_TRY(hipMemcpy(&tmp, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost));
     double T[16];
     compose_host(spec->probe_pose, v->g.calib, T);
-    const int ax = v->p.normal_axis;
-    const double e0[3] = {T[0], T[4], T[8]}, en[3] = {T[ax], T[4 + ax], T[8 + ax]};
-    const double l0 = sqrt((e0[0] * e0[0] + e0[1] * e0[1]) + e0[2] * e0[2]);
-    const double ln = sqrt((en[0] * en[0] + en[1] * en[1]) + en[2] * en[2]);
-    const double xr[3] = {e0[0] / l0, e0[1] / l0, e0[2] / l0}, nr[3] = {en[0] / ln, en[1] / ln, en[2] / ln};
-    int n = 0;
-    for (int b = 0; b < tmp.st.K; ++b) {
-        const double* rn = tmp.rep_n[b];
-        const double* rx = tmp.rep_x[b];
-        const double dn = (rn[0] * nr[0] + rn[1] * nr[1]) + rn[2] * nr[2];
-        const double di = fabs((rx[0] * xr[0] + rx[1] * xr[1]) + rx[2] * xr[2]);
-        if (dn >= tmp.cos_normal && di >= tmp.cos_inplane) {
-            if (bins_out) bins_out[n] = b;
-            if (weights_out) weights_out[n] = exp(tmp.k_normal * (dn - 1.0) + tmp.k_inplane * (di - 1.0));
-            ++n;
-        }
+    int32_t bins[kMaxBins];
+    double w[kMaxBins];
+    const int n = gate_bins(v, T, bins, w);
+    for (int k = 0; k < n; ++k) {
+        if (bins_out) bins_out[k] = bins[k];
+        if (weights_out) weights_out[k] = w[k];
     }
     *count = n;
     return DARE_OK;

@@ -60,7 +60,7 @@ struct TileLds {
 // cells bound every pixel's cell (one voxel of margin per side absorbs
 // rounding).  Lane 0 derives the footprint tests from the slice's plane frame.
 template <int DT>
-__device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+__device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s, const double T[12],
                                            const SetupLds& sh, int kact, int i0, int j0, TileLds<DT>& tl) {
     const int lane = threadIdx.x;
     const int i1 = min(i0 + kTile - 1, s.W - 1), j1 = min(j0 + kTile - 1, s.H - 1);
@@ -70,12 +70,12 @@ __device__ __forceinline__ void tile_setup(const VolDev* __restrict__ vd, const 
         q.t[a] = T[a * 4 + 3];
         q.e0[a] = T[a * 4 + 0];
         q.e1[a] = T[a * 4 + 1];
-        q.o[a] = vd->origin[a];
+        q.o[a] = vd.origin[a];
     }
-    q.inv_h = vd->inv_h;
+    q.inv_h = vd.inv_h;
     q.sx = s.sx;
     q.sy = s.sy;
-    const int n[3] = {vd->nx, vd->ny, vd->nz};
+    const int n[3] = {vd.n[0], vd.n[1], vd.n[2]};
     const int k = lane & 3;
     double c[3];
     pixel_coords(q, (k & 1) ? i1 : i0, (k & 2) ? j1 : j0, c);
@@ -255,24 +255,17 @@ __device__ __forceinline__ void blend_voxel_pair(const typename Pair<DT>::T* __r
     VB = B1 > 0.0f ? A1 / B1 : __builtin_nanf("");
 }
 
-// One 16x16 tile.  With have_setup the slice setup is already in `sh` (batched
-// requests share one record computed by a pre-pass); otherwise wave 0 computes it.
+// One 16x16 tile; the slice's setup (pose, surviving bins and weights, plane frame) is in `sh`.
 template <int DT>
-__device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, const SliceArgs& s, int unit,
-                                                SetupLds& sh, TileLds<DT>& tl, bool have_setup) {
+__device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceArgs& s, int unit, SetupLds& sh,
+                                                TileLds<DT>& tl) {
     const int tx = unit % s.tiles_x, ty = unit / s.tiles_x;
     const int i0 = tx * kTile, j0 = ty * kTile;
     if (threadIdx.x < 64) {
         double T[12];
-        int ka;
-        if (have_setup) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) T[k] = sh.T[k];
-            ka = sh.kact;
-        } else {
-            ka = slice_setup(vd, s, sh, T);
-        }
-        tile_setup<DT>(vd, s, T, sh, ka, i0, j0, tl);
+        for (int k = 0; k < 12; ++k) T[k] = sh.T[k];
+        tile_setup<DT>(vd, s, T, sh, sh.kact, i0, j0, tl);
     }
     __syncthreads();
     const int kact = uniform_i32(sh.kact);
@@ -280,15 +273,15 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
     if (mode == 1) {
         // (a) brick slots (and FP8 scales) of every surviving bin over the box's bricks
         const int nbb = tl.nbb;
-        const int64_t nbricks = vd->nbricks;
+        const int64_t nbricks = vd.nbricks;
         for (int e = threadIdx.x; e < kact * nbb; e += blockDim.x) {
             const int k = e / nbb, r = e - k * nbb;
             const int bxx = r % tl.bdim[0], byz = r / tl.bdim[0];
             const int byy = byz % tl.bdim[1], bzz = byz / tl.bdim[1];
-            const int64_t brick = ((int64_t)(tl.blo[2] + bzz) * vd->nby + (tl.blo[1] + byy)) * vd->nbx + (tl.blo[0] + bxx);
-            const int slot = vd->table[(int64_t)sh.act_bin[k] * nbricks + brick];
+            const int64_t brick = ((int64_t)(tl.blo[2] + bzz) * vd.nby + (tl.blo[1] + byy)) * vd.nbx + (tl.blo[0] + bxx);
+            const int slot = vd.table[(int64_t)sh.act_bin[k] * nbricks + brick];
             tl.slot[e] = slot;
-            if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = slot >= 0 ? vd->scales[slot] : make_float2(0.0f, 0.0f);
+            if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = slot >= 0 ? vd.scales[slot] : make_float2(0.0f, 0.0f);
         }
         // (b) the voxels the tile touches, compacted into a list (ALU work only)
         {
@@ -322,7 +315,7 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
         __syncthreads();
         // (c) one thread per listed voxel (two when the list is longer than the workgroup): all
         // bins' gathers in flight at once, then the blend
-        const typename Pair<DT>::T* __restrict__ data = (const typename Pair<DT>::T*)vd->data;
+        const typename Pair<DT>::T* __restrict__ data = (const typename Pair<DT>::T*)vd.data;
         const int nlist = uniform_i32(tl.nlist);
         const int dxb = tl.dim[0], dyb = tl.dim[1];
         const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2];
@@ -365,8 +358,17 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
         return;
     }
     SlicePos q;
-    load_pos(vd, sh, s, q);
-    const int nx = vd->nx, ny = vd->ny, nz = vd->nz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.t[a] = uniform_f64(sh.T[a * 4 + 3]);
+        q.e0[a] = uniform_f64(sh.T[a * 4 + 0]);
+        q.e1[a] = uniform_f64(sh.T[a * 4 + 1]);
+        q.o[a] = vd.origin[a];
+    }
+    q.inv_h = vd.inv_h;
+    q.sx = s.sx;
+    q.sy = s.sy;
+    const int nx = vd.n[0], ny = vd.n[1], nz = vd.n[2];
     double c[3];
     pixel_coords(q, i, j, c);
     if (!(c[0] >= -1.0 && c[0] < (double)nx && c[1] >= -1.0 && c[1] < (double)ny && c[2] >= -1.0 &&
@@ -375,7 +377,7 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
         return;
     }
     if (mode == 2) {
-        *out = pixel_direct<DT, 2>(view_of(vd), sh, kact, c);
+        *out = pixel_direct<DT, 2>(vd, sh, kact, c);
         return;
     }
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
@@ -415,11 +417,32 @@ __device__ __forceinline__ void reslice_tile_r1(const VolDev* __restrict__ vd, c
 }  // namespace
 
 
+// The per-slice setup (FP64 pose, Eq. 1 gates and Eq. 2 weights, plane frame) is computed once on
+// the host and arrives with the launch, with the volume's geometry and pointers; wave 0 copies the
+// setup to LDS.
 template <int DT>
-__global__ void __launch_bounds__(256) k_reslice_r1(const VolDev* __restrict__ vd, SliceArgs s) {
+__global__ void __launch_bounds__(256) k_reslice_r1(SliceArgs s, SliceCore core, VolView vd) {
     __shared__ SetupLds sh;
     __shared__ TileLds<DT> tl;
-    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh, tl, false);
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        sh.act_bin[l] = core.act_bin[l];
+        sh.act_w[l] = core.act_w[l];
+        if (l < 12) sh.T[l] = core.T[l];
+        if (l < 3) {
+            sh.fm[l] = core.fm[l];
+            sh.fu[l] = core.fu[l];
+            sh.fw[l] = core.fw[l];
+        }
+        if (l == 0) {
+            sh.lu = core.lu;
+            sh.lw = core.lw;
+            sh.dax = core.dax;
+            sh.kact = core.kact;
+        }
+    }
+    __syncthreads();
+    reslice_tile_r1<DT>(vd, s, xcd_remap(blockIdx.x, gridDim.x), sh, tl);
 }
 
 template <int DT, int G>
@@ -438,11 +461,12 @@ int64_t reslice_units(int radius, int W, int H) {
     return ((int64_t)W * H + ppw - 1) / ppw;
 }
 
-hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream) {
+hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, const SliceCore& core,
+                          const VolView& view, hipStream_t stream) {
     const int64_t units = reslice_units(radius, s.W, s.H);
     const dim3 grid((unsigned)units), block(256);
     const int G = reslice_lanes(radius);
-#define L1(D) hipLaunchKernelGGL(k_reslice_r1<D>, grid, block, 0, stream, vd, s)
+#define L1(D) hipLaunchKernelGGL(k_reslice_r1<D>, grid, block, 0, stream, s, core, view)
 #define L16(D) hipLaunchKernelGGL((k_reslice_rn<D, 16>), grid, block, 0, stream, vd, s)
 #define L64(D) hipLaunchKernelGGL((k_reslice_rn<D, 64>), grid, block, 0, stream, vd, s)
     if (G == 1) {

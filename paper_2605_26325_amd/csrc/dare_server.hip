@@ -205,6 +205,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
         q.s.tiles_x = (r.spec.width + kTile - 1) / kTile;
         q.s.tiles = q.s.tiles_x * ((r.spec.height + kTile - 1) / kTile);
         q.s.out = (float*)(S->arena + off);
+        if (S->radius <= 1) host_core(S->vols[r.vol], &r.spec, &q.core);
         // the slab is optional: without room for it the request gathers per pixel, same result
         if (r.slab > 0) {
             const uint64_t so = S->outs.alloc((uint64_t)r.slab * sizeof(float));
