@@ -515,11 +515,13 @@ def main():
     avg_launch = dev_s / launches
     algo = []
     kacts = []
+    nvoxs = []
     for k in range(len(specs)):
         kact = len(vol.active_bins(sl.probe_poses[k], W, H, pitch)[0])
         nvox = footprint_voxels(torch, sl.probe_poses[k], wl.calib, wl.origin, wl.spacing, wl.dims, W, H, pitch)
         algo.append(4 * W * H + nvox * kact * PAIR_BYTES["f32"])
         kacts.append(kact)
+        nvoxs.append(nvox)
     algo = np.array(algo, dtype=np.float64)
     achieved = float(algo.mean() / avg_launch / 1e9)
     traffic = None
@@ -586,6 +588,7 @@ def main():
     # ---- precision forms and the batched entry point on the same slices
     forms = {}
     form_vols = {}
+    roofline_batched = {}
     if not args.no_forms:
         for dt in ("bf16", "f16", "fp8"):
             v, dtr = build_volume(dt)
@@ -636,13 +639,24 @@ def main():
 
             run_batches()
             torch.cuda.synchronize()
+            eb0, eb1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t = time.perf_counter()
+            eb0.record(stream)
             for _ in range(args.steps):
                 run_batches()
+            eb1.record(stream)
             torch.cuda.synchronize()
             mpx = args.steps * px_per_step / (time.perf_counter() - t) / 1e6
             key = "fp32" if dt == "f32" else dt
             forms.setdefault(key, {})["batched64_Mpx_s"] = round(mpx, 1)
+            # algorithmic bytes of the same slices at this storage's pair size, over the device span
+            dev_b = eb0.elapsed_time(eb1) * 1e-3
+            algo_b = float(sum(4 * W * H + nv * ka * PAIR_BYTES[dt] for nv, ka in zip(nvoxs, kacts)))
+            ach_b = algo_b * args.steps / dev_b / 1e9
+            roofline_batched[key] = {"bound": "hbm", "achieved": round(ach_b, 1), "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": round(ach_b / HBM_PEAK_GBS, 4),
+                                     "kernels": "k_batch_setup + k_voxel_pass + k_pixel_pass, 64 slices per call",
+                                     "algo_bytes_per_step": round(algo_b), "device_ms_per_step": round(1e3 * dev_b / args.steps, 3)}
             if dt == "f32":
                 same = bool(torch.equal(torch.nan_to_num(outs_b, nan=-1.0), torch.nan_to_num(outs, nan=-1.0)))
                 forms[key]["batched_equals_alone"] = same
@@ -816,6 +830,7 @@ def main():
                    "slice_px": [W, H], "storage": "fp32", "positions": "f64", "bins": int(info.bins),
                    "bricks_used": int(info.bricks_used), "unassigned_fraction": round(nan_frac, 4)},
         "roofline": roofline,
+        "roofline_batched": roofline_batched or None,
         "latency_ms": {"fp32": lat32, **({"bf16": forms["bf16"]["latency_ms"]} if "bf16" in forms else {})},
         "reconstruct": {"frames": int(F), "frame_px": [Wf, Hf], "median_ms": round(1e3 * float(np.median(recon_times)), 3),
                         "frames_per_s": round(F / float(np.median(recon_times)), 1),
