@@ -1,0 +1,115 @@
+"""GPU parity at the benchmark's full size: the config-2 volume (256^3 at 0.125 mm from 3 x 600
+frames of 256^2) and 512^2 slices at 0.0625 mm, resliced the way the benchmark times them (one
+launch per slice, and a call of 64 slices), checked on seeded sampled pixels that the FP64 oracle
+computes one by one (a 1 x 1 slice placed at the pixel), plus the compounded sums on sampled
+bricks.  Bars as in the other parity tests: |d| <= 1e-5 max(|ref|, 1), identical NaN masks,
+batched = alone bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import note
+from oracle import compound, reslice
+from oracle.reslice import Params
+
+pytestmark = pytest.mark.gpu
+
+# near-acquired slices (first 800) and uniformly oriented ones (last 200)
+SLICES = (0, 1, 417, 799, 800, 999)
+SAMPLES = 160
+
+
+@pytest.fixture(scope="module")
+def c2():
+    import torch
+
+    import paper_2605_26325_amd as dare
+    wl = synth.config2()
+    note("config 2 at full size: rendering and compounding on the GPU, compounding in the oracle")
+    frames = wl.render("cuda")
+    poses = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).cuda()
+    geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+    nb = 1
+    for d in wl.dims:
+        nb *= (d + 7) // 8
+    vol = dare.Volume(geom, dare.default_params(), dtype="f32", bricks=nb * 40)
+    vol.reconstruct(frames, poses, wl.sweep.pitch)
+    prm = Params()
+    g = compound.empty_grid(wl.origin, wl.spacing, wl.dims, prm.bin_tol_deg, prm.max_bins)
+    compound.compound(g, frames.cpu().numpy(), wl.sweep.probe_poses, wl.calib, wl.sweep.pitch)
+    torch.cuda.synchronize()
+    return dare, torch, wl, vol, g, prm
+
+
+def _pixel_pose(P, calib, i, j, pitch):
+    """Probe pose of a 1 x 1 slice whose only pixel sits where pixel (i, j) of slice P sits."""
+    T = np.asarray(P, np.float64) @ calib
+    T2 = T.copy()
+    T2[:3, 3] = (T[:3, 3] + (i * pitch[0]) * T[:3, 0]) + (j * pitch[1]) * T[:3, 1]
+    return T2 @ np.linalg.inv(calib)
+
+
+def test_config2_codebook_and_sampled_sums(c2):
+    dare, torch, wl, vol, g, prm = c2
+    note("config 2: codebook and sampled compounded sums against the oracle")
+    info = vol.info()
+    assert info.bins == g.K
+    rn, rx = vol.codebook()
+    orn, orx = g.codebook.arrays()
+    assert len(rn) == g.K and np.array_equal(rn, orn) and np.array_equal(rx, orx)
+    S, C = vol.download_sums()
+    torch.cuda.synchronize()
+    S = S.cpu().numpy().view(np.uint32)
+    C = C.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(8)
+    for _ in range(64):                               # sampled 8^3 blocks of every bin
+        z, y, x = (int(rng.integers(0, n - 8)) for n in wl.dims[::-1])
+        blk = (slice(None), slice(z, z + 8), slice(y, y + 8), slice(x, x + 8))
+        assert np.array_equal(S[blk].astype(np.int64), np.asarray(g.S[blk], np.int64))
+        assert np.array_equal(C[blk].astype(np.int64), np.asarray(g.C[blk], np.int64))
+
+
+def test_config2_one_launch_per_slice_sampled(c2):
+    dare, torch, wl, vol, g, prm = c2
+    sl = wl.slices
+    a, c = g.mean_count()
+    rn, rx = g.codebook.arrays()
+    rng = np.random.default_rng(9)
+    checked = 0
+    for k in SLICES:
+        note(f"config 2 slice {k}: one launch, {SAMPLES} sampled pixels against the oracle")
+        out = torch.full((sl.height, sl.width), -3.0, device="cuda")
+        dare.dare_reslice(vol, dare.make_spec(sl.probe_poses[k], sl.width, sl.height, sl.pitch), out)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy().astype(np.float64)
+        assert not (out == -3.0).any()
+        ii = rng.integers(0, sl.width, SAMPLES)
+        jj = rng.integers(0, sl.height, SAMPLES)
+        for i, j in zip(ii, jj):
+            P1 = _pixel_pose(sl.probe_poses[k], wl.calib, int(i), int(j), sl.pitch)
+            ref = reslice.reslice(a, c, g.origin, g.spacing, rn, rx, wl.calib, P1, 1, 1, sl.pitch, prm)[0, 0]
+            got = out[j, i]
+            assert np.isnan(got) == np.isnan(ref), (k, i, j, got, ref)
+            if not np.isnan(ref):
+                assert abs(got - ref) <= 1e-5 * max(abs(ref), 1.0), (k, i, j, got, ref)
+                checked += 1
+    assert checked > SAMPLES          # the near-acquired slices are mostly assigned
+
+
+def test_config2_batch_of_64_equals_alone(c2):
+    dare, torch, wl, vol, g, prm = c2
+    note("config 2: one batched call of 64 full-size slices against 64 single launches")
+    sl = wl.slices
+    ks = list(range(0, 1000, 1000 // 64))[:64]
+    specs = [dare.make_spec(sl.probe_poses[k], sl.width, sl.height, sl.pitch) for k in ks]
+    outs = torch.full((64, sl.height, sl.width), -7.0, device="cuda")
+    ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([vol] * 64, specs), dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([vol] * 64, specs, [outs[n] for n in range(64)], ws)
+    alone = torch.full((64, sl.height, sl.width), -9.0, device="cuda")
+    for n in range(64):
+        dare.dare_reslice(vol, specs[n], alone[n])
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(outs, nan=-1.0), torch.nan_to_num(alone, nan=-1.0))
