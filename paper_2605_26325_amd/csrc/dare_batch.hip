@@ -155,57 +155,94 @@ __global__ void __launch_bounds__(64) k_batch_setup(const BatchReq* __restrict__
     }
 }
 
-// V_v of voxel (vx, vy, vz) over the surviving bins, straight from the brick pool.
+// Slab elements per thread in a block of the voxel pass, and surviving bins whose gathers the
+// pass issues together for all of them: two for pairs of 4 bytes or less, one for FP32 pairs,
+// whose extra registers would cost more occupancy than the added loads in flight gain.
+constexpr int kVoxPerThread = kFlatBlock / 256;
+static_assert(kFlatBlock % 256 == 0, "a voxel-pass block spreads evenly over 256 threads");
 template <int DT>
-__device__ __forceinline__ float blend_at(const SliceSetup& su, int kact, int vx, int vy, int vz) {
+constexpr int vox_bins() { return sizeof(typename Pair<DT>::T) > 4 ? 1 : 2; }
+
+// V_v of a thread's slab voxels over the surviving bins, straight from the brick pool: the
+// table reads of all of them, then their pair loads, are issued before any is used, so the
+// thread waits for one memory round trip per group of vox_bins bins instead of one per voxel.
+// Per voxel the arithmetic and its order are those of a single-voxel blend over the present
+// bins in bin order; a voxel that failed the slab tests (ok false) comes out NaN.
+template <int DT>
+__device__ __forceinline__ void blend_vox(const SliceSetup& su, const bool (&ok)[kVoxPerThread],
+                                          const int64_t (&brick)[kVoxPerThread],
+                                          const int (&local)[kVoxPerThread], float (&V)[kVoxPerThread]) {
     using PT = Pair<DT>;
+    constexpr int U = kVoxPerThread;
+    constexpr int kVoxBins = vox_bins<DT>();
     const VolView& vv = su.vol;
     const typename PT::T* __restrict__ data = (const typename PT::T*)vv.data;
-    const int64_t nbricks = vv.nbricks;
-    const int64_t brick = ((int64_t)(vz >> 3) * vv.nby + (vy >> 3)) * vv.nbx + (vx >> 3);
-    const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+    const int* __restrict__ table = vv.table;
+    const int kact = su.kact;
     if (kact == 1) {
-        const int slot = vv.table[(int64_t)su.act_bin[0] * nbricks + brick];
-        if (slot < 0) return __builtin_nanf("");
-        float2 sc = make_float2(0.0f, 0.0f);
-        if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[slot];
-        float a, cnt;
-        PT::decode(data[(size_t)slot * kBrickVox + local], sc, a, cnt);
-        return cnt > 0.0f ? a : __builtin_nanf("");
-    }
-    // chunk entries beyond the survivors are skipped by uniform branches; a surviving bin with
-    // no brick here still loads (slot 0, which exists) and then adds exactly zero to A and B,
-    // so the sums equal those over the present bins in bin order
-    float A = 0.0f, B = 0.0f;
-    for (int k0 = 0; k0 < kact; k0 += kBinChunk) {
-        int sl[kBinChunk];
-        typename PT::T pr[kBinChunk];
-        float2 sc[kBinChunk];
+        const int64_t off = su.act_off[0];
+        int sl[U];
+        typename PT::T pr[U];
 #pragma unroll
-        for (int u = 0; u < kBinChunk; ++u)
-            if (k0 + u < kact) sl[u] = vv.table[su.act_off[k0 + u] + brick];
+        for (int u = 0; u < U; ++u) sl[u] = ok[u] ? table[off + brick[u]] : -1;
 #pragma unroll
-        for (int u = 0; u < kBinChunk; ++u) {
-            if (k0 + u < kact) {
-                const int s0 = max(sl[u], 0);
-                pr[u] = data[(size_t)s0 * kBrickVox + local];
-                sc[u] = make_float2(0.0f, 0.0f);
-                if constexpr (DT == DARE_FP8_E4M3) sc[u] = vv.scales[s0];
-            }
-        }
+        for (int u = 0; u < U; ++u)
+            if (sl[u] >= 0) pr[u] = data[(size_t)sl[u] * kBrickVox + local[u]];
 #pragma unroll
-        for (int u = 0; u < kBinChunk; ++u) {
-            if (k0 + u < kact) {
+        for (int u = 0; u < U; ++u) {
+            V[u] = __builtin_nanf("");
+            if (sl[u] >= 0) {
+                float2 sc = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[sl[u]];
                 float a, cnt;
-                PT::decode(pr[u], sc[u], a, cnt);
-                const bool present = sl[u] >= 0;
-                const float wc = present ? su.act_w[k0 + u] * cnt : 0.0f;
-                A = __builtin_fmaf(wc, present ? a : 0.0f, A);
-                B = B + wc;
+                PT::decode(pr[u], sc, a, cnt);
+                V[u] = cnt > 0.0f ? a : __builtin_nanf("");
+            }
+        }
+        return;
+    }
+    float A[U], B[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) A[u] = B[u] = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += kVoxBins) {
+        int sl[kVoxBins][U];
+        typename PT::T pr[kVoxBins][U];
+#pragma unroll
+        for (int g = 0; g < kVoxBins; ++g) {
+            if (k0 + g < kact) {
+                const int64_t off = su.act_off[k0 + g];
+#pragma unroll
+                for (int u = 0; u < U; ++u) sl[g][u] = ok[u] ? table[off + brick[u]] : -1;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kVoxBins; ++g)
+            if (k0 + g < kact) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (sl[g][u] >= 0) pr[g][u] = data[(size_t)sl[g][u] * kBrickVox + local[u]];
+            }
+#pragma unroll
+        for (int g = 0; g < kVoxBins; ++g) {
+            if (k0 + g < kact) {
+                const float w = su.act_w[k0 + g];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (sl[g][u] >= 0) {
+                        float2 sc = make_float2(0.0f, 0.0f);
+                        if constexpr (DT == DARE_FP8_E4M3) sc = vv.scales[sl[g][u]];
+                        float a, cnt;
+                        PT::decode(pr[g][u], sc, a, cnt);
+                        const float wc = w * cnt;
+                        A[u] = __builtin_fmaf(wc, a, A[u]);
+                        B[u] = B[u] + wc;
+                    }
+                }
             }
         }
     }
-    return B > 0.0f ? A / B : __builtin_nanf("");
+#pragma unroll
+    for (int u = 0; u < U; ++u) V[u] = B[u] > 0.0f ? A[u] / B[u] : __builtin_nanf("");
 }
 
 // The passes run over flat index spaces in blocks of kFlatBlock: each request's range starts on
@@ -247,9 +284,9 @@ __device__ __forceinline__ void divmod(int x, int d, double inv_d, int& q, int& 
     }
 }
 
-// One slab candidate: the plane-slab and lateral tests, then V_v over the surviving bins.
-template <int DT>
-__device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* __restrict__ scratch) {
+// Slab candidate e: its brick and in-brick index, and whether it passes the plane-slab and
+// lateral tests.
+__device__ __forceinline__ bool slab_voxel(const SliceSetup& su, int e, int64_t& brick, int& local) {
     const int dax = su.dax, pax = su.pax;
     const int nd = su.vol.n[dax];
     // slab order: column tiles of kSlabTileP x kSlabTileQ (p fastest), each with all its
@@ -263,7 +300,8 @@ __device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* _
     const int cq = tq * kSlabTileQ + (w >> 3);
     const int vp = su.lo_p + cp, vq = su.lo_q + cq;
     const int vdd = run_start(su, vp, vq) + k;
-    float V = __builtin_nanf("");
+    brick = 0;
+    local = 0;
     if (cp < su.dim_p && cq < su.dim_q && vdd < nd) {
         const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
         const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
@@ -273,10 +311,13 @@ __device__ __forceinline__ void voxel_elem(const SliceSetup& su, int e, float* _
         const float du = su.fu[0] * d0 + su.fu[1] * d1 + su.fu[2] * d2;
         const float dv = su.fw[0] * d0 + su.fw[1] * d1 + su.fw[2] * d2;
         if (fabsf(dn) < su.thr_n && du > -su.thr_u && du < su.len_u + su.thr_u && dv > -su.thr_v &&
-            dv < su.len_v + su.thr_v)
-            V = blend_at<DT>(su, su.kact, vx, vy, vz);
+            dv < su.len_v + su.thr_v) {
+            brick = ((int64_t)(vz >> 3) * su.vol.nby + (vy >> 3)) * su.vol.nbx + (vx >> 3);
+            local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+            return true;
+        }
     }
-    scratch[su.v_off + e] = V;
+    return false;
 }
 
 template <int DT>
@@ -290,8 +331,21 @@ __global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__
         const int r = find_req(s_beg, nreq, blk);
         const SliceSetup& su = setups[r];
         const int e0 = ((blk - s_beg[r]) << kFlatShift) + (int)threadIdx.x;
-        for (int u = 0; u < kFlatBlock; u += 256)
-            if (e0 + u < su.ncand) voxel_elem<DT>(su, e0 + u, scratch);
+        const int ncand = su.ncand;
+        bool ok[kVoxPerThread];
+        int64_t brick[kVoxPerThread];
+        int local[kVoxPerThread];
+        float V[kVoxPerThread];
+#pragma unroll
+        for (int u = 0; u < kVoxPerThread; ++u) {
+            brick[u] = 0;
+            local[u] = 0;
+            ok[u] = e0 + 256 * u < ncand && slab_voxel(su, e0 + 256 * u, brick[u], local[u]);
+        }
+        blend_vox<DT>(su, ok, brick, local, V);
+#pragma unroll
+        for (int u = 0; u < kVoxPerThread; ++u)
+            if (e0 + 256 * u < ncand) scratch[su.v_off + e0 + 256 * u] = V[u];
     }
 }
 
