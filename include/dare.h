@@ -157,8 +157,9 @@ uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, cons
                                             int32_t n);
 
 /* Reslice n planes, possibly of different volumes, sizes and poses, in one
- * launch per (storage dtype, radius) group.  Each request's result equals
- * what dare_reslice gives for it alone.
+ * launch sequence per (storage dtype, radius) group; a group holds at most
+ * 4096 requests, taken in call order (more make further groups).  Each
+ * request's result equals what dare_reslice gives for it alone.
  *   vols       n volume handles (host array)
  *   specs      n requests (host array)
  *   outs_dev   n device output pointers (host array), each height*width float32

@@ -28,6 +28,7 @@ struct BatchHeader {
 
 constexpr int kFlatShift = 10;            // batched passes: elements per workgroup iteration ...
 constexpr int kFlatBlock = 1 << kFlatShift;   // ... (4 per thread)
+constexpr int kBatchMaxReq = 4096;        // requests per launch group (LDS request tables of the passes)
 constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
 constexpr int kSlabTileP = 8;             // slab column tile: 8 along p (a brick row when p is x) ...
 constexpr int kSlabTileQ = 4;             // ... by 4 along q

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dare_staged.h"
@@ -376,12 +377,27 @@ struct GroupSize {
     int64_t slab = 0;
 };
 
-std::map<std::pair<int, int>, GroupSize> group_sizes(const dare_volume* const* vols, const dare_slice_spec* specs,
-                                                     int32_t n) {
-    std::map<std::pair<int, int>, GroupSize> cnt;
+// Launch group of each request: (storage dtype, radius, piece), a piece being each run of
+// kBatchMaxReq requests of one (dtype, radius) in call order.
+using GroupKey = std::tuple<int, int, int>;
+
+std::vector<GroupKey> group_keys(const dare_volume* const* vols, int32_t n) {
+    std::map<std::pair<int, int>, int> seen;
+    std::vector<GroupKey> keys((size_t)n);
     for (int k = 0; k < n; ++k) {
         const int R = (int)vols[k]->p.radius_vox;
-        GroupSize& c = cnt[{vols[k]->dtype, R}];
+        const int i = seen[{vols[k]->dtype, R}]++;
+        keys[k] = GroupKey(vols[k]->dtype, R, i / kBatchMaxReq);
+    }
+    return keys;
+}
+
+std::map<GroupKey, GroupSize> group_sizes(const dare_volume* const* vols, const dare_slice_spec* specs, int32_t n) {
+    std::map<GroupKey, GroupSize> cnt;
+    const std::vector<GroupKey> keys = group_keys(vols, n);
+    for (int k = 0; k < n; ++k) {
+        const int R = (int)vols[k]->p.radius_vox;
+        GroupSize& c = cnt[keys[k]];
         c.nreq += 1;
         if (R <= 1) c.slab += slab_floats(vols[k], specs + k);
         else c.nunits += (size_t)batch_units(R, specs[k].width, specs[k].height);
@@ -638,10 +654,11 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
     if (((uintptr_t)workspace_dev % kAlign) != 0) return DARE_ERR_INVALID_ARG;
     DeviceGuard dg(device);
     hipStream_t stream = (hipStream_t)stream_;
-    std::map<std::pair<int, int>, Group> groups;
+    std::map<GroupKey, Group> groups;
+    const std::vector<GroupKey> keys = group_keys(vols, n);
     for (int k = 0; k < n; ++k) {
         const int R = (int)vols[k]->p.radius_vox;
-        Group& g = groups[{vols[k]->dtype, R}];
+        Group& g = groups[keys[k]];
         const int r = (int)g.reqs.size();
         BatchReq q{};
         q.vol = vols[k]->dev;
@@ -686,11 +703,11 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         const hipError_t ce = hipMemcpyAsync(ws, host, L.upload, hipMemcpyHostToDevice, stream);
         const hipError_t re = pool.release(lease, stream);
         if (ce != hipSuccess || re != hipSuccess) return DARE_ERR_HIP;
-        const int R = kv.first.second;
+        const int R = std::get<1>(kv.first);
         const int grid = R <= 1 ? kBatchGrid : std::min(nunits, 65535);
-        HIP_TRY(launch_reslice_batch(kv.first.first, R, (const BatchReq*)(ws + L.o_req), (SliceSetup*)(ws + L.o_setup),
-                                     (const int2*)(ws + L.o_units), (const int*)ws, (float*)(ws + L.o_slab), nreq,
-                                     grid, stream));
+        HIP_TRY(launch_reslice_batch(std::get<0>(kv.first), R, (const BatchReq*)(ws + L.o_req),
+                                     (SliceSetup*)(ws + L.o_setup), (const int2*)(ws + L.o_units), (const int*)ws,
+                                     (float*)(ws + L.o_slab), nreq, grid, stream));
         ws += L.total;
     }
     return DARE_OK;

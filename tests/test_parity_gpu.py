@@ -382,3 +382,33 @@ def test_batch_equals_alone(dare, torch_cuda, cfg1, cfg1_grid):
     torch.cuda.synchronize()
     for k in range(len(reqs)):
         assert np.array_equal(outs[k].cpu().numpy(), alone[k].cpu().numpy(), equal_nan=True), k
+
+
+def test_batch_beyond_one_launch_group(dare, torch_cuda, cfg1, cfg1_grid):
+    """More requests of one storage form than one launch group takes (4096): the call splits
+    them into groups in call order, each request still equal to itself resliced alone."""
+    torch = torch_cuda
+    n = 4096 + 37
+    note(f"batched reslice of {n} small requests of one volume vs one by one")
+    vol = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(), dtype="f32")
+    upload_grid(vol, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+    # small planes centred on the acquired frames, where the grid holds data
+    half = 64 * np.asarray(cfg1.sweep.pitch, np.float64)
+    poses = []
+    for P in cfg1.sweep.probe_poses:
+        T = np.asarray(P, np.float64) @ cfg1.calib
+        T[:3, 3] = (T[:3, 3] + half[0] * T[:3, 0]) + half[1] * T[:3, 1]
+        poses.append(T @ np.linalg.inv(cfg1.calib))
+    specs = [dare.make_spec(poses[k % len(poses)], 5 + k % 3, 4, (0.3 + 0.01 * (k % 7), 0.35)) for k in range(n)]
+    outs = [torch.full((s.height, s.width), -7.0, device="cuda") for s in specs]
+    ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([vol] * n, specs), dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([vol] * n, specs, outs, ws)
+    alone = [torch.full((s.height, s.width), -9.0, device="cuda") for s in specs]
+    for s, o in zip(specs, alone):
+        dare.dare_reslice(vol, s, o)
+    torch.cuda.synchronize()
+    got = torch.cat([o.flatten() for o in outs]).cpu().numpy()
+    ref = torch.cat([o.flatten() for o in alone]).cpu().numpy()
+    assert not (got == -7.0).any()
+    assert np.array_equal(got, ref, equal_nan=True)
+    assert np.isfinite(ref).mean() > 0.5
