@@ -349,6 +349,79 @@ __global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__
     }
 }
 
+// The pixels p0, p0 + 256, ... of one block of a staged request whose normal's dominant axis is
+// DAX: FP64 position, the 8 cell values from the slab, tent weights.  The corner-to-slab mapping
+// is fixed at compile time per dominant axis.
+template <int DAX>
+__device__ __forceinline__ void staged_block(const SliceSetup& su, int p0, const float* __restrict__ scratch) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const int W = su.W, npx = W * su.H;
+    SlicePos q;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.t[a] = su.T[a * 4 + 3];
+        q.e0[a] = su.T[a * 4 + 0];
+        q.e1[a] = su.T[a * 4 + 1];
+        q.o[a] = su.vol.origin[a];
+    }
+    q.inv_h = su.vol.inv_h;
+    q.sx = su.sx;
+    q.sy = su.sy;
+    const int n[3] = {su.vol.n[0], su.vol.n[1], su.vol.n[2]};
+    const bool live = su.kact > 0 && su.ncand > 0;   // a pixel inside the grid implies a non-empty slab
+    const float* __restrict__ slab = scratch + su.v_off;
+    const int depth = su.depth, ntp = su.ntp, last = su.ncand - 1, lo_p = su.lo_p, lo_q = su.lo_q;
+    const int pe = min(p0 - (int)threadIdx.x + kFlatBlock, npx);
+    for (int p = p0; p < pe; p += 256) {
+        const int j = p / W, i = p - j * W;
+        float* out = su.out + p;
+        double c[3];
+        pixel_coords(q, i, j, c);
+        if (!live || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
+                       c[2] >= -1.0 && c[2] < (double)n[2])) {
+            *out = __builtin_nanf("");
+            continue;
+        }
+        const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
+        const int b0[3] = {(int)f0, (int)f1, (int)f2};
+        const float fr[3] = {(float)(c[0] - f0), (float)(c[1] - f1), (float)(c[2] - f2)};
+        // per-axis tent weights of the cell's lower and upper voxel, 0 for a voxel outside the
+        // grid: a corner's weight is their product, 0 for absent corners, which then add exactly
+        // nothing to the sums below (the fused kernel skips them)
+        float w[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[a][0] = (unsigned)b0[a] < (unsigned)n[a] ? 1.0f - fr[a] : 0.0f;
+            w[a][1] = (unsigned)(b0[a] + 1) < (unsigned)n[a] ? fr[a] : 0.0f;
+        }
+        // the cell's 4 columns (offsets along p, q): slab index of layer b0[DAX]; the next layer
+        // along the dominant axis is 32 floats further.  A voxel with weight inside the grid
+        // always lies in the slab, so only a clamp keeps the other corners' reads in bounds.
+        const int bp = b0[PAX], bq = b0[QAX], bd = b0[DAX];
+        int base[4];
+#pragma unroll
+        for (int col = 0; col < 4; ++col) {
+            const int vp = bp + (col & 1), vq = bq + (col >> 1);
+            base[col] = slab_index(vp - lo_p, vq - lo_q, bd - run_start(su, vp, vq), ntp, depth);
+        }
+        float Vc[8];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {             // c8 = (dz << 2) | (dy << 1) | dx
+            const int od = (c8 >> DAX) & 1, col = ((c8 >> PAX) & 1) | (((c8 >> QAX) & 1) << 1);
+            Vc[c8] = slab[min(max(base[col] + (od << 5), 0), last)];
+        }
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {
+            const float tw = (w[0][c8 & 1] * w[1][(c8 >> 1) & 1]) * w[2][c8 >> 2];
+            const bool use = Vc[c8] == Vc[c8];
+            num = use ? __builtin_fmaf(tw, Vc[c8], num) : num;
+            den = use ? den + tw : den;
+        }
+        *out = den > 0.0f ? num / den : __builtin_nanf("");
+    }
+}
+
 // Pixels of staged requests (STAGED) or of requests that gather per pixel (!STAGED): two
 // kernels, so that the staged one keeps the register budget of its 8 slab reads.  A kernel
 // skips the other kind's requests one whole range at a time.
@@ -369,83 +442,40 @@ __global__ void __launch_bounds__(256) k_pixel_pass(const BatchReq* __restrict__
             blk += (next - blk + (int)gridDim.x - 1) / (int)gridDim.x * (int)gridDim.x - (int)gridDim.x;
             continue;
         }
-        const int W = su.W;
         const int p0 = ((blk - s_beg[r]) << kFlatShift) + (int)threadIdx.x;
-        for (int p = p0; p < p0 + kFlatBlock; p += 256) {
-        if (p >= W * su.H) break;
-        const int j = p / W, i = p - j * W;
-        float* out = su.out + p;
-        const int kact = su.kact;
-        SlicePos q;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            q.t[a] = su.T[a * 4 + 3];
-            q.e0[a] = su.T[a * 4 + 0];
-            q.e1[a] = su.T[a * 4 + 1];
-            q.o[a] = su.vol.origin[a];
-        }
-        q.inv_h = su.vol.inv_h;
-        q.sx = su.sx;
-        q.sy = su.sy;
-        const int n[3] = {su.vol.n[0], su.vol.n[1], su.vol.n[2]};
-        double c[3];
-        pixel_coords(q, i, j, c);
-        if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
-                           c[2] >= -1.0 && c[2] < (double)n[2])) {
-            *out = __builtin_nanf("");
-            continue;
-        }
-        if constexpr (!STAGED) {
-            *out = pixel_direct<DT, 2>(su.vol, su, kact, c);
-            continue;
+        if constexpr (STAGED) {
+            switch (uniform_i32(su.dax)) {
+                case 0: staged_block<0>(su, p0, scratch); break;
+                case 1: staged_block<1>(su, p0, scratch); break;
+                default: staged_block<2>(su, p0, scratch); break;
+            }
         } else {
-        if (su.ncand == 0) {        // unreachable: a pixel inside the grid implies a non-empty slab
-            *out = __builtin_nanf("");
-            continue;
-        }
-        const float* __restrict__ slab = scratch + su.v_off;
-        const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
-        const int b0[3] = {(int)f0, (int)f1, (int)f2};
-        const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
-        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-        const int pax = su.pax, qax = su.qax, dax = su.dax;
-        const int depth = su.depth, ntp = su.ntp, last = su.ncand - 1;
-        // corners inside the grid, as a bit mask over c8 = (dz << 2) | (dy << 1) | dx
-        const unsigned mx = ((unsigned)b0[0] < (unsigned)n[0] ? 0x55u : 0u) |
-                            ((unsigned)(b0[0] + 1) < (unsigned)n[0] ? 0xAAu : 0u);
-        const unsigned my = ((unsigned)b0[1] < (unsigned)n[1] ? 0x33u : 0u) |
-                            ((unsigned)(b0[1] + 1) < (unsigned)n[1] ? 0xCCu : 0u);
-        const unsigned mz = ((unsigned)b0[2] < (unsigned)n[2] ? 0x0Fu : 0u) |
-                            ((unsigned)(b0[2] + 1) < (unsigned)n[2] ? 0xF0u : 0u);
-        const unsigned inside = mx & my & mz;
-        // the cell's 4 columns (offsets along p, q): slab index of layer b0[dax]; the next layer
-        // along the dominant axis is 32 floats further.  A voxel with weight inside the grid
-        // always lies in the slab, so only a clamp keeps the other corners' reads in bounds.
-        const int bp = b0[pax], bq = b0[qax], bd = b0[dax];
-        int base[4];
+            const int W = su.W, npx = W * su.H;
+            for (int p = p0; p < p0 - (int)threadIdx.x + kFlatBlock && p < npx; p += 256) {
+                const int j = p / W, i = p - j * W;
+                float* out = su.out + p;
+                const int kact = su.kact;
+                SlicePos q;
 #pragma unroll
-        for (int col = 0; col < 4; ++col) {
-            const int vp = bp + (col & 1), vq = bq + (col >> 1);
-            base[col] = slab_index(vp - su.lo_p, vq - su.lo_q, bd - run_start(su, vp, vq), ntp, depth);
-        }
-        float tw[8], Vc[8];
-#pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) {
-            const int od = (c8 >> dax) & 1, col = ((c8 >> pax) & 1) | (((c8 >> qax) & 1) << 1);
-            const int ix = min(max(base[col] + (od << 5), 0), last);
-            Vc[c8] = slab[ix];
-            // absent corners get weight 0 and are skipped like the fused kernel's
-            tw[c8] = ((inside >> c8) & 1u) ? (wx[c8 & 1] * wy[(c8 >> 1) & 1]) * wz[c8 >> 2] : 0.0f;
-        }
-        float num = 0.0f, den = 0.0f;
-#pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) {
-            const bool use = tw[c8] > 0.0f && Vc[c8] == Vc[c8];
-            num = use ? __builtin_fmaf(tw[c8], Vc[c8], num) : num;
-            den = use ? den + tw[c8] : den;
-        }
-        *out = den > 0.0f ? num / den : __builtin_nanf("");
-        }
+                for (int a = 0; a < 3; ++a) {
+                    q.t[a] = su.T[a * 4 + 3];
+                    q.e0[a] = su.T[a * 4 + 0];
+                    q.e1[a] = su.T[a * 4 + 1];
+                    q.o[a] = su.vol.origin[a];
+                }
+                q.inv_h = su.vol.inv_h;
+                q.sx = su.sx;
+                q.sy = su.sy;
+                const int n[3] = {su.vol.n[0], su.vol.n[1], su.vol.n[2]};
+                double c[3];
+                pixel_coords(q, i, j, c);
+                if (kact == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
+                                   c[2] >= -1.0 && c[2] < (double)n[2])) {
+                    *out = __builtin_nanf("");
+                    continue;
+                }
+                *out = pixel_direct<DT, 2>(su.vol, su, kact, c);
+            }
         }
     }
 }
