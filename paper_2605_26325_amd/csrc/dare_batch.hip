@@ -20,11 +20,23 @@ namespace dare {
 // The per-voxel and per-pixel arithmetic and its order are those of the fused
 // kernel, so a batched request equals the same request resliced alone.
 
-// First voxel of the slab run of column (vp, vq): one below the slab or the grid floor.
-__device__ __forceinline__ int run_start(const SliceSetup& su, int vp, int vq) {
-    const float centre = su.c0[su.dax] - (su.fm[su.pax] * ((float)vp - su.c0[su.pax]) +
-                                          su.fm[su.qax] * ((float)vq - su.c0[su.qax])) * su.inv_md;
-    return max((int)floorf(centre - su.half), 0);
+// The fields of a request's setup that place its slab runs, for dominant axis DAX (p and q are
+// the other two axes, in the order the setup pass chose them).
+struct RunGeom {
+    float c0d, c0p, c0q, fmp, fmq, inv_md, half;
+};
+
+template <int DAX>
+__device__ __forceinline__ RunGeom run_geom(const SliceSetup& su) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    return RunGeom{su.c0[DAX], su.c0[PAX], su.c0[QAX], su.fm[PAX], su.fm[QAX], su.inv_md, su.half};
+}
+
+// First voxel of the slab run of column (vp, vq): one below the slab or the grid floor.  Both
+// passes place runs with this one function, so they agree on every run.
+__device__ __forceinline__ int run_start(const RunGeom& g, int vp, int vq) {
+    const float centre = g.c0d - (g.fmp * ((float)vp - g.c0p) + g.fmq * ((float)vq - g.c0q)) * g.inv_md;
+    return max((int)floorf(centre - g.half), 0);
 }
 
 static_assert(kSlabTileP == 8 && kSlabTileQ == 4, "slab tile indexing uses shifts by 3 and 5");
@@ -284,40 +296,69 @@ __device__ __forceinline__ void divmod(int x, int d, double inv_d, int& q, int& 
     }
 }
 
-// Slab candidate e: its brick and in-brick index, and whether it passes the plane-slab and
-// lateral tests.
-__device__ __forceinline__ bool slab_voxel(const SliceSetup& su, int e, int64_t& brick, int& local) {
-    const int dax = su.dax, pax = su.pax;
-    const int nd = su.vol.n[dax];
-    // slab order: column tiles of kSlabTileP x kSlabTileQ (p fastest), each with all its
-    // depth layers, so that a workgroup consumes whole brick rows and a pixel's 8 cell
-    // values share a few cache lines
-    const int w = e & (kSlabTileP * kSlabTileQ - 1), rest = e >> 5;
-    int tile, k, tq, tp;
-    divmod(rest, su.depth, su.inv_depth, tile, k);
-    divmod(tile, su.ntp, su.inv_ntp, tq, tp);
-    const int cp = tp * kSlabTileP + (w & (kSlabTileP - 1));
-    const int cq = tq * kSlabTileQ + (w >> 3);
-    const int vp = su.lo_p + cp, vq = su.lo_q + cq;
-    const int vdd = run_start(su, vp, vq) + k;
-    brick = 0;
-    local = 0;
-    if (cp < su.dim_p && cq < su.dim_q && vdd < nd) {
-        const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
-        const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
-        const int vz = dax == 2 ? vdd : (pax == 2 ? vp : vq);
-        const float d0 = (float)vx - su.c0[0], d1 = (float)vy - su.c0[1], d2 = (float)vz - su.c0[2];
-        const float dn = su.fm[0] * d0 + su.fm[1] * d1 + su.fm[2] * d2;
-        const float du = su.fu[0] * d0 + su.fu[1] * d1 + su.fu[2] * d2;
-        const float dv = su.fw[0] * d0 + su.fw[1] * d1 + su.fw[2] * d2;
-        if (fabsf(dn) < su.thr_n && du > -su.thr_u && du < su.len_u + su.thr_u && dv > -su.thr_v &&
-            dv < su.len_v + su.thr_v) {
-            brick = ((int64_t)(vz >> 3) * su.vol.nby + (vy >> 3)) * su.vol.nbx + (vx >> 3);
-            local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
-            return true;
+// One block of a request's slab whose normal's dominant axis is DAX: kVoxPerThread candidates
+// per thread (e0 = this thread's first), each placed in the slab order, tested against the
+// plane slab and the lateral extent, then blended over the surviving bins.  The request's
+// fields are read once per block.
+template <int DT, int DAX>
+__device__ __forceinline__ void voxel_block(const SliceSetup& su, int e0, float* __restrict__ scratch) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const RunGeom rg = run_geom<DAX>(su);
+    const int ncand = su.ncand, depth = su.depth, ntp = su.ntp, lo_p = su.lo_p, lo_q = su.lo_q;
+    const int dim_p = su.dim_p, dim_q = su.dim_q, nd = su.vol.n[DAX], nbx = su.vol.nbx, nby = su.vol.nby;
+    const double inv_depth = su.inv_depth, inv_ntp = su.inv_ntp;
+    float c0[3], fm[3], fu[3], fw[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = su.c0[a];
+        fm[a] = su.fm[a];
+        fu[a] = su.fu[a];
+        fw[a] = su.fw[a];
+    }
+    const float thr_n = su.thr_n, thr_u = su.thr_u, thr_v = su.thr_v;
+    const float hi_u = su.len_u + su.thr_u, hi_v = su.len_v + su.thr_v;
+    bool ok[kVoxPerThread];
+    int64_t brick[kVoxPerThread];
+    int local[kVoxPerThread];
+#pragma unroll
+    for (int u = 0; u < kVoxPerThread; ++u) {
+        const int e = e0 + 256 * u;
+        ok[u] = false;
+        brick[u] = 0;
+        local[u] = 0;
+        if (e >= ncand) continue;
+        // slab order: column tiles of kSlabTileP x kSlabTileQ (p fastest), each with all its
+        // depth layers, so that a workgroup consumes whole brick rows and a pixel's 8 cell
+        // values share a few cache lines
+        const int w = e & (kSlabTileP * kSlabTileQ - 1), rest = e >> 5;
+        int tile, k, tq, tp;
+        divmod(rest, depth, inv_depth, tile, k);
+        divmod(tile, ntp, inv_ntp, tq, tp);
+        const int cp = tp * kSlabTileP + (w & (kSlabTileP - 1));
+        const int cq = tq * kSlabTileQ + (w >> 3);
+        const int vp = lo_p + cp, vq = lo_q + cq;
+        const int vdd = run_start(rg, vp, vq) + k;
+        if (cp >= dim_p || cq >= dim_q || vdd >= nd) continue;
+        int v[3];
+        v[DAX] = vdd;
+        v[PAX] = vp;
+        v[QAX] = vq;
+        const float d0 = (float)v[0] - c0[0], d1 = (float)v[1] - c0[1], d2 = (float)v[2] - c0[2];
+        const float dn = fm[0] * d0 + fm[1] * d1 + fm[2] * d2;
+        const float du = fu[0] * d0 + fu[1] * d1 + fu[2] * d2;
+        const float dv = fw[0] * d0 + fw[1] * d1 + fw[2] * d2;
+        if (fabsf(dn) < thr_n && du > -thr_u && du < hi_u && dv > -thr_v && dv < hi_v) {
+            brick[u] = ((int64_t)(v[2] >> 3) * nby + (v[1] >> 3)) * nbx + (v[0] >> 3);
+            local[u] = (((v[2] & 7) << 3) | (v[1] & 7)) << 3 | (v[0] & 7);
+            ok[u] = true;
         }
     }
-    return false;
+    float V[kVoxPerThread];
+    blend_vox<DT>(su, ok, brick, local, V);
+    float* __restrict__ slab = scratch + su.v_off;
+#pragma unroll
+    for (int u = 0; u < kVoxPerThread; ++u)
+        if (e0 + 256 * u < ncand) slab[e0 + 256 * u] = V[u];
 }
 
 template <int DT>
@@ -331,21 +372,11 @@ __global__ void __launch_bounds__(256) k_voxel_pass(const BatchReq* __restrict__
         const int r = find_req(s_beg, nreq, blk);
         const SliceSetup& su = setups[r];
         const int e0 = ((blk - s_beg[r]) << kFlatShift) + (int)threadIdx.x;
-        const int ncand = su.ncand;
-        bool ok[kVoxPerThread];
-        int64_t brick[kVoxPerThread];
-        int local[kVoxPerThread];
-        float V[kVoxPerThread];
-#pragma unroll
-        for (int u = 0; u < kVoxPerThread; ++u) {
-            brick[u] = 0;
-            local[u] = 0;
-            ok[u] = e0 + 256 * u < ncand && slab_voxel(su, e0 + 256 * u, brick[u], local[u]);
+        switch (uniform_i32(su.dax)) {
+            case 0: voxel_block<DT, 0>(su, e0, scratch); break;
+            case 1: voxel_block<DT, 1>(su, e0, scratch); break;
+            default: voxel_block<DT, 2>(su, e0, scratch); break;
         }
-        blend_vox<DT>(su, ok, brick, local, V);
-#pragma unroll
-        for (int u = 0; u < kVoxPerThread; ++u)
-            if (e0 + 256 * u < ncand) scratch[su.v_off + e0 + 256 * u] = V[u];
     }
 }
 
@@ -371,6 +402,7 @@ __device__ __forceinline__ void staged_block(const SliceSetup& su, int p0, const
     const bool live = su.kact > 0 && su.ncand > 0;   // a pixel inside the grid implies a non-empty slab
     const float* __restrict__ slab = scratch + su.v_off;
     const int depth = su.depth, ntp = su.ntp, last = su.ncand - 1, lo_p = su.lo_p, lo_q = su.lo_q;
+    const RunGeom rg = run_geom<DAX>(su);
     const int pe = min(p0 - (int)threadIdx.x + kFlatBlock, npx);
     for (int p = p0; p < pe; p += 256) {
         const int j = p / W, i = p - j * W;
@@ -402,7 +434,7 @@ __device__ __forceinline__ void staged_block(const SliceSetup& su, int p0, const
 #pragma unroll
         for (int col = 0; col < 4; ++col) {
             const int vp = bp + (col & 1), vq = bq + (col >> 1);
-            base[col] = slab_index(vp - lo_p, vq - lo_q, bd - run_start(su, vp, vq), ntp, depth);
+            base[col] = slab_index(vp - lo_p, vq - lo_q, bd - run_start(rg, vp, vq), ntp, depth);
         }
         float Vc[8];
 #pragma unroll
