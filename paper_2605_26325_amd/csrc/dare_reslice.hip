@@ -39,6 +39,10 @@ constexpr int kBoxMax = 3072;        // LDS values per tile (its clamped voxel b
 constexpr int kBoxEdgeMax = 17;      // voxels per axis: the box spans at most 3 bricks
 constexpr int kSlotMax = 1024;       // (surviving bin, box brick) slots resolved per tile
 
+// Box sizes that the staging phases divide by: bricks of the box, bricks along x and y, run
+// depth, columns along p, voxels along x and y.
+enum { kDivNbb, kDivBdx, kDivBdy, kDivDepth, kDivDp, kDivDx, kDivDy };
+
 template <int DT>
 struct TileLds {
     int mode;                        // 0: nothing in reach, 1: staged, 2: per-pixel gather
@@ -46,6 +50,8 @@ struct TileLds {
     int blo[3], bdim[3], nbb;
     int dax, pax, qax;               // dominant normal axis, the other two
     int depth, ncols;
+    // divisions by the box's sizes (dividends below kBoxMax), indexed by the kDiv* names
+    SmallDiv div[7];
     float m[3], c0[3], ua[3], va[3];
     float thr_n, thr_u, thr_v, len_u, len_v, inv_md;
     int nlist;                       // staged voxels (compacted)
@@ -84,7 +90,8 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int f = (int)fmin(fmax(floor(c[a]), -1048576.0), 1048576.0);
-        int mn = f, mx = f;
+        // every lane of a group of 4 takes all four corners, so every lane holds the box
+        int mn = __shfl(f, 0, 4), mx = mn;
 #pragma unroll
         for (int o = 1; o < 4; ++o) {
             const int g = __shfl(f, o, 4);
@@ -95,10 +102,27 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
         hi[a] = min(mx + 2, n[a] - 1);
         c0[a] = (float)__shfl(c[a], 0, 4);
     }
+    // lanes 0..6 set up one division each, in parallel
+    const int dax = sh.dax;
+    float l1m = 0.0f;
+    int dd[3], bd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        l1m += fabsf(sh.fm[a]);
+        dd[a] = max(hi[a] - lo[a] + 1, 0);
+        bd[a] = dd[a] > 0 ? (hi[a] >> 3) - (lo[a] >> 3) + 1 : 0;
+    }
+    const int depth = (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(sh.fm[dax])) + 2;
+    if (lane < 7) {
+        const int dv = lane == kDivNbb ? bd[0] * bd[1] * bd[2] : lane == kDivBdx ? bd[0] : lane == kDivBdy ? bd[1]
+                     : lane == kDivDepth ? depth : lane == kDivDp ? dd[dax == 0 ? 1 : 0]
+                     : lane == kDivDx ? dd[0] : dd[1];
+        tl.div[lane] = small_div(dv);
+    }
     if (lane != 0) return;
     int mode = kact > 0 ? 1 : 0;
     int nvox = 1, nbb = 1;
-    float l1m = 0.0f, l1u = 0.0f, l1w = 0.0f;
+    float l1u = 0.0f, l1w = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (lo[a] > hi[a]) mode = 0;
@@ -114,7 +138,6 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
         tl.ua[a] = sh.fu[a];
         tl.va[a] = sh.fw[a];
         tl.c0[a] = c0[a];
-        l1m += fabsf(sh.fm[a]);
         l1u += fabsf(sh.fu[a]);
         l1w += fabsf(sh.fw[a]);
     }
@@ -125,7 +148,6 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
     // tile's first pixel: |m.(v - c0)| < |m|_1, and ua.(v - c0), va.(v - c0) within the
     // tile's extent widened by |ua|_1, |va|_1 (margins cover FP32 rounding and the
     // pose rigidity tolerance)
-    const int dax = sh.dax;
     tl.thr_n = l1m + 2e-3f;
     tl.thr_u = l1u + 0.02f;
     tl.thr_v = l1w + 0.02f;
@@ -135,7 +157,7 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
     tl.pax = dax == 0 ? 1 : 0;
     tl.qax = dax == 2 ? 1 : 2;
     tl.inv_md = 1.0f / sh.fm[dax];
-    tl.depth = mode == 1 ? (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(sh.fm[dax])) + 2 : 0;
+    tl.depth = mode == 1 ? depth : 0;
     tl.ncols = mode == 1 ? tl.dim[tl.pax] * tl.dim[tl.qax] : 0;
     tl.nlist = 0;
 }
@@ -255,6 +277,43 @@ __device__ __forceinline__ void blend_voxel_pair(const typename Pair<DT>::T* __r
     VB = B1 > 0.0f ? A1 / B1 : __builtin_nanf("");
 }
 
+// Phase (b) of a staged tile whose normal's dominant axis is DAX: the box voxels within the
+// slab and lateral extent of the tile's pixels, enumerated as runs along DAX (one per column
+// of the other two axes) and appended to the tile's list.
+template <int DT, int DAX>
+__device__ __forceinline__ void list_footprint(TileLds<DT>& tl) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const int depth = tl.depth;
+    const int nwork = tl.ncols * depth;
+    const int lo[3] = {tl.lo[0], tl.lo[1], tl.lo[2]}, dim[3] = {tl.dim[0], tl.dim[1], tl.dim[2]};
+    const float m[3] = {tl.m[0], tl.m[1], tl.m[2]}, c0[3] = {tl.c0[0], tl.c0[1], tl.c0[2]};
+    const float ua[3] = {tl.ua[0], tl.ua[1], tl.ua[2]}, va[3] = {tl.va[0], tl.va[1], tl.va[2]};
+    const float thr_n = tl.thr_n, thr_u = tl.thr_u, thr_v = tl.thr_v, len_u = tl.len_u, len_v = tl.len_v;
+    const float inv_md = tl.inv_md, half = thr_n * fabsf(inv_md);
+    const SmallDiv div_depth = tl.div[kDivDepth], div_dp = tl.div[kDivDp];
+    for (int e = threadIdx.x; e < nwork; e += blockDim.x) {
+        const int col = sdiv(e, div_depth), k = e - col * depth;
+        const int cq = sdiv(col, div_dp);
+        const int vp = lo[PAX] + (col - cq * div_dp.d), vq = lo[QAX] + cq;
+        const float centre = c0[DAX] - (m[PAX] * ((float)vp - c0[PAX]) + m[QAX] * ((float)vq - c0[QAX])) * inv_md;
+        // runs start one below the slab (or at the box floor): depth covers the whole slab
+        const int vdd = max((int)floorf(centre - half), lo[DAX]) + k;
+        if (vdd >= lo[DAX] + dim[DAX]) continue;
+        int v[3];
+        v[DAX] = vdd;
+        v[PAX] = vp;
+        v[QAX] = vq;
+        const float d0 = (float)v[0] - c0[0], d1 = (float)v[1] - c0[1], d2 = (float)v[2] - c0[2];
+        const float dn = m[0] * d0 + m[1] * d1 + m[2] * d2;
+        const float du = ua[0] * d0 + ua[1] * d1 + ua[2] * d2;
+        const float dv = va[0] * d0 + va[1] * d1 + va[2] * d2;
+        if (!(fabsf(dn) < thr_n && du > -thr_u && du < len_u + thr_u && dv > -thr_v && dv < len_v + thr_v))
+            continue;
+        const int idx = atomicAdd(&tl.nlist, 1);
+        tl.list[idx] = (unsigned short)(((v[2] - lo[2]) * dim[1] + (v[1] - lo[1])) * dim[0] + (v[0] - lo[0]));
+    }
+}
+
 // One 16x16 tile; the slice's setup (pose, surviving bins and weights, plane frame) is in `sh`.
 template <int DT>
 __device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceArgs& s, int unit, SetupLds& sh,
@@ -274,43 +333,21 @@ __device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceAr
         // (a) brick slots (and FP8 scales) of every surviving bin over the box's bricks
         const int nbb = tl.nbb;
         const int64_t nbricks = vd.nbricks;
+        const SmallDiv div_nbb = tl.div[kDivNbb], div_bdx = tl.div[kDivBdx], div_bdy = tl.div[kDivBdy];
         for (int e = threadIdx.x; e < kact * nbb; e += blockDim.x) {
-            const int k = e / nbb, r = e - k * nbb;
-            const int bxx = r % tl.bdim[0], byz = r / tl.bdim[0];
-            const int byy = byz % tl.bdim[1], bzz = byz / tl.bdim[1];
+            const int k = sdiv(e, div_nbb), r = e - k * nbb;
+            const int byz = sdiv(r, div_bdx), bxx = r - byz * div_bdx.d;
+            const int bzz = sdiv(byz, div_bdy), byy = byz - bzz * div_bdy.d;
             const int64_t brick = ((int64_t)(tl.blo[2] + bzz) * vd.nby + (tl.blo[1] + byy)) * vd.nbx + (tl.blo[0] + bxx);
             const int slot = vd.table[(int64_t)sh.act_bin[k] * nbricks + brick];
             tl.slot[e] = slot;
             if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = slot >= 0 ? vd.scales[slot] : make_float2(0.0f, 0.0f);
         }
         // (b) the voxels the tile touches, compacted into a list (ALU work only)
-        {
-            const int dax = tl.dax, pax = tl.pax, qax = tl.qax, depth = tl.depth;
-            const int nwork = tl.ncols * depth;
-            const int lo[3] = {tl.lo[0], tl.lo[1], tl.lo[2]}, dim[3] = {tl.dim[0], tl.dim[1], tl.dim[2]};
-            const float m[3] = {tl.m[0], tl.m[1], tl.m[2]}, c0[3] = {tl.c0[0], tl.c0[1], tl.c0[2]};
-            const float ua[3] = {tl.ua[0], tl.ua[1], tl.ua[2]}, va[3] = {tl.va[0], tl.va[1], tl.va[2]};
-            const float thr_n = tl.thr_n, thr_u = tl.thr_u, thr_v = tl.thr_v, len_u = tl.len_u, len_v = tl.len_v;
-            const float inv_md = tl.inv_md, half = thr_n * fabsf(inv_md);
-            for (int e = threadIdx.x; e < nwork; e += blockDim.x) {
-                const int col = e / depth, k = e - col * depth;
-                const int vp = lo[pax] + col % dim[pax], vq = lo[qax] + col / dim[pax];
-                const float centre = c0[dax] - (m[pax] * ((float)vp - c0[pax]) + m[qax] * ((float)vq - c0[qax])) * inv_md;
-                // runs start one below the slab (or at the box floor): depth covers the whole slab
-                const int vdd = max((int)floorf(centre - half), lo[dax]) + k;
-                if (vdd >= lo[dax] + dim[dax]) continue;
-                const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
-                const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
-                const int vz = dax == 2 ? vdd : (pax == 2 ? vp : vq);
-                const float d0 = (float)vx - c0[0], d1 = (float)vy - c0[1], d2 = (float)vz - c0[2];
-                const float dn = m[0] * d0 + m[1] * d1 + m[2] * d2;
-                const float du = ua[0] * d0 + ua[1] * d1 + ua[2] * d2;
-                const float dv = va[0] * d0 + va[1] * d1 + va[2] * d2;
-                if (!(fabsf(dn) < thr_n && du > -thr_u && du < len_u + thr_u && dv > -thr_v && dv < len_v + thr_v))
-                    continue;
-                const int idx = atomicAdd(&tl.nlist, 1);
-                tl.list[idx] = (unsigned short)(((vz - lo[2]) * dim[1] + (vy - lo[1])) * dim[0] + (vx - lo[0]));
-            }
+        switch (uniform_i32(tl.dax)) {
+            case 0: list_footprint<DT, 0>(tl); break;
+            case 1: list_footprint<DT, 1>(tl); break;
+            default: list_footprint<DT, 2>(tl); break;
         }
         __syncthreads();
         // (c) one thread per listed voxel (two when the list is longer than the workgroup): all
@@ -320,9 +357,11 @@ __device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceAr
         const int dxb = tl.dim[0], dyb = tl.dim[1];
         const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2];
         const int bx0 = tl.blo[0], by0 = tl.blo[1], bz0 = tl.blo[2], bdx = tl.bdim[0], bdy = tl.bdim[1];
+        const SmallDiv div_dx = tl.div[kDivDx], div_dy = tl.div[kDivDy];
         auto locate = [&](int bi, int& bb, int& local) {
-            const int ex = bi % dxb, eyz = bi / dxb;
-            const int vx = lox + ex, vy = loy + eyz % dyb, vz = loz + eyz / dyb;
+            const int eyz = sdiv(bi, div_dx), ex = bi - eyz * dxb;
+            const int ez = sdiv(eyz, div_dy), ey = eyz - ez * dyb;
+            const int vx = lox + ex, vy = loy + ey, vz = loz + ez;
             bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
             local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
         };

@@ -150,6 +150,27 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 
 constexpr int kBinChunk = 16;        // gathers issued together per voxel
 
+// Division by a divisor shared by a workgroup, for small dividends: x / d = the high word of
+// x * m with m = ceil(2^32 / d), exact for 0 <= x < 2^16 and 2 <= d < 2^16 (m exceeds 2^32 / d
+// by less than 1, which moves x * m / 2^32 by less than 2^-16, less than the 1/d gap between
+// x / d and the next integer).  d = 1 passes x through.  m is set from a correctly rounded FP64
+// quotient: 2^32 / d is either an integer (exact in FP64) or at least 1/d from one.
+struct SmallDiv {
+    uint32_t m;
+    int d;
+};
+
+__device__ __forceinline__ SmallDiv small_div(int d) {
+    SmallDiv s;
+    s.d = d;
+    s.m = d > 1 ? (uint32_t)ceil(4294967296.0 / (double)d) : 0u;
+    return s;
+}
+
+__device__ __forceinline__ int sdiv(int x, SmallDiv s) {
+    return s.d == 1 ? x : (int)__umulhi((uint32_t)x, s.m);
+}
+
 __device__ __forceinline__ VolView view_of(const VolDev* __restrict__ vd) {
     VolView v;
     v.table = vd->table;
