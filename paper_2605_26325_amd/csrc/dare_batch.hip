@@ -32,11 +32,13 @@ __device__ __forceinline__ RunGeom run_geom(const SliceSetup& su) {
     return RunGeom{su.c0[DAX], su.c0[PAX], su.c0[QAX], su.fm[PAX], su.fm[QAX], su.inv_md, su.half};
 }
 
-// First voxel of the slab run of column (vp, vq): one below the slab or the grid floor.  Both
+// First voxel of the slab run of column (vp, vq): the first whole voxel above centre - half, or
+// the grid floor.  The column's slab voxels are the integers in (centre - half, centre + half), at
+// most ceil(2 half) of them (half carries the slop that covers the FP32 rounding of centre).  Both
 // passes place runs with this one function, so they agree on every run.
 __device__ __forceinline__ int run_start(const RunGeom& g, int vp, int vq) {
     const float centre = g.c0d - (g.fmp * ((float)vp - g.c0p) + g.fmq * ((float)vq - g.c0q)) * g.inv_md;
-    return max((int)floorf(centre - g.half), 0);
+    return max((int)floorf(centre - g.half) + 1, 0);
 }
 
 static_assert(kSlabTileP == 8 && kSlabTileQ == 4, "slab tile indexing uses shifts by 3 and 5");
@@ -109,7 +111,7 @@ __device__ __forceinline__ void slab_setup(const VolDev* __restrict__ vd, const 
     su.thr_v = l1w + 0.02f + slop;
     su.inv_md = 1.0f / su.fm[dax];
     su.half = su.thr_n * fabsf(su.inv_md);
-    const float dep = ceilf(2.0f * su.half) + 2.0f;
+    const float dep = ceilf(2.0f * su.half);
     su.depth = dep <= (float)kSlabDepthMax ? (int)dep : kSlabDepthMax + 1;
     su.ntp = (su.dim_p + kSlabTileP - 1) / kSlabTileP;
     const int ntq = (su.dim_q + kSlabTileQ - 1) / kSlabTileQ;

@@ -53,7 +53,7 @@ struct TileLds {
     // divisions by the box's sizes (dividends below kBoxMax), indexed by the kDiv* names
     SmallDiv div[7];
     float m[3], c0[3], ua[3], va[3];
-    float thr_n, thr_u, thr_v, len_u, len_v, inv_md;
+    float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
     int nlist;                       // staged voxels (compacted)
     int slot[kSlotMax];
     float2 scale[DT == DARE_FP8_E4M3 ? kSlotMax : 1];
@@ -112,7 +112,10 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
         dd[a] = max(hi[a] - lo[a] + 1, 0);
         bd[a] = dd[a] > 0 ? (hi[a] >> 3) - (lo[a] >> 3) + 1 : 0;
     }
-    const int depth = (int)ceilf(2.0f * (l1m + 2e-3f) / fabsf(sh.fm[dax])) + 2;
+    // a column's voxels within the slab are the integers in (centre - half, centre + half), at
+    // most ceil(2 half) of them; half carries the slop that covers the FP32 rounding of centre
+    const float half = (l1m + 2e-3f) * fabsf(1.0f / sh.fm[dax]);
+    const int depth = (int)ceilf(2.0f * half);
     if (lane < 7) {
         const int dv = lane == kDivNbb ? bd[0] * bd[1] * bd[2] : lane == kDivBdx ? bd[0] : lane == kDivBdy ? bd[1]
                      : lane == kDivDepth ? depth : lane == kDivDp ? dd[dax == 0 ? 1 : 0]
@@ -157,6 +160,7 @@ __device__ __forceinline__ void tile_setup(const VolView& vd, const SliceArgs& s
     tl.pax = dax == 0 ? 1 : 0;
     tl.qax = dax == 2 ? 1 : 2;
     tl.inv_md = 1.0f / sh.fm[dax];
+    tl.half = half;
     tl.depth = mode == 1 ? depth : 0;
     tl.ncols = mode == 1 ? tl.dim[tl.pax] * tl.dim[tl.qax] : 0;
     tl.nlist = 0;
@@ -289,15 +293,15 @@ __device__ __forceinline__ void list_footprint(TileLds<DT>& tl) {
     const float m[3] = {tl.m[0], tl.m[1], tl.m[2]}, c0[3] = {tl.c0[0], tl.c0[1], tl.c0[2]};
     const float ua[3] = {tl.ua[0], tl.ua[1], tl.ua[2]}, va[3] = {tl.va[0], tl.va[1], tl.va[2]};
     const float thr_n = tl.thr_n, thr_u = tl.thr_u, thr_v = tl.thr_v, len_u = tl.len_u, len_v = tl.len_v;
-    const float inv_md = tl.inv_md, half = thr_n * fabsf(inv_md);
+    const float inv_md = tl.inv_md, half = tl.half;
     const SmallDiv div_depth = tl.div[kDivDepth], div_dp = tl.div[kDivDp];
     for (int e = threadIdx.x; e < nwork; e += blockDim.x) {
         const int col = sdiv(e, div_depth), k = e - col * depth;
         const int cq = sdiv(col, div_dp);
         const int vp = lo[PAX] + (col - cq * div_dp.d), vq = lo[QAX] + cq;
         const float centre = c0[DAX] - (m[PAX] * ((float)vp - c0[PAX]) + m[QAX] * ((float)vq - c0[QAX])) * inv_md;
-        // runs start one below the slab (or at the box floor): depth covers the whole slab
-        const int vdd = max((int)floorf(centre - half), lo[DAX]) + k;
+        // runs start at the first whole voxel above centre - half (or at the box floor)
+        const int vdd = max((int)floorf(centre - half) + 1, lo[DAX]) + k;
         if (vdd >= lo[DAX] + dim[DAX]) continue;
         int v[3];
         v[DAX] = vdd;
