@@ -426,30 +426,33 @@ __device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceAr
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
     const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
     const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
-    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-    const int lox = tl.lo[0], loy = tl.lo[1], loz = tl.lo[2], dx = tl.dim[0], dy = tl.dim[1], dz = tl.dim[2];
-    // indices first, then all 8 LDS reads at once (absent corners read entry 0 and are discarded)
+    // per-axis tent weights of the cell's two voxels, 0 for a voxel outside the box (the box lies
+    // inside the grid and holds every in-grid cell voxel of the tile); clamped box coordinates keep
+    // every LDS read in bounds, and corners of weight 0 are skipped (only voxels with weight were
+    // staged)
+    const int e0[3] = {x0 - tl.lo[0], y0 - tl.lo[1], z0 - tl.lo[2]};
+    const int dm[3] = {tl.dim[0], tl.dim[1], tl.dim[2]};
+    const float fr[3] = {fx, fy, fz};
+    float w[3][2];
+    int cc[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w[a][0] = (unsigned)e0[a] < (unsigned)dm[a] ? 1.0f - fr[a] : 0.0f;
+        w[a][1] = (unsigned)(e0[a] + 1) < (unsigned)dm[a] ? fr[a] : 0.0f;
+        cc[a][0] = min(max(e0[a], 0), dm[a] - 1);
+        cc[a][1] = min(max(e0[a] + 1, 0), dm[a] - 1);
+    }
     float tw[8], Vc[8];
-    int ix[8];
-    bool ok[8];
 #pragma unroll
     for (int c8 = 0; c8 < 8; ++c8) {                 // c8 = (dz << 2) | (dy << 1) | dx
         const int ddx = c8 & 1, ddy = (c8 >> 1) & 1, ddz = c8 >> 2;
-        tw[c8] = (wx[ddx] * wy[ddy]) * wz[ddz];      // only voxels with weight were staged
-        const int vx = x0 + ddx, vy = y0 + ddy, vz = z0 + ddz;
-        const int ex = vx - lox, ey = vy - loy, ez = vz - loz;
-        // the box holds every in-grid cell voxel of the tile: its test only bounds the index
-        ok[c8] = tw[c8] > 0.0f && (unsigned)vx < (unsigned)nx && (unsigned)vy < (unsigned)ny &&
-                 (unsigned)vz < (unsigned)nz && (unsigned)ex < (unsigned)dx && (unsigned)ey < (unsigned)dy &&
-                 (unsigned)ez < (unsigned)dz;
-        ix[c8] = ok[c8] ? (ez * dy + ey) * dx + ex : 0;
+        tw[c8] = (w[0][ddx] * w[1][ddy]) * w[2][ddz];
+        Vc[c8] = tl.V[(cc[2][ddz] * dm[1] + cc[1][ddy]) * dm[0] + cc[0][ddx]];
     }
-#pragma unroll
-    for (int c8 = 0; c8 < 8; ++c8) Vc[c8] = tl.V[ix[c8]];
     float num = 0.0f, den = 0.0f;
 #pragma unroll
     for (int c8 = 0; c8 < 8; ++c8) {
-        if (ok[c8] && Vc[c8] == Vc[c8]) {
+        if (tw[c8] > 0.0f && Vc[c8] == Vc[c8]) {
             num = __builtin_fmaf(tw[c8], Vc[c8], num);
             den = den + tw[c8];
         }

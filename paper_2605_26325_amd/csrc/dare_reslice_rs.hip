@@ -113,7 +113,9 @@ __device__ __forceinline__ void tile_setup_r(const VolDev* __restrict__ vd, cons
     tl.pax = dax == 0 ? 1 : 0;
     tl.qax = dax == 2 ? 1 : 2;
     tl.inv_md = 1.0f / sh.fm[dax];
-    tl.depth = mode == 1 ? (int)ceilf(2.0f * tl.thr_n / fabsf(sh.fm[dax])) + 2 : 0;
+    // a column's voxels in reach are the integers in (centre - half, centre + half), half =
+    // thr_n / |m[dax]|: at most ceil(2 half) of them, the first one above centre - half
+    tl.depth = mode == 1 ? (int)ceilf(2.0f * (tl.thr_n * fabsf(tl.inv_md))) : 0;
     tl.ncols = mode == 1 ? tl.dim[tl.pax] * tl.dim[tl.qax] : 0;
     tl.nlist = 0;
 }
@@ -231,7 +233,7 @@ __device__ __forceinline__ void reslice_tile_rs(const VolDev* __restrict__ vd, c
                 const int col = e / depth, k = e - col * depth;
                 const int vp = lo[pax] + col % dim[pax], vq = lo[qax] + col / dim[pax];
                 const float centre = c0[dax] - (m[pax] * ((float)vp - c0[pax]) + m[qax] * ((float)vq - c0[qax])) * inv_md;
-                const int vdd = max((int)floorf(centre - half), lo[dax]) + k;
+                const int vdd = max((int)floorf(centre - half) + 1, lo[dax]) + k;
                 if (vdd >= lo[dax] + dim[dax]) continue;
                 const int vx = dax == 0 ? vdd : (pax == 0 ? vp : vq);
                 const int vy = dax == 1 ? vdd : (pax == 1 ? vp : vq);
