@@ -351,7 +351,7 @@ __device__ __forceinline__ void voxel_block(const SliceSetup& su, int e0, float*
         const float dv = fw[0] * d0 + fw[1] * d1 + fw[2] * d2;
         if (fabsf(dn) < thr_n && du > -thr_u && du < hi_u && dv > -thr_v && dv < hi_v) {
             brick[u] = ((int64_t)(v[2] >> 3) * nby + (v[1] >> 3)) * nbx + (v[0] >> 3);
-            local[u] = (((v[2] & 7) << 3) | (v[1] & 7)) << 3 | (v[0] & 7);
+            local[u] = brick_local(v[0], v[1], v[2]);
             ok[u] = true;
         }
     }

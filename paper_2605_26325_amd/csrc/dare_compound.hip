@@ -45,10 +45,6 @@ __device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, 
     return (int64_t)b * vd->nbricks + ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
 }
 
-__device__ __forceinline__ int brick_local(int vx, int vy, int vz) {
-    return (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
-}
-
 }  // namespace
 
 // K1: T = P . C per frame (row-major, summed left to right), rigidity check of P.

@@ -24,6 +24,17 @@ namespace dare {
 
 constexpr int kBrick = 8;
 constexpr int kBrickVox = 512;
+
+// Position of voxel (vx, vy, vz) inside its 8^3 brick.  The brick is 64 cubes of 2 x 2 x 2
+// voxels (x fastest inside a cube), the cubes ordered z fastest, then y, then x: a 128-byte line
+// of FP32 pairs holds a 2 x 2 x 4 block (BF16: 2 x 2 x 8), so the 2-3 voxel thick slab of a
+// slice whose normal is near x or y (freehand sweeps image near-vertical planes) uses most of
+// every line it touches, where x-fastest rows of 8 would be used for 2-3 voxels of 8 when the
+// normal is near x.  Every kernel that reads or writes brick storage (accumulators, stored
+// pairs) takes positions from here.
+__host__ __device__ inline int brick_local(int vx, int vy, int vz) {
+    return ((vx & 6) << 6) | ((vy & 6) << 4) | ((vz & 6) << 2) | ((vz & 1) << 2) | ((vy & 1) << 1) | (vx & 1);
+}
 constexpr int kMaxBins = 64;
 constexpr int kFrameChunk = 4096;
 constexpr int kTile = 16;                 // reslice output tile edge (pixels)

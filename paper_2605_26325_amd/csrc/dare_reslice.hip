@@ -367,7 +367,7 @@ __device__ __forceinline__ void reslice_tile_r1(const VolView& vd, const SliceAr
             const int ez = sdiv(eyz, div_dy), ey = eyz - ez * dyb;
             const int vx = lox + ex, vy = loy + ey, vz = loz + ez;
             bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
-            local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+            local = brick_local(vx, vy, vz);
         };
         if (nlist <= (int)blockDim.x) {
             for (int e = threadIdx.x; e < nlist; e += blockDim.x) {

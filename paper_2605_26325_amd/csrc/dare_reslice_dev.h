@@ -208,7 +208,7 @@ __device__ __forceinline__ float pixel_direct(const VolView& vv, const SetupLds&
         const int vx = x0 + (v & 1), vy = y0 + ((v >> 1) & 1), vz = z0 + (v >> 2);
         in[v] = (unsigned)vx < (unsigned)nx && (unsigned)vy < (unsigned)ny && (unsigned)vz < (unsigned)nz;
         tix[v] = in[v] ? ((vz >> 3) * nby + (vy >> 3)) * nbx + (vx >> 3) : 0;
-        lix[v] = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+        lix[v] = brick_local(vx, vy, vz);
     }
     const typename PT::T* __restrict__ data = (const typename PT::T*)vv.data;
     const int64_t nbricks = vv.nbricks;
@@ -316,7 +316,6 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
             const float tyz = ty * tz;
             if (!(tyz > 0.0f)) continue;
             const int rb = ((vz >> 3) * nby + (vy >> 3)) * nbx;
-            const int rl = ((vz & 7) << 6) | ((vy & 7) << 3);
             for (int ox = -R + 1; ox <= R; ++ox) {
                 const int vx = x0 + ox;
                 if ((unsigned)vx >= (unsigned)nx) continue;
@@ -331,7 +330,7 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
                     float2 sc = make_float2(0.0f, 0.0f);
                     if constexpr (DT == DARE_FP8_E4M3) sc = vd->scales[slot];
                     float a, cnt;
-                    PT::decode(data[(size_t)slot * kBrickVox + (rl | (vx & 7))], sc, a, cnt);
+                    PT::decode(data[(size_t)slot * kBrickVox + brick_local(vx, vy, vz)], sc, a, cnt);
                     const float wc = sh.act_w[k] * cnt;
                     A = __builtin_fmaf(wc, a, A);
                     B = B + wc;

@@ -168,7 +168,7 @@ __device__ __forceinline__ float voxel_value(const VolDev* __restrict__ vd, cons
     const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
     const int64_t nbricks = vd->nbricks;
     const int64_t brick = ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
-    const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+    const int local = brick_local(vx, vy, vz);
     if (kact == 1) {
         const int slot = vd->table[(int64_t)sh.act_bin[0] * nbricks + brick];
         if (slot < 0) return __builtin_nanf("");
@@ -260,7 +260,7 @@ __device__ __forceinline__ void reslice_tile_rs(const VolDev* __restrict__ vd, c
             const int ex = bi % dxb, eyz = bi / dxb;
             const int vx = lox + ex, vy = loy + eyz % dyb, vz = loz + eyz / dyb;
             const int bb = (((vz >> 3) - bz0) * bdy + ((vy >> 3) - by0)) * bdx + ((vx >> 3) - bx0);
-            const int local = (((vz & 7) << 3) | (vy & 7)) << 3 | (vx & 7);
+            const int local = brick_local(vx, vy, vz);
             tl.V[bi] = blend_voxel_r<DT, R>(data, sh, tl, kact, bb, local);
         }
         __syncthreads();
