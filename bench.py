@@ -424,6 +424,7 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--saturation-seconds", type=float, default=4.0)
     ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--no-literal", action="store_true")
     ap.add_argument("--streaming-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -690,6 +691,54 @@ def main():
         torch.cuda.synchronize()
         del rad_out
 
+    # ---- per-sample store (Sec. 2.1's flat per-sample storage read literally): built from the same
+    # frames; the first 100 slices resliced one launch each in both readings; the tent reading
+    # compared with the binned FP32 volume above (the binning approximation at its tolerance)
+    literal_res = None
+    if not args.no_forms and not args.no_literal:
+        nl = min(100, len(specs))
+        store = dare.SampleStore(geom, int(F) * Wf * Hf, int(F))
+        builds = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_samples = store.build(frames, poses, pitch_f)
+            torch.cuda.synchronize()
+            builds.append(time.perf_counter() - t0)
+        prm_l = dare.default_params()
+        lit_fn = dare.lib.dare_samples_reslice
+        lit_out = torch.empty((nl, H, W), dtype=torch.float32, device=dev)
+        lit_ptrs = [ct.c_void_p(lit_out[k].data_ptr()) for k in range(nl)]
+        literal_res = {"samples": int(n_samples), "build_ms": round(1e3 * min(builds), 2),
+                       "store_MB": round(store.arena.numel() / 1e6, 1), "slices": nl}
+        for mode_name, mode in (("box", 0), ("tent", 1)):
+            for k in range(nl):
+                lit_fn(store.handle, ct.byref(prm_l), spec_refs[k], mode, lit_ptrs[k], sh)
+            torch.cuda.synchronize()
+            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e_a.record(stream)
+            for k in range(nl):
+                st_l = lit_fn(store.handle, ct.byref(prm_l), spec_refs[k], mode, lit_ptrs[k], sh)
+                if st_l != 0:
+                    raise dare.DareError(st_l, "dare_samples_reslice")
+            e_b.record(stream)
+            torch.cuda.synchronize()
+            ms = e_a.elapsed_time(e_b) / nl
+            literal_res[mode_name] = {"ms_per_slice": round(ms, 4), "Mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1)}
+            if mode_name == "tent":
+                a, b = lit_out.double(), outs[:nl].double()
+                both = torch.isfinite(a) & torch.isfinite(b)
+                d = (a - b).abs()[both]
+                literal_res["tent_vs_binned_fp32"] = {
+                    "bin_tol_deg": float(dare.default_params().bin_tol_deg), "pixels": int(both.sum().item()),
+                    "max_abs_grey": round(float(d.max().item()) if d.numel() else 0.0, 4),
+                    "mean_abs_grey": round(float(d.mean().item()) if d.numel() else 0.0, 5),
+                    "nan_mask_mismatch": int((torch.isfinite(a) != torch.isfinite(b)).sum().item())}
+            log(f"per-sample store {mode_name}: {ms * 1e3:.1f} us per 512^2 slice ({n_samples} samples)")
+        log(f"per-sample store: {literal_res}")
+        del store, lit_out
+        torch.cuda.synchronize()
+
     # GPU results on the oracle's sample, kept before the serving form frees the volumes
     ncs = min(args.cpu_slices, len(specs))
     sample_out = {}
@@ -837,6 +886,7 @@ def main():
                         "input_Mpx_s": round(F * Wf * Hf / float(np.median(recon_times)) / 1e6, 1)},
         "forms": forms,
         "radius_sweep": radius,
+        "per_sample_store": literal_res,
         "serving": serving,
         "streaming": streaming,
         "cpu_baseline": cpu_baseline,

@@ -213,6 +213,63 @@ dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n_host, co
 dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* spec, int32_t* bins_out,
                                    double* weights_out, int32_t* count);
 
+/* ------------------------------------------------------------------------
+ * Per-sample store: Sec. 2.1 read literally (Fig. 1: every grid location
+ * points into a flat store of the samples that landed there, each with its
+ * own acquisition orientation; "Reslicing": every sample weighed by Eq. 1,
+ * the two thresholds and Eq. 2 with its own frame's orientation).  No
+ * direction bins: this is the formulation the binned volume approximates
+ * (with bin_tol_deg = 0 and the tent reading the two agree), at GPU speed.
+ * A store lives in a caller-supplied arena on the current device.
+ * ------------------------------------------------------------------------ */
+typedef struct dare_samples dare_samples;
+
+/* Reslice readings of the per-sample store, for output position c and radius R:
+ *   BOX   the (2R+1)^3 voxels around the nearest voxel floor(c + 0.5), one
+ *         weighted average over all their samples: sum w I / sum w;
+ *   TENT  the voxels with |c - v|_inf < R, each averaged over its samples
+ *         (sum w I / sum w), then averaged with tent weights
+ *         prod(1 - |c_a - v_a| / R) over the voxels with weight (the
+ *         reading dare_reslice uses).
+ * A pixel whose neighbourhood holds no sample of positive weight is NaN. */
+typedef enum { DARE_LITERAL_BOX = 0, DARE_LITERAL_TENT = 1 } dare_literal_mode;
+
+/* Arena bytes for a store over geometry g holding up to max_samples samples
+ * (every in-grid frame pixel is one) from up to max_frames frames; 0 for
+ * invalid arguments. */
+uint64_t dare_samples_arena_bytes(const dare_geometry* g, int64_t max_samples, int32_t max_frames);
+/* Create an empty store in [arena_dev, arena_dev + arena_bytes) (256-byte
+ * aligned, kept allocated until destroy).  max_samples <= 2^32 - 1,
+ * 1 <= max_frames <= 2^24.  Synchronous.  Errors: INVALID_ARG, BAD_POSE
+ * (calibration not rigid), HIP. */
+dare_status dare_samples_create(const dare_geometry* g, int64_t max_samples, int32_t max_frames, void* arena_dev,
+                                uint64_t arena_bytes, dare_samples** out);
+/* Release the handle (not the arena).  Synchronises the device first. */
+dare_status dare_samples_destroy(dare_samples* s);
+/* Replace the store's content with the samples of n frames: every pixel's
+ * nearest voxel (floor(c + 0.5), positions as for dare_reconstruct_frames),
+ * kept with its intensity and frame; pixels outside the grid are dropped.
+ * The frames' acquisition normal is column normal_axis (1 or 2) of
+ * T = P . C.  frames_dev: n * h * w uint8; probe_poses_dev: n * 16 float32,
+ * row-major.  Synchronises `stream` twice (pose check, sample count); the
+ * placing pass is left enqueued.  Errors: INVALID_ARG (n > max_frames),
+ * BAD_POSE, BUDGET (more samples than max_samples), HIP; on any error the
+ * store is left empty. */
+dare_status dare_samples_build(dare_samples* s, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
+                               const double pitch_mm[2], const float* probe_poses_dev, int32_t normal_axis,
+                               void* stream);
+/* Samples and frames the last build stored (host bookkeeping, no sync). */
+dare_status dare_samples_count(const dare_samples* s, int64_t* n_samples, int32_t* n_frames);
+/* Reslice one plane from the store in the given reading (dare_literal_mode)
+ * with parameters p (radius_vox, thresholds, k_normal, k_inplane;
+ * normal_axis must equal the build's): a per-frame weight table for the
+ * slice, then one kernel over the output pixels.  out_dev: height * width
+ * float32, row-major, NaN where unassigned.  Calls on one store must not
+ * overlap in time (they share the weight table).  Errors: INVALID_ARG,
+ * BAD_POSE, HIP. */
+dare_status dare_samples_reslice(const dare_samples* s, const dare_params* p, const dare_slice_spec* spec,
+                                 int32_t mode, float* out_dev, void* stream);
+
 /* Streaming copy of n_bytes (multiple of 16) from src_dev to dst_dev: the
  * bandwidth probe that calibrates the HBM roofline and the byte counters. */
 dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes, void* stream);

@@ -126,6 +126,12 @@ def _load():
         "dare_server_drain": (ct.c_int, [V]),
         "dare_server_get_stats": (ct.c_int, [V, ct.POINTER(ServerStats)]),
         "dare_server_destroy": (ct.c_int, [V]),
+        "dare_samples_arena_bytes": (U64, [ct.POINTER(Geometry), I64, I32]),
+        "dare_samples_create": (ct.c_int, [ct.POINTER(Geometry), I64, I32, P, U64, ct.POINTER(V)]),
+        "dare_samples_destroy": (ct.c_int, [V]),
+        "dare_samples_build": (ct.c_int, [V, P, I32, I32, I32, ct.POINTER(D), P, I32, P]),
+        "dare_samples_count": (ct.c_int, [V, ct.POINTER(I64), ct.POINTER(I32)]),
+        "dare_samples_reslice": (ct.c_int, [V, ct.POINTER(Params), ct.POINTER(SliceSpec), I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -342,6 +348,64 @@ class Volume:
         rx = (ct.c_double * max(1, 3 * K))(*np.asarray(rep_x, np.float64).reshape(-1).tolist())
         return _check(lib.dare_volume_upload_sums(self.handle, rn, rx, K, _ptr(S.contiguous()),
                                                   _ptr(C.contiguous()), _stream(stream)), "dare_volume_upload_sums")
+
+
+LITERAL_MODES = {"box": 0, "tent": 1}
+
+
+class SampleStore:
+    """Per-sample store (every in-grid frame pixel kept with its own frame's orientation) in a
+    torch-owned device arena; reslices it in the box or tent reading."""
+
+    def __init__(self, geometry: Geometry, max_samples: int, max_frames: int, device="cuda"):
+        import torch
+        self.geometry = geometry
+        nbytes = lib.dare_samples_arena_bytes(ct.byref(geometry), int(max_samples), int(max_frames))
+        if nbytes == 0:
+            raise DareError(ERR_INVALID_ARG, "dare_samples_arena_bytes")
+        self.arena = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        h = ct.c_void_p()
+        _check(lib.dare_samples_create(ct.byref(geometry), int(max_samples), int(max_frames), _ptr(self.arena),
+                                       int(nbytes), ct.byref(h)), "dare_samples_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.dare_samples_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, frames, probe_poses, pitch, normal_axis=2, stream=None) -> int:
+        """frames: (F, H, W) uint8 device tensor; probe_poses: (F, 4, 4) float32 device tensor."""
+        F, H, W = frames.shape
+        p = (ct.c_double * 2)(float(pitch[0]), float(pitch[1]))
+        _check(lib.dare_samples_build(self.handle, _ptr(frames.contiguous()), int(F), int(W), int(H), p,
+                                      _ptr(probe_poses.contiguous()), int(normal_axis), _stream(stream)),
+               "dare_samples_build", allow_warn=False)
+        return self.count()[0]
+
+    def count(self):
+        n = ct.c_int64()
+        f = ct.c_int32()
+        _check(lib.dare_samples_count(self.handle, ct.byref(n), ct.byref(f)), "dare_samples_count")
+        return n.value, f.value
+
+    def reslice(self, probe_pose, width, height, pitch, params: Params | None = None, mode="box", out=None,
+                stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((height, width), dtype=torch.float32, device=self.arena.device)
+        prm = params if params is not None else default_params()
+        _check(lib.dare_samples_reslice(self.handle, ct.byref(prm), ct.byref(make_spec(probe_pose, width, height,
+                                                                                         pitch)),
+                                        LITERAL_MODES[mode] if isinstance(mode, str) else int(mode), _ptr(out),
+                                        _stream(stream)), "dare_samples_reslice", allow_warn=False)
+        return out
 
 
 def default_server_config(**over) -> ServerConfig:

@@ -10,6 +10,7 @@
 #include <tuple>
 #include <vector>
 
+#include "dare_host.h"
 #include "dare_staged.h"
 
 using namespace dare;
@@ -33,18 +34,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kBatchGrid = 2048;   // workgroups of each batched pass (grid-stride)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 bool finite_all(const double* v, int n) {
     for (int k = 0; k < n; ++k)
@@ -140,14 +129,6 @@ Layout layout(const dare_geometry* g, const dare_params* p, int dtype, uint64_t 
     L.end = off;
     return L;
 }
-
-dare_status hip_status(hipError_t e) { return e == hipSuccess ? DARE_OK : DARE_ERR_HIP; }
-
-#define HIP_TRY(expr)                                 \
-    do {                                              \
-        hipError_t _e = (expr);                       \
-        if (_e != hipSuccess) return DARE_ERR_HIP;    \
-    } while (0)
 
 // Device header at a sync point: the state, and the codebook the host keeps a copy of (the
 // per-slice setup is computed on the host from it).
@@ -259,6 +240,10 @@ int volume_dtype(const dare_volume* v) { return v->dtype; }
 int volume_radius(const dare_volume* v) { return (int)v->p.radius_vox; }
 int volume_device_id(const dare_volume* v) { return v->device; }
 dare_status check_slice_spec(const dare_slice_spec* s) { return check_spec(s); }
+bool rigid_pose(const double* M) { return rigid(M); }
+void compose_pose(const double* P, const double* C, double* T) { compose_host(P, C, T); }
+dare_status check_method_params(const dare_params* p) { return check_params(p); }
+dare_status check_volume_geometry(const dare_geometry* g) { return check_geometry(g); }
 }  // namespace dare
 
 namespace {

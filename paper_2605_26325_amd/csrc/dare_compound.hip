@@ -7,6 +7,7 @@
 #include <math.h>
 
 #include "dare_codec.h"
+#include "dare_frames.h"
 #include "dare_internal.h"
 
 #pragma clang fp contract(off)
@@ -19,26 +20,10 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
 }
 
-__device__ __forceinline__ double norm3(const double* v) { return sqrt(dot3(v, v)); }
-
 // Nearest voxel of frame pixel (i, j); false when outside the grid.
 __device__ __forceinline__ bool pixel_voxel(const VolDev* __restrict__ vd, const FrameDesc* __restrict__ fd,
                                             int i, int j, double sx, double sy, int& vx, int& vy, int& vz) {
-    const double is = (double)i * sx;
-    const double js = (double)j * sy;
-    double c[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double p = (fd->t[a] + is * fd->e0[a]) + js * fd->e1[a];
-        c[a] = floor((p - vd->origin[a]) * vd->inv_h + 0.5);
-    }
-    if (!(c[0] >= 0.0 && c[0] < (double)vd->nx && c[1] >= 0.0 && c[1] < (double)vd->ny && c[2] >= 0.0 &&
-          c[2] < (double)vd->nz))
-        return false;
-    vx = (int)c[0];
-    vy = (int)c[1];
-    vz = (int)c[2];
-    return true;
+    return frame_voxel(fd, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, i, j, sx, sy, vx, vy, vz);
 }
 
 __device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, int vy, int vz) {
@@ -51,49 +36,8 @@ __device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, 
 __global__ void k_compose_frames(VolDev* vd, const float* __restrict__ poses, int n) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n) return;
-    double P[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) P[k] = (double)poses[(size_t)f * 16 + k];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ok = ok && isfinite(P[k]);
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            double d = (P[a] * P[b] + P[4 + a] * P[4 + b]) + P[8 + a] * P[8 + b];
-            ok = ok && fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-4;
-        }
-    ok = ok && fabs(P[12]) <= 1e-4 && fabs(P[13]) <= 1e-4 && fabs(P[14]) <= 1e-4 && fabs(P[15] - 1.0) <= 1e-4;
-    if (!ok) atomicOr(&vd->st.bad_pose, 1);
-    const double* C = vd->calib;
-    double T[12];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double acc = P[r * 4 + 0] * C[0 * 4 + c];
-            acc = acc + P[r * 4 + 1] * C[1 * 4 + c];
-            acc = acc + P[r * 4 + 2] * C[2 * 4 + c];
-            acc = acc + P[r * 4 + 3] * C[3 * 4 + c];
-            T[r * 4 + c] = acc;
-        }
     FrameDesc d;
-    double e2[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        d.t[a] = T[a * 4 + 3];
-        d.e0[a] = T[a * 4 + 0];
-        d.e1[a] = T[a * 4 + 1];
-        e2[a] = T[a * 4 + 2];
-    }
-    const double l0 = norm3(d.e0);
-    const double* en = vd->normal_axis == 1 ? d.e1 : e2;
-    const double ln = norm3(en);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        d.xh[a] = d.e0[a] / l0;
-        d.nh[a] = en[a] / ln;
-    }
-    d.pad = 0.0;
+    if (!compose_frame(poses + (size_t)f * 16, vd->calib, vd->normal_axis, d)) atomicOr(&vd->st.bad_pose, 1);
     vd->frames[f] = d;
 }
 

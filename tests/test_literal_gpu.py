@@ -1,0 +1,164 @@
+"""GPU per-sample store (Sec. 2.1 read literally) against the per-sample oracle
+(`oracle.literal`): random tiny scenes with frames at scattered orientations (some gated by
+either threshold), both readings (box, one normalisation over samples; tent, per voxel then by
+distance) at R = 1 and 2, a subset of the config-1 sweeps, the tent reading against the binned
+volume with bin tolerance 0, and the error paths.  Bar: |d| <= 1e-5 max(|ref|, 1), identical
+NaN masks (the store's per-frame weights are FP32, the oracle's FP64).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import assert_parity, lib_params, make_volume, note
+from helpers import pose_from_axes, random_unit, rodrigues
+from oracle import literal
+from oracle.reslice import Params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dare():
+    import paper_2605_26325_amd as d
+    return d
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _scene(seed, dims=(9, 8, 7), h=0.5, F=6, fw=5, fh=4, pitch=(0.45, 0.4)):
+    rng = np.random.default_rng(seed)
+    origin = np.array([-850.0, 310.0, -1620.0]) + rng.uniform(-1, 1, 3)
+    calib = pose_from_axes(random_unit(rng), random_unit(rng), rng.normal(0, 5, 3))
+    n0 = random_unit(rng)
+    x0 = random_unit(rng)
+    centre = origin + h * (np.array(dims) - 1) / 2
+    poses = []
+    for _ in range(F):            # orientations up to ~35 deg from (n0, x0): some frames gated
+        R = rodrigues(random_unit(rng), math.radians(rng.uniform(0, 35)))
+        x, n = R @ x0, R @ n0
+        T = pose_from_axes(x, n, np.zeros(3))
+        T[:3, 3] = centre + rng.normal(0, 0.6, 3) - T[:3, 0] * (fw - 1) * pitch[0] / 2 - \
+            T[:3, 1] * (fh - 1) * pitch[1] / 2
+        poses.append(T @ np.linalg.inv(calib))
+    poses = np.asarray(poses, np.float32)          # the library takes FP32 probe poses
+    frames = rng.integers(0, 256, size=(F, fh, fw), dtype=np.uint8)
+    return rng, origin, h, dims, calib, poses, frames, pitch, n0, x0, centre
+
+
+def _slice(rng, calib, n0, x0, centre, W, H, pitch, spread=20.0):
+    R = rodrigues(random_unit(rng), math.radians(rng.uniform(0, spread)))
+    T = pose_from_axes(R @ x0, R @ n0, np.zeros(3))
+    T[:3, 3] = centre + rng.normal(0, 0.5, 3) - T[:3, 0] * (W - 1) * pitch[0] / 2 - T[:3, 1] * (H - 1) * pitch[1] / 2
+    return T @ np.linalg.inv(calib)
+
+
+def _store(dare, torch, origin, h, dims, calib, poses, frames, pitch, normal_axis=2, max_samples=None):
+    g = dare.make_geometry(origin, h, dims, calib)
+    F, H, W = frames.shape
+    st = dare.SampleStore(g, max_samples if max_samples is not None else F * H * W, F)
+    st.build(torch.from_numpy(frames).cuda(), torch.from_numpy(poses).cuda(), pitch, normal_axis)
+    torch.cuda.synchronize()
+    return st
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_tiny_scenes_both_readings(dare, torch_cuda, seed):
+    torch = torch_cuda
+    rng, origin, h, dims, calib, poses, frames, pitch, n0, x0, centre = _scene(seed)
+    note(f"per-sample store, tiny scene seed {seed}")
+    st = _store(dare, torch, origin, h, dims, calib, poses, frames, pitch)
+    ref_store = literal.SampleStore(origin, h, dims, normal_axis=2)
+    ref_store.add_frames(frames, poses.astype(np.float64), calib, pitch)
+    assert st.count()[0] == sum(len(v) for v in ref_store.samples.values())
+    checked = 0
+    for k in range(4):
+        W, H, sp = 7, 5, (0.3, 0.35)
+        P = _slice(rng, calib, n0, x0, centre, W, H, sp)
+        for R in (1, 2):
+            prm = Params(radius_vox=R)
+            for mode, spatial, norm in (("box", "box", "sample"), ("tent", "tent", "two_stage")):
+                got = st.reslice(P, W, H, sp, lib_params(prm), mode).cpu().numpy()
+                ref = literal.reslice(ref_store, calib, P, W, H, sp, prm, spatial=spatial, norm=norm)
+                checked += assert_parity(got, ref, what=f"seed {seed} slice {k} R {R} {mode}")
+    assert checked > 0
+
+
+def test_config1_subset(dare, torch_cuda):
+    torch = torch_cuda
+    wl = synth.config1()
+    frames = wl.render("cpu").numpy()
+    sel = list(range(0, 100, 8)) + list(range(100, 200, 8))      # both sweeps
+    fr = np.ascontiguousarray(frames[sel])
+    poses = np.asarray(wl.sweep.probe_poses, np.float32)[sel]
+    note(f"per-sample store, config 1 subset of {len(sel)} frames")
+    st = _store(dare, torch, wl.origin, wl.spacing, wl.dims, wl.calib, poses, fr, wl.sweep.pitch)
+    ref_store = literal.SampleStore(wl.origin, wl.spacing, wl.dims, normal_axis=2)
+    ref_store.add_frames(fr, poses.astype(np.float64), wl.calib, wl.sweep.pitch)
+    assert st.count() == (sum(len(v) for v in ref_store.samples.values()), len(sel))
+    prm = Params()
+    checked = 0
+    for k in range(3):
+        P = wl.slices.probe_poses[k]
+        for mode, spatial, norm in (("box", "box", "sample"), ("tent", "tent", "two_stage")):
+            got = st.reslice(P, 20, 20, (0.5, 0.5), lib_params(prm), mode).cpu().numpy()
+            ref = literal.reslice(ref_store, wl.calib, P, 20, 20, (0.5, 0.5), prm, spatial=spatial, norm=norm)
+            checked += assert_parity(got, ref, what=f"config-1 slice {k} {mode}")
+    assert checked > 100
+
+
+def test_tent_reading_equals_binned_volume_without_tolerance(dare, torch_cuda):
+    """With bin tolerance 0 every distinct frame orientation is its own bin, so the binned
+    volume's reslice is the per-sample tent reading (FP32 sums there, FP64 here)."""
+    torch = torch_cuda
+    wl = synth.config1()
+    frames = wl.render("cpu").numpy()
+    sel = list(range(0, 100, 5)) + list(range(100, 200, 5))
+    fr = torch.from_numpy(np.ascontiguousarray(frames[sel])).cuda()
+    poses = torch.from_numpy(np.asarray(wl.sweep.probe_poses, np.float32)[sel]).cuda()
+    note("per-sample tent reading vs binned volume at bin tolerance 0, config 1 subset")
+    st = _store(dare, torch, wl.origin, wl.spacing, wl.dims, wl.calib, poses.cpu().numpy(), fr.cpu().numpy(),
+                wl.sweep.pitch)
+    prm = Params(bin_tol_deg=0.0)
+    vol = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, prm)
+    vol.reconstruct(fr, poses, wl.sweep.pitch)
+    torch.cuda.synchronize()
+    assert vol.info().bins <= 64
+    for k in range(4):
+        P = wl.slices.probe_poses[k]
+        got = st.reslice(P, 64, 64, (0.25, 0.25), lib_params(prm), "tent").cpu().numpy()
+        ref = vol.reslice(P, 64, 64, (0.25, 0.25)).cpu().numpy()
+        assert_parity(got, ref, what=f"slice {k}")
+
+
+def test_errors_leave_the_store_empty(dare, torch_cuda):
+    torch = torch_cuda
+    rng, origin, h, dims, calib, poses, frames, pitch, n0, x0, centre = _scene(11)
+    note("per-sample store: budget, bad pose and empty store")
+    F, H, W = frames.shape
+    g = dare.make_geometry(origin, h, dims, calib)
+    st = dare.SampleStore(g, 3, F)                     # far fewer samples than the frames hold
+    with pytest.raises(dare.DareError) as e:
+        st.build(torch.from_numpy(frames).cuda(), torch.from_numpy(poses).cuda(), pitch)
+    assert e.value.status == dare.ERR_BUDGET
+    assert st.count() == (0, 0)
+    P = _slice(rng, calib, n0, x0, centre, 6, 4, (0.3, 0.3))
+    assert np.isnan(st.reslice(P, 6, 4, (0.3, 0.3)).cpu().numpy()).all()
+    bad = poses.copy()
+    bad[2, 0, 0] *= 1.5                                # not a rotation
+    st2 = dare.SampleStore(g, F * H * W, F)
+    with pytest.raises(dare.DareError) as e:
+        st2.build(torch.from_numpy(frames).cuda(), torch.from_numpy(bad).cuda(), pitch)
+    assert e.value.status == dare.ERR_BAD_POSE
+    assert st2.count() == (0, 0)
+    with pytest.raises(dare.DareError):
+        st2.reslice(P, 6, 4, (0.3, 0.3), mode=5)
+    torch.cuda.synchronize()
