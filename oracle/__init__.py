@@ -22,9 +22,11 @@ What it computes, and where the paper defines it:
   literal   -- the same reslice over every individual sample with its own
                acquisition orientation, written separately with explicit loops
                for tiny inputs (the paper's flat per-sample storage).
+  metrics   -- the evaluation's image similarity of a reslice against the
+               acquired frame at its pose (Sec. 3: NCC and SSIM).
 
 Every floating-point step is FP64 unless a storage form fixes another
 precision.  Where the paper is silent the readings are stated in each module.
 """
 
-from . import geometry, bins, compound, quant, reslice, literal  # noqa: F401
+from . import geometry, bins, compound, quant, reslice, literal, metrics  # noqa: F401

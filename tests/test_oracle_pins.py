@@ -536,3 +536,55 @@ def test_storage_forms_error_bounds():
     a16, c16 = quant.storage(S, Cn, "fp16")
     small = has & (Cn <= 256)
     np.testing.assert_array_equal(c16[small], Cn[small])
+
+
+# ---------------------------------------------------------------- evaluation metrics (Sec. 3)
+
+from oracle import metrics  # noqa: E402
+
+
+def test_ncc_pins():
+    rng = np.random.default_rng(31)
+    a = rng.uniform(0, 255, (23, 17))
+    assert metrics.ncc(a, a)[0] == pytest.approx(1.0, abs=1e-12)
+    assert metrics.ncc(a, 3.0 * a + 7.0)[0] == pytest.approx(1.0, abs=1e-12)
+    assert metrics.ncc(a, 100.0 - 2.0 * a)[0] == pytest.approx(-1.0, abs=1e-12)
+    b = rng.uniform(0, 255, a.shape)
+    holes = a.copy()
+    holes[rng.random(a.shape) < 0.3] = np.nan
+    m = np.isfinite(holes)
+    got, n = metrics.ncc(holes, b)
+    assert n == int(m.sum())
+    assert got == pytest.approx(float(np.corrcoef(a[m], b[m])[0, 1]), abs=1e-12)
+
+
+def test_ssim_pins():
+    rng = np.random.default_rng(32)
+    g = metrics.gaussian_window()
+    assert g.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(g, g.T) and np.allclose(g, g[::-1, ::-1])
+    a = rng.uniform(0, 255, (26, 21))
+    b = np.clip(a + rng.normal(0, 25, a.shape), 0, 255)
+    assert metrics.ssim(a, a)[0] == pytest.approx(1.0, abs=1e-12)
+    s_ab, n = metrics.ssim(a, b)
+    assert n == (26 - 10) * (21 - 10)
+    assert s_ab == pytest.approx(metrics.ssim(b, a)[0], abs=1e-12)
+    # the same index from separable Gaussian filtering (radius 5 = truncate 5 / 1.5)
+    f = lambda x: ndi.gaussian_filter(x, 1.5, truncate=5.0 / 1.5, mode="constant")  # noqa: E731
+    ma, mb = f(a), f(b)
+    va, vb, cab = f(a * a) - ma * ma, f(b * b) - mb * mb, f(a * b) - ma * mb
+    c1, c2 = (0.01 * 255) ** 2, (0.03 * 255) ** 2
+    smap = ((2 * ma * mb + c1) * (2 * cab + c2)) / ((ma * ma + mb * mb + c1) * (va + vb + c2))
+    assert s_ab == pytest.approx(float(smap[5:-5, 5:-5].mean()), abs=1e-9)
+    assert s_ab < 0.99
+    # an unassigned pixel removes exactly the windows that contain it
+    holes = a.copy()
+    holes[9, 12] = np.nan
+    got, n2 = metrics.ssim(holes, b)
+    inside = [(j, i) for j in range(5, 21) for i in range(5, 16) if abs(j - 9) <= 5 and abs(i - 12) <= 5]
+    assert n2 == n - len(inside)
+    keep = np.ones_like(smap, bool)
+    for j, i in inside:
+        keep[j, i] = False
+    keep[:5], keep[-5:], keep[:, :5], keep[:, -5:] = False, False, False, False
+    assert got == pytest.approx(float(smap[keep].mean()), abs=1e-9)
