@@ -20,6 +20,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import ctypes as ct
 import hashlib
 import json
@@ -739,6 +740,53 @@ def main():
         del store, lit_out
         torch.cuda.synchronize()
 
+    # ---- evaluation protocol (Sec. 3: NCC and SSIM of reslices against the acquired frames), on
+    # held-out frames: every 20th frame of each sweep is left out of the reconstruction, and each
+    # is resliced at its own pose from the rest, by DARE and by plain mean compounding (both
+    # thresholds at 180 degrees, k = 0: every sample weighs 1), then compared with the frame
+    evaluation = None
+    if not args.no_forms and not args.no_literal:
+        held = [f for f in range(int(F)) if f % 20 == 10]
+        kept = [f for f in range(int(F)) if f % 20 != 10]
+        kept_t = torch.tensor(kept, device=dev)
+        fr_k, po_k = frames.index_select(0, kept_t).contiguous(), poses.index_select(0, kept_t).contiguous()
+        ws_c = torch.empty(int(dare.lib.dare_compare_workspace_bytes()), dtype=torch.uint8, device=dev)
+        img = torch.empty((Hf, Wf), dtype=torch.float32, device=dev)
+        # the same held-out views without speckle: the echo the frame's direction sees (the frames'
+        # speckle is drawn independently per frame, so no reconstruction can predict it)
+        echo = synth.render.render_frames(dataclasses.replace(wl.phantom, speckle_sigma=0.0),
+                                          np.asarray(wl.sweep.probe_poses)[held], wl.calib, Wf, Hf, pitch_f,
+                                          seed=0, device=dev)
+        evaluation = {"held_out_frames": len(held), "reconstructed_from": len(kept), "frame_px": [Wf, Hf]}
+        for name, prm_e in (("dare", dare.default_params()),
+                            ("plain_mean", dare.default_params(k_normal=0.0, k_inplane=0.0, thr_normal_deg=180.0,
+                                                               thr_inplane_deg=180.0))):
+            v_e = dare.Volume(geom, prm_e, dtype="f32", bricks=nb * 40)
+            v_e.reconstruct(fr_k, po_k, pitch_f)
+            res = {"vs_frame": ([], []), "vs_echo": ([], [])}
+            fracs = []
+            t_cmp = 0.0
+            for k, f in enumerate(held):
+                v_e.reslice(wl.sweep.probe_poses[f], Wf, Hf, pitch_f, out=img)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c = dare.compare_to_frame(img, frames[f], ws_c)
+                t_cmp += time.perf_counter() - t0
+                ce = dare.compare_to_frame(img, echo[k], ws_c)
+                for key, cc in (("vs_frame", c), ("vs_echo", ce)):
+                    res[key][0].append(cc[0])
+                    res[key][1].append(cc[1])
+                fracs.append(c[2] / (Wf * Hf))
+            q = lambda xs: [round(float(np.nanpercentile(xs, p_)), 4) for p_ in (25, 50, 75)]  # noqa: E731
+            evaluation[name] = {key: {"ncc_q25_median_q75": q(v[0]), "ssim_q25_median_q75": q(v[1])}
+                                for key, v in res.items()}
+            evaluation[name]["assigned_fraction_mean"] = round(float(np.mean(fracs)), 4)
+            evaluation[name]["compare_ms_per_image"] = round(1e3 * t_cmp / len(held), 3)
+            log(f"evaluation {name}: {evaluation[name]}")
+            del v_e
+        del fr_k, po_k, img, ws_c, echo
+        torch.cuda.synchronize()
+
     # GPU results on the oracle's sample, kept before the serving form frees the volumes
     ncs = min(args.cpu_slices, len(specs))
     sample_out = {}
@@ -887,6 +935,7 @@ def main():
         "forms": forms,
         "radius_sweep": radius,
         "per_sample_store": literal_res,
+        "evaluation": evaluation,
         "serving": serving,
         "streaming": streaming,
         "cpu_baseline": cpu_baseline,

@@ -270,6 +270,23 @@ dare_status dare_samples_count(const dare_samples* s, int64_t* n_samples, int32_
 dare_status dare_samples_reslice(const dare_samples* s, const dare_params* p, const dare_slice_spec* spec,
                                  int32_t mode, float* out_dev, void* stream);
 
+/* Image similarity of a reslice against the acquired frame at the same pose
+ * (Sec. 3, quantitative evaluation: normalised cross-correlation and the
+ * structural similarity index against ground truth).  Readings (the paper
+ * names the measures only): zero-mean NCC over the pixels the reslice
+ * assigns (finite); SSIM of Wang et al. with an 11 x 11 Gaussian window
+ * (sigma 1.5, weights summing to 1), K1 = 0.01, K2 = 0.03, L = 255, averaged
+ * over the pixels whose whole window lies inside the image and is assigned.
+ *   image_dev  h * w float32 reslice (NaN = unassigned); frame_dev h * w uint8
+ *   workspace_dev / workspace_bytes: device scratch, at least
+ *              dare_compare_workspace_bytes(), 8-byte aligned
+ *   out_host   4 doubles: NCC, mean SSIM (NaN when undefined), pixels used
+ *              for NCC, windows used for SSIM.
+ * Synchronises `stream`.  Errors: INVALID_ARG, HIP. */
+uint64_t dare_compare_workspace_bytes(void);
+dare_status dare_compare_to_frame(const float* image_dev, const uint8_t* frame_dev, int32_t w, int32_t h,
+                                  void* workspace_dev, uint64_t workspace_bytes, double* out_host, void* stream);
+
 /* Streaming copy of n_bytes (multiple of 16) from src_dev to dst_dev: the
  * bandwidth probe that calibrates the HBM roofline and the byte counters. */
 dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes, void* stream);

@@ -132,6 +132,8 @@ def _load():
         "dare_samples_build": (ct.c_int, [V, P, I32, I32, I32, ct.POINTER(D), P, I32, P]),
         "dare_samples_count": (ct.c_int, [V, ct.POINTER(I64), ct.POINTER(I32)]),
         "dare_samples_reslice": (ct.c_int, [V, ct.POINTER(Params), ct.POINTER(SliceSpec), I32, P, P]),
+        "dare_compare_workspace_bytes": (U64, []),
+        "dare_compare_to_frame": (ct.c_int, [P, P, I32, I32, P, U64, ct.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -348,6 +350,20 @@ class Volume:
         rx = (ct.c_double * max(1, 3 * K))(*np.asarray(rep_x, np.float64).reshape(-1).tolist())
         return _check(lib.dare_volume_upload_sums(self.handle, rn, rx, K, _ptr(S.contiguous()),
                                                   _ptr(C.contiguous()), _stream(stream)), "dare_volume_upload_sums")
+
+
+def compare_to_frame(image, frame, workspace=None, stream=None):
+    """(NCC, mean SSIM, pixels used, windows used) of a float32 reslice against a uint8 frame of
+    the same shape, both device tensors (Sec. 3's evaluation measures)."""
+    import torch
+    H, W = image.shape
+    if workspace is None:
+        workspace = torch.empty(int(lib.dare_compare_workspace_bytes()), dtype=torch.uint8, device=image.device)
+    out = (ct.c_double * 4)()
+    _check(lib.dare_compare_to_frame(_ptr(image.contiguous()), _ptr(frame.contiguous()), int(W), int(H),
+                                     _ptr(workspace), int(workspace.numel()), out, _stream(stream)),
+           "dare_compare_to_frame", allow_warn=False)
+    return out[0], out[1], int(out[2]), int(out[3])
 
 
 LITERAL_MODES = {"box": 0, "tent": 1}
