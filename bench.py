@@ -410,6 +410,52 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
     return res, {"workload": wls[0], "frames": frames0, "items": served_sample}
 
 
+def run_evaluation(dare, torch, synth, wl, frames, poses, geom, every, bricks, log):
+    """Held-out frames (every ``every``-th, offset every/2) left out of the reconstruction and
+    resliced at their own poses from the rest, by DARE and by plain mean compounding (thresholds
+    at 180 degrees, k = 0: every sample weighs 1); each reslice scored with NCC and SSIM against
+    the acquired frame and against the same view rendered without speckle (the frames' speckle is
+    drawn independently per frame, so no reconstruction can predict it)."""
+    dev = frames.device
+    F, Hf, Wf = frames.shape
+    pitch = wl.sweep.pitch
+    held = [f for f in range(int(F)) if f % every == every // 2]
+    kept = torch.tensor([f for f in range(int(F)) if f % every != every // 2], device=dev)
+    fr_k, po_k = frames.index_select(0, kept).contiguous(), poses.index_select(0, kept).contiguous()
+    ws_c = torch.empty(int(dare.lib.dare_compare_workspace_bytes()), dtype=torch.uint8, device=dev)
+    img = torch.empty((Hf, Wf), dtype=torch.float32, device=dev)
+    echo = synth.render.render_frames(dataclasses.replace(wl.phantom, speckle_sigma=0.0),
+                                      np.asarray(wl.sweep.probe_poses)[held], wl.calib, Wf, Hf, pitch,
+                                      seed=0, device=dev)
+    out = {"held_out_frames": len(held), "reconstructed_from": int(kept.numel()), "frame_px": [Wf, Hf]}
+    for name, prm_e in (("dare", dare.default_params()),
+                        ("plain_mean", dare.default_params(k_normal=0.0, k_inplane=0.0, thr_normal_deg=180.0,
+                                                           thr_inplane_deg=180.0))):
+        v_e = dare.Volume(geom, prm_e, dtype="f32", bricks=bricks)
+        v_e.reconstruct(fr_k, po_k, pitch)
+        res = {"vs_frame": ([], []), "vs_echo": ([], [])}
+        fracs = []
+        t_cmp = 0.0
+        for k, f in enumerate(held):
+            v_e.reslice(wl.sweep.probe_poses[f], Wf, Hf, pitch, out=img)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = dare.compare_to_frame(img, frames[f], ws_c)
+            t_cmp += time.perf_counter() - t0
+            ce = dare.compare_to_frame(img, echo[k], ws_c)
+            for key, cc in (("vs_frame", c), ("vs_echo", ce)):
+                res[key][0].append(cc[0])
+                res[key][1].append(cc[1])
+            fracs.append(c[2] / (Wf * Hf))
+        q = lambda xs: [round(float(np.nanpercentile(xs, p_)), 4) for p_ in (25, 50, 75)]  # noqa: E731
+        out[name] = {key: {"ncc_q25_median_q75": q(v[0]), "ssim_q25_median_q75": q(v[1])} for key, v in res.items()}
+        out[name]["assigned_fraction_mean"] = round(float(np.mean(fracs)), 4)
+        out[name]["compare_ms_per_image"] = round(1e3 * t_cmp / len(held), 3)
+        log(f"evaluation {wl.name.split(':')[0]} {name}: {out[name]}")
+        del v_e
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -740,51 +786,18 @@ def main():
         del store, lit_out
         torch.cuda.synchronize()
 
-    # ---- evaluation protocol (Sec. 3: NCC and SSIM of reslices against the acquired frames), on
-    # held-out frames: every 20th frame of each sweep is left out of the reconstruction, and each
-    # is resliced at its own pose from the rest, by DARE and by plain mean compounding (both
-    # thresholds at 180 degrees, k = 0: every sample weighs 1), then compared with the frame
+    # ---- evaluation protocol (Sec. 3: NCC and SSIM of reslices against the acquired frames) on
+    # held-out frames of config 1 (two sweeps whose beams are tilted +-20 deg: the views differ in
+    # direction) and config 2 (three azimuths with vertical beams: the views share the beam)
     evaluation = None
     if not args.no_forms and not args.no_literal:
-        held = [f for f in range(int(F)) if f % 20 == 10]
-        kept = [f for f in range(int(F)) if f % 20 != 10]
-        kept_t = torch.tensor(kept, device=dev)
-        fr_k, po_k = frames.index_select(0, kept_t).contiguous(), poses.index_select(0, kept_t).contiguous()
-        ws_c = torch.empty(int(dare.lib.dare_compare_workspace_bytes()), dtype=torch.uint8, device=dev)
-        img = torch.empty((Hf, Wf), dtype=torch.float32, device=dev)
-        # the same held-out views without speckle: the echo the frame's direction sees (the frames'
-        # speckle is drawn independently per frame, so no reconstruction can predict it)
-        echo = synth.render.render_frames(dataclasses.replace(wl.phantom, speckle_sigma=0.0),
-                                          np.asarray(wl.sweep.probe_poses)[held], wl.calib, Wf, Hf, pitch_f,
-                                          seed=0, device=dev)
-        evaluation = {"held_out_frames": len(held), "reconstructed_from": len(kept), "frame_px": [Wf, Hf]}
-        for name, prm_e in (("dare", dare.default_params()),
-                            ("plain_mean", dare.default_params(k_normal=0.0, k_inplane=0.0, thr_normal_deg=180.0,
-                                                               thr_inplane_deg=180.0))):
-            v_e = dare.Volume(geom, prm_e, dtype="f32", bricks=nb * 40)
-            v_e.reconstruct(fr_k, po_k, pitch_f)
-            res = {"vs_frame": ([], []), "vs_echo": ([], [])}
-            fracs = []
-            t_cmp = 0.0
-            for k, f in enumerate(held):
-                v_e.reslice(wl.sweep.probe_poses[f], Wf, Hf, pitch_f, out=img)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                c = dare.compare_to_frame(img, frames[f], ws_c)
-                t_cmp += time.perf_counter() - t0
-                ce = dare.compare_to_frame(img, echo[k], ws_c)
-                for key, cc in (("vs_frame", c), ("vs_echo", ce)):
-                    res[key][0].append(cc[0])
-                    res[key][1].append(cc[1])
-                fracs.append(c[2] / (Wf * Hf))
-            q = lambda xs: [round(float(np.nanpercentile(xs, p_)), 4) for p_ in (25, 50, 75)]  # noqa: E731
-            evaluation[name] = {key: {"ncc_q25_median_q75": q(v[0]), "ssim_q25_median_q75": q(v[1])}
-                                for key, v in res.items()}
-            evaluation[name]["assigned_fraction_mean"] = round(float(np.mean(fracs)), 4)
-            evaluation[name]["compare_ms_per_image"] = round(1e3 * t_cmp / len(held), 3)
-            log(f"evaluation {name}: {evaluation[name]}")
-            del v_e
-        del fr_k, po_k, img, ws_c, echo
+        wl1 = synth.config1()
+        fr1 = wl1.render(dev)
+        po1 = torch.from_numpy(np.ascontiguousarray(wl1.sweep.probe_poses, np.float32)).to(dev)
+        g1 = dare.make_geometry(wl1.origin, wl1.spacing, wl1.dims, wl1.calib)
+        evaluation = {"config1": run_evaluation(dare, torch, synth, wl1, fr1, po1, g1, 10, None, log),
+                      "config2": run_evaluation(dare, torch, synth, wl, frames, poses, geom, 20, nb * 40, log)}
+        del fr1, po1
         torch.cuda.synchronize()
 
     # GPU results on the oracle's sample, kept before the serving form frees the volumes
