@@ -205,6 +205,23 @@ dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n_host, co
                                     int32_t bins, const uint32_t* sums_dev, const uint32_t* counts_dev,
                                     void* stream);
 
+/* Volume persistence: save a volume's whole state (geometry, parameters,
+ * dtype, codebook, brick table, exact accumulators, stored pairs and FP8
+ * scales) to host memory, and load it into a new arena, possibly on another
+ * device or process.  A loaded volume reslices bit for bit like the saved one
+ * and keeps compounding incrementally (the accumulators travel with it).
+ * The format is this library's own (a versioned header, then the arrays).
+ *   save_bytes: bytes dare_volume_save writes (0 for an invalid handle).
+ *   save:       synchronises the device; INVALID_ARG if bytes is too small.
+ *   load:       creates the volume in [arena_dev, arena_dev + arena_bytes)
+ *               on the current device (as dare_volume_create) and fills it;
+ *               INVALID_ARG for a damaged or foreign buffer, BUDGET if the
+ *               arena cannot hold the saved bricks.  Synchronous. */
+uint64_t dare_volume_save_bytes(const dare_volume* v);
+dare_status dare_volume_save(const dare_volume* v, void* host_out, uint64_t bytes);
+dare_status dare_volume_load(const void* host_in, uint64_t bytes, void* arena_dev, uint64_t arena_bytes,
+                             dare_volume** out);
+
 /* The direction bins that survive both thresholds for this slice pose and
  * their Eq. 2 weights (Sec. 2.1, Eq. 1 and Eq. 2), evaluated on the host in
  * FP64 from the volume's codebook.  bins_out / weights_out (may be NULL)

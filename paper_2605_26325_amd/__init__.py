@@ -133,6 +133,9 @@ def _load():
         "dare_samples_count": (ct.c_int, [V, ct.POINTER(I64), ct.POINTER(I32)]),
         "dare_samples_reslice": (ct.c_int, [V, ct.POINTER(Params), ct.POINTER(SliceSpec), I32, P, P]),
         "dare_compare_workspace_bytes": (U64, []),
+        "dare_volume_save_bytes": (U64, [V]),
+        "dare_volume_save": (ct.c_int, [V, P, U64]),
+        "dare_volume_load": (ct.c_int, [P, U64, P, U64, ct.POINTER(V)]),
         "dare_compare_to_frame": (ct.c_int, [P, P, I32, I32, P, U64, ct.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
@@ -275,6 +278,35 @@ class Volume:
         if getattr(self, "handle", None):
             lib.dare_volume_destroy(self.handle)
             self.handle = None
+
+    def save(self) -> np.ndarray:
+        """The volume's whole state as a host byte array (dare_volume_save)."""
+        n = int(lib.dare_volume_save_bytes(self.handle))
+        if n == 0:
+            raise DareError(ERR_INVALID_ARG, "dare_volume_save_bytes")
+        buf = np.empty(n, np.uint8)
+        _check(lib.dare_volume_save(self.handle, buf.ctypes.data_as(ct.c_void_p), n), "dare_volume_save")
+        return buf
+
+    @classmethod
+    def load(cls, buf, arena_bytes: int, device="cuda") -> "Volume":
+        """A new volume holding a saved state, in a fresh arena of ``arena_bytes``."""
+        import torch
+        buf = np.ascontiguousarray(buf, np.uint8)
+        self = cls.__new__(cls)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ct.c_void_p()
+        _check(lib.dare_volume_load(buf.ctypes.data_as(ct.c_void_p), buf.nbytes, _ptr(self.arena), int(arena_bytes),
+                                    ct.byref(h)), "dare_volume_load")
+        self.handle = h
+        hdr = Geometry()
+        ct.memmove(ct.byref(hdr), buf.ctypes.data + 16, ct.sizeof(Geometry))
+        self.geometry = hdr
+        prm = Params()
+        ct.memmove(ct.byref(prm), buf.ctypes.data + 16 + ct.sizeof(Geometry), ct.sizeof(Params))
+        self.params = prm
+        self.dtype = int(np.frombuffer(buf[16 + ct.sizeof(Geometry) + ct.sizeof(Params):][:4].tobytes(), np.int32)[0])
+        return self
 
     def __del__(self):
         try:

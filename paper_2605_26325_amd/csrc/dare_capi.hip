@@ -761,6 +761,134 @@ dare_status dare_volume_get_codebook(const dare_volume* v, double* rep_n, double
     return DARE_OK;
 }
 
+// ------------------------------------------------------------------ persistence
+// A saved volume: a fixed header, then the brick table (max_bins x bricks per bin int32), the
+// accumulators, stored pairs and FP8 scales of the `used` slots, back to back.
+namespace {
+
+struct SavedHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    dare_geometry g;
+    dare_params p;
+    int32_t dtype, K, saturated;
+    uint32_t used;
+    double rep_n[kMaxBins][3], rep_x[kMaxBins][3];
+    uint64_t table_bytes, acc_bytes, data_bytes, scales_bytes;
+};
+
+constexpr char kSaveMagic[8] = {'D', 'A', 'R', 'E', 'V', 'O', 'L', '1'};
+
+void saved_sizes(const dare_geometry* g, const dare_params* p, int dtype, uint32_t used, SavedHeader* h) {
+    const Layout L = layout(g, p, dtype, 0);
+    h->table_bytes = (uint64_t)p->max_bins * L.nbricks * sizeof(int32_t);
+    h->acc_bytes = (uint64_t)used * kBrickVox * sizeof(unsigned long long);
+    h->data_bytes = (uint64_t)used * kBrickVox * (uint64_t)pair_bytes(dtype);
+    h->scales_bytes = (uint64_t)used * sizeof(float2);
+}
+
+uint64_t saved_total(const SavedHeader& h) {
+    return sizeof(SavedHeader) + h.table_bytes + h.acc_bytes + h.data_bytes + h.scales_bytes;
+}
+
+}  // namespace
+
+uint64_t dare_volume_save_bytes(const dare_volume* v) {
+    if (!v) return 0;
+    DeviceGuard dg(v->device);
+    if (hipDeviceSynchronize() != hipSuccess) return 0;
+    SavedHeader h{};
+    saved_sizes(&v->g, &v->p, v->dtype, v->used, &h);
+    return saved_total(h);
+}
+
+dare_status dare_volume_save(const dare_volume* v, void* host_out, uint64_t bytes) {
+    if (!v || !host_out) return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    HIP_TRY(hipDeviceSynchronize());
+    VolDev d;
+    HIP_TRY(hipMemcpy(&d, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost));
+    SavedHeader h{};
+    memcpy(h.magic, kSaveMagic, sizeof(h.magic));
+    h.version = 1;
+    h.header_bytes = sizeof(SavedHeader);
+    h.g = v->g;
+    h.p = v->p;
+    h.dtype = v->dtype;
+    h.K = d.st.K;
+    h.saturated = d.st.saturated;
+    h.used = d.st.used;
+    memcpy(h.rep_n, d.rep_n, sizeof(h.rep_n));
+    memcpy(h.rep_x, d.rep_x, sizeof(h.rep_x));
+    saved_sizes(&v->g, &v->p, v->dtype, h.used, &h);
+    if (bytes < saved_total(h)) return DARE_ERR_INVALID_ARG;
+    char* o = (char*)host_out;
+    memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    HIP_TRY(hipMemcpy(o, d.table, h.table_bytes, hipMemcpyDeviceToHost));
+    o += h.table_bytes;
+    if (h.used) {
+        HIP_TRY(hipMemcpy(o, d.acc, h.acc_bytes, hipMemcpyDeviceToHost));
+        o += h.acc_bytes;
+        HIP_TRY(hipMemcpy(o, d.data, h.data_bytes, hipMemcpyDeviceToHost));
+        o += h.data_bytes;
+        HIP_TRY(hipMemcpy(o, d.scales, h.scales_bytes, hipMemcpyDeviceToHost));
+    }
+    return DARE_OK;
+}
+
+dare_status dare_volume_load(const void* host_in, uint64_t bytes, void* arena_dev, uint64_t arena_bytes,
+                             dare_volume** out) {
+    if (!host_in || !out || bytes < sizeof(SavedHeader)) return DARE_ERR_INVALID_ARG;
+    *out = nullptr;
+    SavedHeader h;
+    memcpy(&h, host_in, sizeof(h));
+    if (memcmp(h.magic, kSaveMagic, sizeof(h.magic)) != 0 || h.version != 1 || h.header_bytes != sizeof(SavedHeader))
+        return DARE_ERR_INVALID_ARG;
+    if (check_geometry(&h.g) != DARE_OK || check_params(&h.p) != DARE_OK || !valid_dtype(h.dtype) || h.K < 0 ||
+        h.K > h.p.max_bins)
+        return DARE_ERR_INVALID_ARG;
+    SavedHeader sz = h;
+    saved_sizes(&h.g, &h.p, h.dtype, h.used, &sz);
+    if (sz.table_bytes != h.table_bytes || sz.acc_bytes != h.acc_bytes || sz.data_bytes != h.data_bytes ||
+        sz.scales_bytes != h.scales_bytes || bytes < saved_total(h))
+        return DARE_ERR_INVALID_ARG;
+    dare_volume* v = nullptr;
+    dare_status st = dare_volume_create(&h.g, &h.p, (dare_dtype)h.dtype, arena_dev, arena_bytes, &v);
+    if (st != DARE_OK) return st;
+    if (h.used > v->host.cap) {
+        dare_volume_destroy(v);
+        return DARE_ERR_BUDGET;
+    }
+    const char* in = (const char*)host_in + sizeof(SavedHeader);
+    VolDev& d = v->host;
+    hipError_t e = hipMemcpy(d.table, in, h.table_bytes, hipMemcpyHostToDevice);
+    in += h.table_bytes;
+    if (e == hipSuccess && h.used) {
+        e = hipMemcpy(d.acc, in, h.acc_bytes, hipMemcpyHostToDevice);
+        in += h.acc_bytes;
+        if (e == hipSuccess) e = hipMemcpy(d.data, in, h.data_bytes, hipMemcpyHostToDevice);
+        in += h.data_bytes;
+        if (e == hipSuccess) e = hipMemcpy(d.scales, in, h.scales_bytes, hipMemcpyHostToDevice);
+    }
+    d.st.K = h.K;
+    d.st.saturated = h.saturated;
+    d.st.used = h.used;
+    memcpy(d.rep_n, h.rep_n, sizeof(d.rep_n));
+    memcpy(d.rep_x, h.rep_x, sizeof(d.rep_x));
+    if (e == hipSuccess) e = hipMemcpy(v->dev, &d, sizeof(VolDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        dare_volume_destroy(v);
+        return DARE_ERR_HIP;
+    }
+    v->K = h.K;
+    v->saturated = h.saturated;
+    v->used = h.used;
+    *out = v;
+    return DARE_OK;
+}
+
 dare_status dare_volume_download_sums(const dare_volume* v, uint32_t* S, uint32_t* C, int32_t bins, void* stream) {
     if (!v || !S || !C || bins != v->K) return DARE_ERR_INVALID_ARG;
     if (bins == 0) return DARE_OK;
