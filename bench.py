@@ -80,6 +80,50 @@ def footprint_voxels(torch, P, calib, origin, h, dims, W, H, pitch):
     return int(torch.unique(torch.cat(keys)).numel())
 
 
+def voxel_sample_counts(torch, frames_shape, poses, calib, origin, h, dims, pitch):
+    """Samples per voxel of the per-sample store (every in-grid frame pixel at its nearest voxel),
+    recomputed in torch for the untimed algorithmic-byte count."""
+    dev = poses.device
+    F, Hf, Wf = frames_shape
+    n = torch.tensor(dims, device=dev)
+    counts = torch.zeros(int(dims[0]) * int(dims[1]) * int(dims[2]), dtype=torch.int64, device=dev)
+    C = torch.tensor(calib, dtype=torch.float64, device=dev)
+    i = torch.arange(Wf, device=dev, dtype=torch.float64) * pitch[0]
+    j = torch.arange(Hf, device=dev, dtype=torch.float64) * pitch[1]
+    o = torch.tensor(origin, dtype=torch.float64, device=dev)
+    for f0 in range(0, F, 64):
+        T = poses[f0:f0 + 64].to(torch.float64) @ C
+        p = T[:, None, None, :3, 3] + i[None, None, :, None] * T[:, None, None, :3, 0] \
+            + j[None, :, None, None] * T[:, None, None, :3, 1]
+        v = torch.floor((p - o) / h + 0.5).to(torch.int64).reshape(-1, 3)
+        ok = ((v >= 0) & (v < n)).all(-1)
+        v = v[ok]
+        counts += torch.bincount((v[:, 2] * n[1] + v[:, 1]) * n[0] + v[:, 0], minlength=counts.numel())
+    return counts
+
+
+def box_reading_bytes(torch, counts, P, calib, origin, h, dims, W, H, pitch, R=1):
+    """Algorithmic bytes of one box-reading reslice: the samples (4 B) and CSR offsets (8 B) of the
+    distinct voxels within R of some pixel's nearest voxel, plus 4 B of output per pixel."""
+    dev = counts.device
+    T = torch.tensor(P, dtype=torch.float64, device=dev) @ torch.tensor(calib, dtype=torch.float64, device=dev)
+    i = torch.arange(W, device=dev, dtype=torch.float64) * pitch[0]
+    j = torch.arange(H, device=dev, dtype=torch.float64) * pitch[1]
+    p = T[:3, 3] + i[None, :, None] * T[:3, 0] + j[:, None, None] * T[:3, 1]
+    ctr = torch.floor((p - torch.tensor(origin, dtype=torch.float64, device=dev)) / h + 0.5).to(torch.int64)
+    ctr = torch.unique(ctr.reshape(-1, 3), dim=0)
+    n = torch.tensor(dims, device=dev)
+    keys = []
+    for dz in range(-R, R + 1):
+        for dy in range(-R, R + 1):
+            for dx in range(-R, R + 1):
+                v = ctr + torch.tensor([dx, dy, dz], device=dev)
+                v = v[((v >= 0) & (v < n)).all(-1)]
+                keys.append((v[:, 2] * n[1] + v[:, 1]) * n[0] + v[:, 0])
+    u = torch.unique(torch.cat(keys))
+    return int(4 * counts[u].sum().item() + 8 * u.numel() + 4 * W * H)
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
@@ -772,6 +816,19 @@ def main():
             torch.cuda.synchronize()
             ms = e_a.elapsed_time(e_b) / nl
             literal_res[mode_name] = {"ms_per_slice": round(ms, 4), "Mpx_s": round(W * H / (ms * 1e-3) / 1e6, 1)}
+            if mode_name == "box":
+                counts = voxel_sample_counts(torch, tuple(frames.shape), poses, wl.calib, wl.origin, wl.spacing,
+                                             wl.dims, pitch_f)
+                nb_l = min(10, nl)
+                byt = float(np.mean([box_reading_bytes(torch, counts, sl.probe_poses[k], wl.calib, wl.origin,
+                                                       wl.spacing, wl.dims, W, H, pitch) for k in range(nb_l)]))
+                ach = byt / (ms * 1e-3) / 1e9
+                literal_res["box"]["roofline"] = {
+                    "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "algo_bytes_per_launch": round(byt),
+                    "bytes_basis": f"first {nb_l} slices: samples (4 B) and CSR offsets (8 B) of the distinct "
+                                   "voxels in reach, 4 B output per pixel"}
+                del counts
             if mode_name == "tent":
                 a, b = lit_out.double(), outs[:nl].double()
                 both = torch.isfinite(a) & torch.isfinite(b)
