@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
 
 This package simulates an acquisition: a phantom of spheres and planes with a
-beam-angle dependent echo, tracked linear-array sweeps, their 2D uint8 frames,
+beam-angle dependent echo, tracked sweeps of a linear array (or of a curvilinear
+probe, ``fan_config``), their 2D uint8 frames,
 and reslice poses.  It holds none of the reconstruction or reslicing
 arithmetic; both the FP64 oracle and the GPU path receive what it produces as
 plain arrays.
@@ -21,5 +22,5 @@ from .sweeps import (  # noqa: F401
 )
 from .render import render_frames  # noqa: F401
 from .configs import (  # noqa: F401
-    Workload, config1, config2, config3_slices, config5, serving_volume, tiny_workload,
+    Workload, config1, config2, config3_slices, config5, serving_volume, tiny_workload, fan_beams, fan_config, fan_config2,
 )

@@ -36,11 +36,21 @@ class Workload:
     frame_seed: int
     params: dict = field(default_factory=dict)
     frames: object = None         # torch uint8 (F,H,W), filled by ``render``
+    fan: dict = None              # fan probes: apex (a0, a1), r0, dr, sectors, width, height
+    beams: np.ndarray = None      # fan probes: (width, 2) unit beam direction per column
 
     def render(self, device="cpu"):
-        self.frames = render_frames(self.phantom, self.sweep.probe_poses, self.calib,
-                                    self.sweep.width, self.sweep.height, self.sweep.pitch,
-                                    seed=self.frame_seed, device=device)
+        if self.fan is None:
+            self.frames = render_frames(self.phantom, self.sweep.probe_poses, self.calib,
+                                        self.sweep.width, self.sweep.height, self.sweep.pitch,
+                                        seed=self.frame_seed, device=device)
+        else:
+            W, H = self.fan["width"], self.fan["height"]
+            r = self.fan["r0"] + self.fan["dr"] * np.arange(H, dtype=np.float64)
+            uv = (self.fan["apex"][0] + r[:, None] * self.beams[None, :, 0],
+                  self.fan["apex"][1] + r[:, None] * self.beams[None, :, 1])
+            self.frames = render_frames(self.phantom, self.sweep.probe_poses, self.calib, W, H, self.sweep.pitch,
+                                        seed=self.frame_seed, device=device, fan_uv=uv, fan_beams=self.beams)
         return self.frames
 
 
@@ -56,6 +66,43 @@ def config1(n_slices: int = 16, n_near: int = 12) -> Workload:
     sl = slice_poses(101, sw, n_slices, n_near, 128, 128, (0.25, 0.25), N, h, C)
     return Workload("config1: 64^3 @0.5mm, 2x100 frames 128^2, 16 slices 128^2", (N, N, N), h,
                     WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=1, params=dict(DEFAULT_PARAMS))
+
+
+def fan_beams(width: int, step_deg: float) -> np.ndarray:
+    """(width, 2) unit beam directions (lateral, axial) of a fan whose columns are step_deg apart,
+    symmetric about the axial direction."""
+    th = np.deg2rad((np.arange(width, dtype=np.float64) - (width - 1) / 2.0) * step_deg)
+    return np.stack([np.sin(th), np.cos(th)], axis=1)
+
+
+def fan_config(sectors: int = 8, n_slices: int = 16, n_near: int = 12) -> Workload:
+    """Config 1's grid, phantom and two tilted sweeps, imaged by a curvilinear probe: 96 beams
+    0.5 deg apart (a 47.5 deg fan) from an apex 8 mm above the first row, 128 rows 0.2 mm apart,
+    the columns binned in ``sectors`` sectors."""
+    N, h, w, pitch = 64, 0.5, 128, (0.25, 0.25)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=1, L=N * h, n_sph=12, n_pl=4, shell_mm=h)
+    sw = linear_tilted_sweeps(N, h, 100, w, w, pitch, (20.0, -20.0), C)
+    sl = slice_poses(101, sw, n_slices, n_near, 128, 128, (0.25, 0.25), N, h, C)
+    fan = dict(apex=((w - 1) * pitch[0] / 2.0, -6.0), r0=8.0, dr=0.2, sectors=int(sectors), width=96, height=128)
+    return Workload(f"fan: 64^3 @0.5mm, 2x100 curvilinear frames 96x128, {sectors} sectors", (N, N, N), h,
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=11, params=dict(DEFAULT_PARAMS), fan=fan,
+                    beams=fan_beams(96, 0.5))
+
+
+def fan_config2(sectors: int = 8, n_slices: int = 100, n_near: int = 80) -> Workload:
+    """Config 2's grid, phantom and three azimuth sweeps of 600 frames, imaged by a curvilinear
+    probe: 192 beams 0.25 deg apart (a 47.75 deg fan) from an apex 4 mm above the first row,
+    256 rows 0.1 mm apart, the columns binned in ``sectors`` sectors; 512^2 slices."""
+    N, h, w, pitch = 256, 0.125, 256, (0.125, 0.125)
+    C = make_calibration(w, pitch[0])
+    ph = make_phantom(seed=2, L=N * h, n_sph=30, n_pl=10, shell_mm=h)
+    sw = azimuth_sweeps(N, h, 600, w, w, pitch, (0.0, 120.0, 240.0), 1.0, 2.0, seed=202, calib=C)
+    sl = slice_poses(203, sw, n_slices, n_near, 512, 512, (0.0625, 0.0625), N, h, C)
+    fan = dict(apex=((w - 1) * pitch[0] / 2.0, -3.0), r0=4.0, dr=0.1, sectors=int(sectors), width=192, height=256)
+    return Workload(f"fan config2: 256^3 @0.125mm, 3x600 curvilinear frames 192x256, {sectors} sectors", (N, N, N),
+                    h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=12, params=dict(DEFAULT_PARAMS), fan=fan,
+                    beams=fan_beams(192, 0.25))
 
 
 def config2(n_slices: int = 1000, n_near: int = 800) -> Workload:

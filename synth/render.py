@@ -23,8 +23,12 @@ def _frame_seed(seed: int, f: int) -> int:
 @torch.no_grad()
 def render_frames(ph: Phantom, probe_poses: np.ndarray, calib: np.ndarray, width: int,
                   height: int, pitch, seed: int, device="cpu", chunk: int = 32,
-                  world_offset=WORLD_OFFSET_MM) -> torch.Tensor:
-    """Render ``len(probe_poses)`` frames; returns uint8 (F, height, width) on ``device``."""
+                  world_offset=WORLD_OFFSET_MM, fan_uv=None, fan_beams=None) -> torch.Tensor:
+    """Render ``len(probe_poses)`` frames; returns uint8 (F, height, width) on ``device``.
+
+    A fan probe passes ``fan_uv`` = (u, v), the image-mm position of every pixel (each
+    (height, width)), and ``fan_beams`` (width, 2), every column's unit beam direction in image
+    mm (lateral, axial); the echo then takes each column's own beam."""
     dev = torch.device(device)
     P = torch.as_tensor(np.asarray(probe_poses, dtype=np.float32), device=dev).to(torch.float64)
     C = torch.as_tensor(np.asarray(calib, dtype=np.float64), device=dev)
@@ -41,10 +45,20 @@ def render_frames(ph: Phantom, probe_poses: np.ndarray, calib: np.ndarray, width
         f1 = min(F, f0 + chunk)
         T = P[f0:f1] @ C                                     # (B,4,4)
         e0, e1, t = T[:, :3, 0], T[:, :3, 1], T[:, :3, 3]
-        loc = (t - W0)[:, None, None, :] \
-            + jj[None, :, None, None] * e1[:, None, None, :] \
-            + ii[None, None, :, None] * e0[:, None, None, :]   # (B,H,W,3) local mm
-        beam = (e1 / e1.norm(dim=1, keepdim=True))[:, None, None, :]
+        if fan_uv is None:
+            loc = (t - W0)[:, None, None, :] \
+                + jj[None, :, None, None] * e1[:, None, None, :] \
+                + ii[None, None, :, None] * e0[:, None, None, :]   # (B,H,W,3) local mm
+            beam = (e1 / e1.norm(dim=1, keepdim=True))[:, None, None, :]
+        else:
+            uu = torch.as_tensor(np.asarray(fan_uv[0], np.float64), device=dev)
+            vv = torch.as_tensor(np.asarray(fan_uv[1], np.float64), device=dev)
+            bb = torch.as_tensor(np.asarray(fan_beams, np.float64), device=dev)
+            loc = (t - W0)[:, None, None, :] + vv[None, :, :, None] * e1[:, None, None, :] \
+                + uu[None, :, :, None] * e0[:, None, None, :]
+            x0 = e0 / e0.norm(dim=1, keepdim=True)
+            y0 = e1 / e1.norm(dim=1, keepdim=True)
+            beam = (bb[None, :, 0, None] * x0[:, None, :] + bb[None, :, 1, None] * y0[:, None, :])[:, None, :, :]
         E = torch.zeros(loc.shape[:3], dtype=torch.float64, device=dev)
         for s in range(sph_c.shape[0]):
             d = loc - sph_c[s]
