@@ -12,8 +12,10 @@ slice (FP32 storage, FP64 positions, FP32 blending), inputs resident in HBM.
 The same run also measures: the reconstruction (compounding) of the frames,
 BF16/FP16/FP8 storage and the batched entry point on the same slices,
 unloaded submit-to-host latency, the reslice kernel's average launch time
-with HIP events against its algorithmic bytes (the HBM roofline), and the FP64
-CPU oracle on a bounded sample of the same workload.
+with HIP events against its algorithmic bytes (the HBM roofline), the
+per-sample store, the evaluation protocol, compounding from a curvilinear probe,
+compounding with bricks spilled to host memory, serving and streaming, and the
+FP64 CPU oracle on a bounded sample of the same workload.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -454,6 +456,99 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, log):
     return res, {"workload": wls[0], "frames": frames0, "items": served_sample}
 
 
+def run_fan(dare, torch, synth, dev, bricks, log):
+    """Curvilinear-probe compounding at config-2 scale: the three azimuth sweeps of 600 frames
+    imaged by a 192-beam fan (256 rows), binned per column sector, timed as the linear
+    reconstruction is (median of three builds after a warm-up build); then 100 slices of 512^2
+    resliced from the fan-built volume, one launch each."""
+    wl = synth.fan_config2()
+    fr = wl.render(dev)
+    po = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).to(dev)
+    beams = torch.from_numpy(np.ascontiguousarray(wl.beams, np.float64)).to(dev)
+    geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+    prm = dare.default_params()
+    fz = wl.fan
+    times, vol = [], None
+    for k in range(4):
+        vol = dare.Volume(geom, prm, dtype="f32", bricks=bricks)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        vol.reconstruct_fan(fr, po, fz["apex"], fz["r0"], fz["dr"], fz["sectors"], beams)
+        torch.cuda.synchronize()
+        if k:
+            times.append(time.perf_counter() - t)
+    F, H, W = fr.shape
+    info = vol.info()
+    sl = wl.slices
+    specs = [dare.make_spec(P, sl.width, sl.height, sl.pitch) for P in sl.probe_poses]
+    out = torch.empty((len(specs), sl.height, sl.width), dtype=torch.float32, device=dev)
+    sh = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for k, sp in enumerate(specs):
+        dare.lib.dare_reslice(vol.handle, ct.byref(sp), ct.c_void_p(out[k].data_ptr()), sh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k, sp in enumerate(specs):
+        dare.lib.dare_reslice(vol.handle, ct.byref(sp), ct.c_void_p(out[k].data_ptr()), sh)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / len(specs)
+    med = float(np.median(times))
+    res = {"workload": wl.name, "frames": int(F), "frame_px": [W, H], "sectors": int(fz["sectors"]),
+           "bins": int(info.bins), "bricks_used": int(info.bricks_used),
+           "reconstruct_ms": round(1e3 * med, 3), "frames_per_s": round(F / med, 1),
+           "input_Mpx_s": round(F * W * H / med / 1e6, 1),
+           "reslice_ms_per_slice": round(ms, 4), "reslice_Mpx_s": round(sl.width * sl.height / (ms * 1e-3) / 1e6, 1),
+           "unassigned_fraction": round(float(torch.isnan(out).float().mean()), 4)}
+    log(f"curvilinear: {res}")
+    del vol, fr, out
+    torch.cuda.synchronize()
+    return res
+
+
+def run_out_of_core(dare, torch, geom, prm, frames, poses, pitch, total_bricks, in_core_ms, log):
+    """Out-of-core bricks on config 2: the 1800 frames compounded 100 per call with spilling on,
+    in an arena of a third of the bricks the volume needs; then every brick moved to host memory
+    and one z quarter of the grid brought back (PCIe rates from the bytes moved)."""
+    cap = max(1, total_bricks // 3)
+    vol = dare.Volume(geom, prm, dtype="f32", bricks=cap)
+    vol.set_spill(True)
+    F = frames.shape[0]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for a in range(0, F, 100):
+        vol.reconstruct(frames[a:a + 100], poses[a:a + 100], pitch)
+    torch.cuda.synchronize()
+    t_spill = time.perf_counter() - t
+    held, held_bytes = vol.held()
+    resident = vol.info().bricks_used
+    acc_bytes = 512 * 8
+    t = time.perf_counter()
+    vol.evict_outside((1, 1, 1), (0, 0, 0))
+    t_evict = time.perf_counter() - t
+    nz = int(geom.dims[2])
+    lo, hi = (0, 0, 0), (int(geom.dims[0]) - 1, int(geom.dims[1]) - 1, nz // 4 - 1)
+    n_before = vol.held()[0]
+    t = time.perf_counter()
+    try:
+        vol.restore_box(lo, hi)
+        restored = n_before - vol.held()[0]
+    except dare.DareError:
+        restored = 0
+    t_restore = time.perf_counter() - t
+    res = {"arena_bricks": int(vol.info().bricks_capacity), "volume_bricks": int(total_bricks),
+           "spill_reconstruct_ms": round(1e3 * t_spill, 2), "in_core_reconstruct_ms": round(in_core_ms, 2),
+           "calls": (F + 99) // 100, "held_after_reconstruct": int(held), "held_MB": round(held_bytes / 1e6, 1),
+           "resident_after_reconstruct": int(resident),
+           "evict_bricks": int(resident), "evict_ms": round(1e3 * t_evict, 2),
+           "evict_GBps": round(resident * acc_bytes / max(t_evict, 1e-9) / 1e9, 2),
+           "restore_bricks": int(restored), "restore_ms": round(1e3 * t_restore, 2),
+           "restore_GBps": round(restored * acc_bytes / max(t_restore, 1e-9) / 1e9, 2)}
+    log(f"out-of-core: {res}")
+    del vol
+    torch.cuda.synchronize()
+    return res
+
+
 def run_evaluation(dare, torch, synth, wl, frames, poses, geom, every, bricks, log):
     """Held-out frames (every ``every``-th, offset every/2) left out of the reconstruction and
     resliced at their own poses from the rest, by DARE and by plain mean compounding (thresholds
@@ -516,6 +611,7 @@ def main():
     ap.add_argument("--saturation-seconds", type=float, default=4.0)
     ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--no-literal", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--streaming-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -857,6 +953,13 @@ def main():
         del fr1, po1
         torch.cuda.synchronize()
 
+    # ---- curvilinear probes (binning per column sector) and out-of-core bricks
+    curvilinear, out_of_core = None, None
+    if not args.no_forms and not args.no_extras:
+        curvilinear = run_fan(dare, torch, synth, dev, nb * 40, log)
+        out_of_core = run_out_of_core(dare, torch, geom, prm, frames, poses, pitch_f, int(info.bricks_used),
+                                      1e3 * float(np.median(recon_times)), log)
+
     # GPU results on the oracle's sample, kept before the serving form frees the volumes
     ncs = min(args.cpu_slices, len(specs))
     sample_out = {}
@@ -1006,6 +1109,8 @@ def main():
         "radius_sweep": radius,
         "per_sample_store": literal_res,
         "evaluation": evaluation,
+        "curvilinear": curvilinear,
+        "out_of_core": out_of_core,
         "serving": serving,
         "streaming": streaming,
         "cpu_baseline": cpu_baseline,

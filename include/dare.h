@@ -142,6 +142,38 @@ dare_status dare_reconstruct_frames(dare_volume* v, const uint8_t* frames_dev, i
                                     int32_t h, const double pitch_mm[2], const float* probe_poses_dev,
                                     void* stream);
 
+/* Fan probes: curvilinear arrays, and phased arrays (r0_mm = 0).  The paper
+ * images with a linear array (Sec. 2.2), whose samples all share the frame's
+ * in-plane direction, the x-axis Eq. 1 compares.  A fan's beams leave one
+ * apex at different angles, so that direction changes across the columns:
+ * column i's beam has unit direction b_i = (b_i0, b_i1) in image millimetres
+ * (lateral, axial), and pixel (i, j) lies on it at r = r0 + j * dr from the
+ * apex a, at image millimetres (a0 + r b_i0, a1 + r b_i1), placed in the
+ * world as a linear-array pixel at those millimetres.  Its in-plane direction
+ * is the one across its beam, b_i1 xhat - b_i0 yhat (xhat, yhat: the image
+ * axes in the world).  Binning per column fan: the columns are split into
+ * `sectors` equal sectors (column i in sector i * sectors / w), each sector's
+ * samples taking the in-plane direction of its middle column, and every
+ * (frame, sector) enters the direction binning as a frame of its own, frames
+ * in order, sectors in order.  Reslicing is unchanged. */
+typedef struct {
+    double apex_mm[2];     /* the fan's apex, image mm (lateral, axial), finite */
+    double r0_mm;          /* distance of the first row from the apex, >= 0     */
+    double dr_mm;          /* radial step per row, > 0                          */
+    int32_t sectors;       /* 1 .. min(64, w)                                    */
+} dare_fan;
+
+/* Volume reconstruction from fan frames: dare_reconstruct_frames with the
+ * pixel placement and per-sector binning above.
+ *   beams_dev  w * 2 doubles on the device: every column's unit beam
+ *              direction (not checked; the caller's table is used as given).
+ * The volume's normal_axis must be 2 (the image-plane normal): INVALID_ARG
+ * otherwise.  Batches hold 4096 / sectors frames.  Errors and return values as
+ * dare_reconstruct_frames. */
+dare_status dare_reconstruct_fan(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
+                                 const dare_fan* fan, const double* beams_dev, const float* probe_poses_dev,
+                                 void* stream);
+
 /* Reslice one plane (Sec. 2.1 "Reslicing", Eq. 1, Eq. 2): for each output
  * pixel, the FP64 sample position, its neighbourhood |c - v|_inf < R with
  * tent weights prod(1 - |c_a - v_a| / R), per-voxel direction blending with
@@ -212,7 +244,9 @@ dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n_host, co
  * and keeps compounding incrementally (the accumulators travel with it).
  * The format is this library's own (a versioned header, then the arrays).
  *   save_bytes: bytes dare_volume_save writes (0 for an invalid handle).
- *   save:       synchronises the device; INVALID_ARG if bytes is too small.
+ *   save:       synchronises the device; INVALID_ARG if bytes is too small
+ *               or the volume holds bricks in host memory (restore them
+ *               first: dare_volume_restore_box).
  *   load:       creates the volume in [arena_dev, arena_dev + arena_bytes)
  *               on the current device (as dare_volume_create) and fills it;
  *               INVALID_ARG for a damaged or foreign buffer, BUDGET if the
@@ -221,6 +255,36 @@ uint64_t dare_volume_save_bytes(const dare_volume* v);
 dare_status dare_volume_save(const dare_volume* v, void* host_out, uint64_t bytes);
 dare_status dare_volume_load(const void* host_in, uint64_t bytes, void* arena_dev, uint64_t arena_bytes,
                              dare_volume** out);
+
+/* Out-of-core bricks (Sec. 4 names data sets beyond GPU memory and the
+ * incremental integration of frames during a scan as the next steps).  A
+ * (bin, 8^3 brick) can be moved to host memory ("held"): its exact
+ * accumulators leave, its pool slot is freed, and reslices see the volume
+ * without it.  Compounding carries on as usual: a frame that reaches a held
+ * brick starts it afresh in HBM, and bringing the held part back adds the two
+ * (integer sums) and refinalises.  Hence, once every held brick is restored,
+ * the volume equals bit for bit the one a large enough arena would have
+ * built, whatever was moved out and back, and when.  The host memory is the
+ * library's and goes with dare_volume_destroy (or dare_volume_upload_sums).
+ *   evict_outside: hold every resident brick that does not meet the voxel box
+ *                  lo..hi (inclusive, voxel indices; lo > hi on an axis holds
+ *                  every brick).  The pool is compacted.
+ *   restore_box:   bring back every held brick that meets the box.  BUDGET,
+ *                  with nothing changed, if the pool lacks free slots for the
+ *                  ones not resident meanwhile.
+ *   set_spill:     enabled != 0: a frame batch whose new bricks do not fit
+ *                  first holds the least recently touched bricks (none that
+ *                  the batch touches): enough for the batch and a sixteenth
+ *                  of the pool more.  BUDGET remains for a batch that alone
+ *                  touches more bricks than the pool has slots.  Off at
+ *                  creation.
+ *   held:          number of held bricks and the host bytes they take.
+ * evict_outside and restore_box synchronise `stream`; none may overlap
+ * another call on the same volume.  Errors: INVALID_ARG, BUDGET, HIP. */
+dare_status dare_volume_evict_outside(dare_volume* v, const int32_t lo[3], const int32_t hi[3], void* stream);
+dare_status dare_volume_restore_box(dare_volume* v, const int32_t lo[3], const int32_t hi[3], void* stream);
+dare_status dare_volume_set_spill(dare_volume* v, int32_t enabled);
+dare_status dare_volume_held(const dare_volume* v, int64_t* bricks, uint64_t* bytes);
 
 /* The direction bins that survive both thresholds for this slice pose and
  * their Eq. 2 weights (Sec. 2.1, Eq. 1 and Eq. 2), evaluated on the host in

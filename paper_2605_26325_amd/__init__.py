@@ -48,6 +48,11 @@ class VolumeInfo(ct.Structure):
                 ("bricks_capacity", ct.c_int64), ("bytes_per_brick", ct.c_int64), ("brick_grid", ct.c_int64 * 3)]
 
 
+class Fan(ct.Structure):
+    _fields_ = [("apex_mm", ct.c_double * 2), ("r0_mm", ct.c_double), ("dr_mm", ct.c_double),
+                ("sectors", ct.c_int32)]
+
+
 class ServerConfig(ct.Structure):
     _fields_ = [("max_tick_pixels", ct.c_int64), ("max_tick_requests", ct.c_int32), ("n_streams", ct.c_int32),
                 ("max_queue", ct.c_int32), ("use_graphs", ct.c_int32)]
@@ -101,6 +106,7 @@ def _load():
                                           ct.POINTER(V)]),
         "dare_volume_destroy": (ct.c_int, [V]),
         "dare_reconstruct_frames": (ct.c_int, [V, P, I32, I32, I32, ct.POINTER(D), P, P]),
+        "dare_reconstruct_fan": (ct.c_int, [V, P, I32, I32, I32, ct.POINTER(Fan), P, P, P]),
         "dare_reslice": (ct.c_int, [V, ct.POINTER(SliceSpec), P, P]),
         "dare_reslice_batch_workspace_bytes": (U64, [ct.POINTER(V), ct.POINTER(SliceSpec), I32]),
         "dare_reslice_batch": (ct.c_int, [ct.POINTER(V), ct.POINTER(SliceSpec), ct.POINTER(P), I32, P, U64, P]),
@@ -136,6 +142,10 @@ def _load():
         "dare_volume_save_bytes": (U64, [V]),
         "dare_volume_save": (ct.c_int, [V, P, U64]),
         "dare_volume_load": (ct.c_int, [P, U64, P, U64, ct.POINTER(V)]),
+        "dare_volume_evict_outside": (ct.c_int, [V, ct.POINTER(I32), ct.POINTER(I32), P]),
+        "dare_volume_restore_box": (ct.c_int, [V, ct.POINTER(I32), ct.POINTER(I32), P]),
+        "dare_volume_set_spill": (ct.c_int, [V, I32]),
+        "dare_volume_held": (ct.c_int, [V, ct.POINTER(I64), ct.POINTER(U64)]),
         "dare_compare_to_frame": (ct.c_int, [P, P, I32, I32, P, U64, ct.POINTER(D), P]),
     }
     for name, (res, args) in sig.items():
@@ -308,6 +318,27 @@ class Volume:
         self.dtype = int(np.frombuffer(buf[16 + ct.sizeof(Geometry) + ct.sizeof(Params):][:4].tobytes(), np.int32)[0])
         return self
 
+    def evict_outside(self, lo, hi, stream=None):
+        """Move every resident brick that does not meet the voxel box lo..hi (inclusive) to host
+        memory (dare_volume_evict_outside)."""
+        a, b = (ct.c_int32 * 3)(*[int(x) for x in lo]), (ct.c_int32 * 3)(*[int(x) for x in hi])
+        _check(lib.dare_volume_evict_outside(self.handle, a, b, _stream(stream)), "dare_volume_evict_outside")
+
+    def restore_box(self, lo, hi, stream=None):
+        """Bring back every held brick that meets the voxel box lo..hi (dare_volume_restore_box)."""
+        a, b = (ct.c_int32 * 3)(*[int(x) for x in lo]), (ct.c_int32 * 3)(*[int(x) for x in hi])
+        _check(lib.dare_volume_restore_box(self.handle, a, b, _stream(stream)), "dare_volume_restore_box")
+
+    def set_spill(self, enabled: bool):
+        """Hold least recently touched bricks in host memory instead of failing a batch for room."""
+        _check(lib.dare_volume_set_spill(self.handle, 1 if enabled else 0), "dare_volume_set_spill")
+
+    def held(self):
+        """(bricks held in host memory, their host bytes)."""
+        n, b = ct.c_int64(), ct.c_uint64()
+        _check(lib.dare_volume_held(self.handle, ct.byref(n), ct.byref(b)), "dare_volume_held")
+        return n.value, b.value
+
     def __del__(self):
         try:
             self.close()
@@ -321,6 +352,15 @@ class Volume:
     def reconstruct(self, frames, probe_poses, pitch, stream=None) -> int:
         F, H, W = frames.shape
         return dare_reconstruct_frames(self, frames, W, H, pitch, probe_poses, stream)
+
+    def reconstruct_fan(self, frames, probe_poses, apex, r0, dr, sectors, beams, stream=None) -> int:
+        """Fan frames (F, H, W) uint8; beams: (W, 2) float64 device tensor of unit beam
+        directions (dare_reconstruct_fan)."""
+        F, H, W = frames.shape
+        fan = Fan((ct.c_double * 2)(float(apex[0]), float(apex[1])), float(r0), float(dr), int(sectors))
+        return _check(lib.dare_reconstruct_fan(self.handle, _ptr(frames), int(F), int(W), int(H), ct.byref(fan),
+                                               _ptr(beams), _ptr(probe_poses), _stream(stream)),
+                      "dare_reconstruct_fan")
 
     def reslice(self, probe_pose, width, height, pitch, out=None, stream=None):
         import torch

@@ -15,21 +15,6 @@
 
 using namespace dare;
 
-struct dare_volume {
-    int device = 0;
-    dare_geometry g{};
-    dare_params p{};
-    dare_dtype dtype = DARE_F32;
-    char* arena = nullptr;
-    uint64_t arena_bytes = 0;
-    VolDev host{};              // host mirror of the device header (pointers, geometry, codebook)
-    VolDev* dev = nullptr;      // device header at the start of the arena
-    VolDev* hdr_pinned = nullptr;   // pinned copy of the device header, read at sync points
-    int K = 0;
-    int saturated = 0;
-    uint32_t used = 0;
-};
-
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -516,6 +501,7 @@ dare_status dare_volume_create(const dare_geometry* g, const dare_params* p, dar
     h.data = (void*)(base + L.off_data);
     h.scales = (float2*)(base + L.off_scales);
     v->dev = (VolDev*)base;
+    v->stamp.assign(cap, 0);
     if (hipHostMalloc((void**)&v->hdr_pinned, sizeof(VolDev), hipHostMallocDefault) != hipSuccess) {
         delete v;
         return DARE_ERR_HIP;
@@ -542,8 +528,89 @@ dare_status dare_volume_destroy(dare_volume* v) {
     return hip_status(e);
 }
 
+namespace {
+
+// Frame batches of linear-array frames (fan == nullptr) or fan frames: per batch, placement and
+// bin assignment, one sync to admit the new bricks (spilling cold ones in spill mode), then
+// allocation, accumulation and finalisation.
+dare_status reconstruct_batches(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
+                                const double* pitch_mm, const FanArgs* fan, const float* probe_poses_dev,
+                                hipStream_t stream) {
+    VolDev* vd = v->dev;
+    const int G = fan ? fan->sectors : 1;
+    const int per_batch = kFrameChunk / G;
+    bool retried = false;
+    for (int32_t f0 = 0; f0 < n;) {
+        const int nf = std::min<int32_t>(per_batch, n - f0);
+        const int K0 = v->K, sat0 = v->saturated;
+        const uint32_t used = v->used;
+        const float* poses = probe_poses_dev + (size_t)f0 * 16;
+        if (fan) {
+            HIP_TRY(launch_compose_fan(vd, poses, nf, *fan, w, stream));
+        } else {
+            HIP_TRY(launch_compose_frames(vd, poses, nf, stream));
+        }
+        HIP_TRY(launch_assign_bins(vd, nf * G, K0, stream));
+        if (fan) {
+            HIP_TRY(launch_mark_fan(vd, nf, w, h, *fan, stream));
+        } else {
+            HIP_TRY(launch_mark_pixels(vd, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
+        }
+        VolState st;
+        dare_status s = read_state(v, stream, &st);
+        if (s != DARE_OK) return s;
+        const bool bad = st.bad_pose != 0;
+        const bool over = (uint64_t)used + st.new_count > v->host.cap;
+        // slots the batch touches: kept in HBM by a spill, stamped as recently used
+        std::vector<int32_t> touched;
+        const bool spill = v->spill && !bad && !retried && (uint64_t)st.dirty_count + st.new_count <= v->host.cap;
+        if ((over && spill) || (!over && !bad && v->spill)) {
+            touched.resize(st.dirty_count);
+            if (st.dirty_count) {
+                HIP_TRY(hipMemcpyAsync(touched.data(), v->host.dirty_list, (size_t)st.dirty_count * sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, stream));
+                HIP_TRY(hipStreamSynchronize(stream));
+            }
+        }
+        if (bad || over) {
+            HIP_TRY(launch_rollback(vd, st.new_count, st.dirty_count, K0, sat0, stream));
+            if (st.new_count > v->host.cap)   // marks beyond the list: clear them table-wide
+                HIP_TRY(launch_clear_marks(v->host.table, (int64_t)v->p.max_bins * v->host.nbricks, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (over && spill) {   // make room, then the same batch again
+                s = spill_for_batch(v, touched, (uint64_t)used + st.new_count - v->host.cap, stream);
+                if (s != DARE_OK) return s;
+                retried = true;
+                continue;
+            }
+            return bad ? DARE_ERR_BAD_POSE : DARE_ERR_BUDGET;
+        }
+        HIP_TRY(launch_alloc(vd, st.new_count, used, st.dirty_count, stream));
+        const uint8_t* fr = frames_dev + (size_t)f0 * w * h;
+        if (fan) {
+            HIP_TRY(launch_accumulate_fan(vd, fr, nf, w, h, *fan, stream));
+        } else {
+            HIP_TRY(launch_accumulate(vd, fr, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
+        }
+        HIP_TRY(launch_finalize(vd, v->dtype, st.dirty_count + st.new_count, stream));
+        v->K = st.K;
+        v->saturated = st.saturated;
+        v->used = used + st.new_count;
+        if (v->spill) {
+            ++v->clock;
+            for (int32_t t : touched) v->stamp[t] = v->clock;
+            for (uint32_t t = used; t < v->used; ++t) v->stamp[t] = v->clock;
+        }
+        retried = false;
+        f0 += nf;
+    }
+    return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
+}
+
+}  // namespace
+
 dare_status dare_reconstruct_frames(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
-                                    const double pitch_mm[2], const float* probe_poses_dev, void* stream_) {
+                                    const double pitch_mm[2], const float* probe_poses_dev, void* stream) {
     if (!v || !pitch_mm || n < 0) return DARE_ERR_INVALID_ARG;
     if (n == 0) return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
     if (!frames_dev || !probe_poses_dev || w <= 0 || h <= 0 || (int64_t)w * h > (int64_t)1 << 30)
@@ -551,35 +618,32 @@ dare_status dare_reconstruct_frames(dare_volume* v, const uint8_t* frames_dev, i
     if (!(pitch_mm[0] > 0.0) || !(pitch_mm[1] > 0.0) || !std::isfinite(pitch_mm[0]) || !std::isfinite(pitch_mm[1]))
         return DARE_ERR_INVALID_ARG;
     DeviceGuard dg(v->device);
-    hipStream_t stream = (hipStream_t)stream_;
-    VolDev* vd = v->dev;
-    for (int32_t f0 = 0; f0 < n; f0 += kFrameChunk) {
-        const int nf = std::min<int32_t>(kFrameChunk, n - f0);
-        const int K0 = v->K, sat0 = v->saturated;
-        const uint32_t used = v->used;
-        HIP_TRY(launch_compose_frames(vd, probe_poses_dev + (size_t)f0 * 16, nf, stream));
-        HIP_TRY(launch_assign_bins(vd, nf, K0, stream));
-        HIP_TRY(launch_mark_pixels(vd, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
-        VolState st;
-        dare_status s = read_state(v, stream, &st);
-        if (s != DARE_OK) return s;
-        const bool bad = st.bad_pose != 0;
-        const bool over = (uint64_t)used + st.new_count > v->host.cap;
-        if (bad || over) {
-            HIP_TRY(launch_rollback(vd, st.new_count, st.dirty_count, K0, sat0, stream));
-            if (st.new_count > v->host.cap)   // marks beyond the list: clear them table-wide
-                HIP_TRY(launch_clear_marks(v->host.table, (int64_t)v->p.max_bins * v->host.nbricks, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            return bad ? DARE_ERR_BAD_POSE : DARE_ERR_BUDGET;
-        }
-        HIP_TRY(launch_alloc(vd, st.new_count, used, st.dirty_count, stream));
-        HIP_TRY(launch_accumulate(vd, frames_dev + (size_t)f0 * w * h, nf, w, h, pitch_mm[0], pitch_mm[1], stream));
-        HIP_TRY(launch_finalize(vd, v->dtype, st.dirty_count + st.new_count, stream));
-        v->K = st.K;
-        v->saturated = st.saturated;
-        v->used = used + st.new_count;
-    }
-    return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
+    return reconstruct_batches(v, frames_dev, n, w, h, pitch_mm, nullptr, probe_poses_dev, (hipStream_t)stream);
+}
+
+dare_status dare_reconstruct_fan(dare_volume* v, const uint8_t* frames_dev, int32_t n, int32_t w, int32_t h,
+                                 const dare_fan* fan, const double* beams_dev, const float* probe_poses_dev,
+                                 void* stream) {
+    if (!v || !fan || n < 0) return DARE_ERR_INVALID_ARG;
+    if (v->p.normal_axis != 2) return DARE_ERR_INVALID_ARG;
+    if (!std::isfinite(fan->apex_mm[0]) || !std::isfinite(fan->apex_mm[1]) || !std::isfinite(fan->r0_mm) ||
+        !(fan->r0_mm >= 0.0) || !std::isfinite(fan->dr_mm) || !(fan->dr_mm > 0.0))
+        return DARE_ERR_INVALID_ARG;
+    if (fan->sectors < 1 || fan->sectors > kMaxBins || (w > 0 && fan->sectors > w) ||
+        (int64_t)w * fan->sectors > 0x7FFFFFFF)
+        return DARE_ERR_INVALID_ARG;
+    if (n == 0) return v->saturated ? DARE_WARN_BINS_SATURATED : DARE_OK;
+    if (!frames_dev || !probe_poses_dev || !beams_dev || w <= 0 || h <= 0 || (int64_t)w * h > (int64_t)1 << 30)
+        return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(v->device);
+    FanArgs a;
+    a.apex[0] = fan->apex_mm[0];
+    a.apex[1] = fan->apex_mm[1];
+    a.r0 = fan->r0_mm;
+    a.dr = fan->dr_mm;
+    a.beams = beams_dev;
+    a.sectors = fan->sectors;
+    return reconstruct_batches(v, frames_dev, n, w, h, nullptr, &a, probe_poses_dev, (hipStream_t)stream);
 }
 
 dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, float* out_dev, void* stream) {
@@ -803,7 +867,7 @@ uint64_t dare_volume_save_bytes(const dare_volume* v) {
 }
 
 dare_status dare_volume_save(const dare_volume* v, void* host_out, uint64_t bytes) {
-    if (!v || !host_out) return DARE_ERR_INVALID_ARG;
+    if (!v || !host_out || !v->held.empty()) return DARE_ERR_INVALID_ARG;
     DeviceGuard dg(v->device);
     HIP_TRY(hipDeviceSynchronize());
     VolDev d;
@@ -929,6 +993,8 @@ dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n, const d
     v->K = bins;
     v->saturated = 0;
     v->used = 0;
+    v->held.clear();
+    std::fill(v->stamp.begin(), v->stamp.end(), 0);
     if (bins == 0) return hip_status(hipStreamSynchronize(stream));
     HIP_TRY(launch_dense_mark(v->dev, C, bins, stream));
     VolState st;

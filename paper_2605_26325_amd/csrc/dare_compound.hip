@@ -140,6 +140,30 @@ __global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, d
     mark_entry(vd, brick_entry(vd, vd->frame_bin[f], vx, vy, vz));
 }
 
+// Fan probes: one frame descriptor per (frame, sector), each with the frame's pose and the
+// sector's in-plane direction, so that the bin assignment runs over them as over frames.
+__global__ void k_compose_fan(VolDev* vd, const float* __restrict__ poses, int n, FanArgs fan, int width) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n * fan.sectors) return;
+    const int f = k / fan.sectors;
+    FrameDesc d;
+    if (!compose_frame(poses + (size_t)f * 16, vd->calib, 2, d)) atomicOr(&vd->st.bad_pose, 1);
+    fan_sector_axis(d, fan, width, k - f * fan.sectors);
+    vd->frames[k] = d;
+}
+
+// K3a for fan frames: the pixel's (frame, sector) descriptor gives its pose and bin.
+__global__ void __launch_bounds__(256) k_mark_fan(VolDev* vd, int w, int h, FanArgs fan) {
+    const int f = blockIdx.y;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= w * h) return;
+    const int i = pix % w, j = pix / w;
+    const int e = f * fan.sectors + i * fan.sectors / w;
+    int vx, vy, vz;
+    if (!fan_voxel(vd->frames + e, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, fan, i, j, vx, vy, vz)) return;
+    mark_entry(vd, brick_entry(vd, vd->frame_bin[e], vx, vy, vz));
+}
+
 // Undo the marks of a rejected batch and restore the codebook size.
 __global__ void k_rollback(VolDev* vd, uint32_t new_count, uint32_t dirty_count, int K0, int sat0) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,6 +208,22 @@ __global__ void __launch_bounds__(256) k_accumulate(const VolDev* __restrict__ v
     int vx, vy, vz;
     if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
     const int slot = vd->table[brick_entry(vd, vd->frame_bin[f], vx, vy, vz)];
+    if (slot < 0) return;   // unreachable: every entry hit here was marked and allocated
+    const unsigned long long inten = frames[(size_t)f * w * h + pix];
+    atomicAdd(vd->acc + (size_t)slot * kBrickVox + brick_local(vx, vy, vz), (inten << 32) | 1ull);
+}
+
+// K4 for fan frames.
+__global__ void __launch_bounds__(256) k_accumulate_fan(const VolDev* __restrict__ vd,
+                                                        const uint8_t* __restrict__ frames, int w, int h, FanArgs fan) {
+    const int f = blockIdx.y;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= w * h) return;
+    const int i = pix % w, j = pix / w;
+    const int e = f * fan.sectors + i * fan.sectors / w;
+    int vx, vy, vz;
+    if (!fan_voxel(vd->frames + e, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, fan, i, j, vx, vy, vz)) return;
+    const int slot = vd->table[brick_entry(vd, vd->frame_bin[e], vx, vy, vz)];
     if (slot < 0) return;   // unreachable: every entry hit here was marked and allocated
     const unsigned long long inten = frames[(size_t)f * w * h + pix];
     atomicAdd(vd->acc + (size_t)slot * kBrickVox + brick_local(vx, vy, vz), (inten << 32) | 1ull);
@@ -383,6 +423,26 @@ hipError_t launch_assign_bins(VolDev* vd, int n, int K0, hipStream_t stream) {
 hipError_t launch_mark_pixels(const VolDev* vd, int n, int w, int h, double sx, double sy, hipStream_t stream) {
     hipLaunchKernelGGL(k_mark_pixels, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, const_cast<VolDev*>(vd),
                        w, h, sx, sy);
+    return hipGetLastError();
+}
+
+hipError_t launch_compose_fan(const VolDev* vd, const float* poses, int n, const FanArgs& fan, int width,
+                              hipStream_t stream) {
+    const int m = n * fan.sectors;
+    hipLaunchKernelGGL(k_compose_fan, dim3((m + 63) / 64), dim3(64), 0, stream, const_cast<VolDev*>(vd), poses, n, fan,
+                       width);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_fan(const VolDev* vd, int n, int w, int h, const FanArgs& fan, hipStream_t stream) {
+    hipLaunchKernelGGL(k_mark_fan, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, const_cast<VolDev*>(vd), w, h,
+                       fan);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_fan(const VolDev* vd, const uint8_t* frames, int n, int w, int h, const FanArgs& fan,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(k_accumulate_fan, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, vd, frames, w, h, fan);
     return hipGetLastError();
 }
 

@@ -65,13 +65,10 @@ __device__ inline bool compose_frame(const float* __restrict__ pose, const doubl
     return ok;
 }
 
-// Nearest voxel floor(c + 0.5) of frame pixel (i, j), c = (p - o) / h with
-// p = (t + (i sx) e0) + (j sy) e1; false when it lies outside the grid.
-__device__ inline bool frame_voxel(const FrameDesc* __restrict__ fd, const double* __restrict__ origin, double inv_h,
-                                   int nx, int ny, int nz, int i, int j, double sx, double sy, int& vx, int& vy,
-                                   int& vz) {
-    const double is = (double)i * sx;
-    const double js = (double)j * sy;
+// Nearest voxel floor(c + 0.5) of the image-plane point (u, v) millimetres, c = (p - o) / h with
+// p = (t + u e0) + v e1; false when it lies outside the grid.
+__device__ inline bool plane_voxel(const FrameDesc* __restrict__ fd, const double* __restrict__ origin, double inv_h,
+                                   int nx, int ny, int nz, double is, double js, int& vx, int& vy, int& vz) {
     double c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -84,6 +81,49 @@ __device__ inline bool frame_voxel(const FrameDesc* __restrict__ fd, const doubl
     vy = (int)c[1];
     vz = (int)c[2];
     return true;
+}
+
+// Nearest voxel of linear-array pixel (i, j), at image millimetres (i sx, j sy).
+__device__ inline bool frame_voxel(const FrameDesc* __restrict__ fd, const double* __restrict__ origin, double inv_h,
+                                   int nx, int ny, int nz, int i, int j, double sx, double sy, int& vx, int& vy,
+                                   int& vz) {
+    return plane_voxel(fd, origin, inv_h, nx, ny, nz, (double)i * sx, (double)j * sy, vx, vy, vz);
+}
+
+// A fan probe (curvilinear, or phased array with r0 = 0): column i's beam leaves the apex with
+// unit direction beams[2i], beams[2i + 1] (image mm: lateral, axial), and pixel (i, j) lies on it
+// at r0 + j dr from the apex.  Columns are binned in `sectors` equal sectors, column i in sector
+// i * sectors / width.
+struct FanArgs {
+    double apex[2];
+    double r0, dr;
+    const double* beams;   // device, width x 2
+    int sectors;
+};
+
+// Nearest voxel of fan pixel (i, j): r = r0 + j dr, (u, v) = (a0 + r b_i0, a1 + r b_i1).
+__device__ inline bool fan_voxel(const FrameDesc* __restrict__ fd, const double* __restrict__ origin, double inv_h,
+                                 int nx, int ny, int nz, const FanArgs& fan, int i, int j, int& vx, int& vy, int& vz) {
+    const double r = fan.r0 + (double)j * fan.dr;
+    const double u = fan.apex[0] + r * fan.beams[2 * i];
+    const double v = fan.apex[1] + r * fan.beams[2 * i + 1];
+    return plane_voxel(fd, origin, inv_h, nx, ny, nz, u, v, vx, vy, vz);
+}
+
+// In-plane direction of sector g of a `width`-column fan: across the beam of the sector's middle
+// column, x = b1 xhat - b0 yhat with yhat = e1 / |e1| (xhat for a beam along the axial axis).
+__device__ inline void fan_sector_axis(FrameDesc& d, const FanArgs& fan, int width, int g) {
+    const int G = fan.sectors;
+    const int first = (g * width + G - 1) / G;
+    const int last = ((g + 1) * width + G - 1) / G - 1;
+    const int m = (first + last) / 2;
+    const double b0 = fan.beams[2 * m], b1 = fan.beams[2 * m + 1];
+    const double ly = sqrt(frame_dot3(d.e1, d.e1));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double yh = d.e1[a] / ly;
+        d.xh[a] = b1 * d.xh[a] - b0 * yh;
+    }
 }
 
 }  // namespace dare
