@@ -41,75 +41,94 @@ __global__ void k_compose_frames(VolDev* vd, const float* __restrict__ poses, in
     vd->frames[f] = d;
 }
 
-// K2: leader clustering of frame orientations, frames in order; one wave,
-// lane b holds representative b in registers.
-__global__ void __launch_bounds__(64) k_assign_bins(VolDev* vd, int n, int K0) {
-    const int lane = threadIdx.x;
-    double rn[3] = {0, 0, 0}, rx[3] = {0, 0, 0};
-    if (lane < K0) {
+// K2: leader clustering of frame orientations, frames in order, by one workgroup.  The
+// sequential rule (an entry joins its best qualifying bin, else opens a new one, else, with the
+// codebook full, joins its best bin overall) only changes the codebook when an entry opens a bin,
+// so chunks of 256 consecutive entries are tested in parallel against the current codebook:
+// every entry before the chunk's first opener is final as tested, the opener takes the next bin,
+// and the scan resumes after it.  Identical results in at most n / 256 + max_bins steps.
+__global__ void __launch_bounds__(256) k_assign_bins(VolDev* vd, int n, int K0) {
+    __shared__ double rep[kMaxBins][6];   // per bin: representative normal, then in-plane axis
+    __shared__ int s_first, s_sat;
+    const int tid = threadIdx.x;
+    if (tid < K0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            rn[a] = vd->rep_n[lane][a];
-            rx[a] = vd->rep_x[lane][a];
+            rep[tid][a] = vd->rep_n[tid][a];
+            rep[tid][3 + a] = vd->rep_x[tid][a];
         }
+    }
+    if (tid == 0) {
+        s_first = 256;
+        s_sat = vd->st.saturated;
     }
     int K = K0;
-    int sat = vd->st.saturated;
     const double ct = vd->cos_tol;
     const int kmax = vd->max_bins;
-    for (int f = 0; f < n; ++f) {
-        const FrameDesc* fd = vd->frames + f;
-        double nf[3], xf[3];
+    for (int base = 0; base < n;) {
+        __syncthreads();
+        const int f = base + tid;
+        double nf[3] = {0, 0, 0}, xf[3] = {0, 0, 0};
+        int best = -1, any = -1;
+        if (f < n) {
+            const FrameDesc* fd = vd->frames + f;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            nf[a] = fd->nh[a];
-            xf[a] = fd->xh[a];
-        }
-        double s = -INFINITY, key = -INFINITY;
-        if (lane < K) {
-            const double dn = dot3(nf, rn);
-            const double di = fabs(dot3(xf, rx));
-            s = dn + di;
-            if (dn >= ct && di >= ct) key = s;
-        }
-        // argmax over qualifying bins and over all bins; ties go to the lowest index
-        double bk = key, ak = s;
-        int bi = lane, ai = lane;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ok = __shfl_xor(bk, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ok > bk || (ok == bk && oi < bi)) { bk = ok; bi = oi; }
-            const double ok2 = __shfl_xor(ak, off);
-            const int oi2 = __shfl_xor(ai, off);
-            if (ok2 > ak || (ok2 == ak && oi2 < ai)) { ak = ok2; ai = oi2; }
-        }
-        int b;
-        if (bk > -INFINITY) {
-            b = bi;
-        } else if (K < kmax) {
-            b = K;
-            if (lane == K) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) { rn[a] = nf[a]; rx[a] = xf[a]; }
+            for (int a = 0; a < 3; ++a) {
+                nf[a] = fd->nh[a];
+                xf[a] = fd->xh[a];
             }
-            ++K;
-        } else {
-            b = ai;
-            sat = 1;
+            double best_s = -INFINITY, any_s = -INFINITY;
+            for (int b = 0; b < K; ++b) {   // strict > keeps the lowest index on ties
+                const double rn[3] = {rep[b][0], rep[b][1], rep[b][2]};
+                const double rx[3] = {rep[b][3], rep[b][4], rep[b][5]};
+                const double dn = dot3(nf, rn);
+                const double di = fabs(dot3(xf, rx));
+                const double sc = dn + di;
+                if (sc > any_s) {
+                    any_s = sc;
+                    any = b;
+                }
+                if (dn >= ct && di >= ct && sc > best_s) {
+                    best_s = sc;
+                    best = b;
+                }
+            }
+            if (best < 0 && K < kmax) atomicMin(&s_first, tid);
         }
-        if (lane == 0) vd->frame_bin[f] = b;
+        __syncthreads();
+        const int p = s_first;
+        if (f < n && tid < p) {
+            vd->frame_bin[f] = best >= 0 ? best : any;
+            if (best < 0) s_sat = 1;   // only with the codebook full
+        }
+        if (tid == p) {
+            vd->frame_bin[f] = K;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                rep[K][a] = nf[a];
+                rep[K][3 + a] = xf[a];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_first = 256;
+        if (p < 256) {
+            ++K;
+            base += p + 1;
+        } else {
+            base += 256;
+        }
     }
-    if (lane < K) {
+    __syncthreads();
+    if (tid >= K0 && tid < K) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            vd->rep_n[lane][a] = rn[a];
-            vd->rep_x[lane][a] = rx[a];
+            vd->rep_n[tid][a] = rep[tid][a];
+            vd->rep_x[tid][a] = rep[tid][3 + a];
         }
     }
-    if (lane == 0) {
+    if (tid == 0) {
         vd->st.K = K;
-        vd->st.saturated = sat;
+        vd->st.saturated = s_sat;
     }
 }
 
@@ -416,7 +435,7 @@ hipError_t launch_compose_frames(const VolDev* vd, const float* poses, int n, hi
 }
 
 hipError_t launch_assign_bins(VolDev* vd, int n, int K0, hipStream_t stream) {
-    hipLaunchKernelGGL(k_assign_bins, dim3(1), dim3(64), 0, stream, vd, n, K0);
+    hipLaunchKernelGGL(k_assign_bins, dim3(1), dim3(256), 0, stream, vd, n, K0);
     return hipGetLastError();
 }
 
