@@ -13,8 +13,9 @@
 // where every term is a multiple of 2^-26 below 2^8, so the sums are exact in any order.
 //
 // Reslice: a small kernel evaluates Eq. 1, the two thresholds and Eq. 2 for every frame (the
-// per-slice weight table); the reslice kernel keeps the table in LDS and takes one output pixel
-// per thread: FP64 position, then its neighbourhood's samples, in one of two readings:
+// per-slice weight table); the reslice kernel keeps the table in LDS, takes 16 x 16 output pixels
+// per workgroup, sums every voxel the tile reaches once (into LDS), and gives each pixel (FP64
+// position) its neighbourhood's blend in one of two readings:
 //   box   the (2R+1)^3 voxels around the nearest voxel, one weighted average over all their
 //         samples: sum w I / sum w;
 //   tent  the voxels with |c - v|_inf < R, each blended over its samples first, then averaged
@@ -22,6 +23,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <climits>
 #include <cmath>
 
 #include "dare_frames.h"
@@ -35,6 +37,7 @@ namespace {
 
 constexpr int kScanBlock = 1024;          // counts scanned per workgroup (4 per thread)
 constexpr int kLutLds = 8192;             // frames whose weights a reslice workgroup keeps in LDS
+constexpr int kTileBox = 1536;            // voxels whose sums a tiled reslice workgroup keeps in LDS
 constexpr int32_t kMaxFrames = 1 << 24;   // frame index bits of a packed sample
 constexpr uint64_t kAlignBytes = 256;
 
@@ -219,19 +222,12 @@ __global__ void __launch_bounds__(256) k_lit_lut(SampleDev d, LutArgs a) {
     d.lut[f] = w;
 }
 
-__global__ void __launch_bounds__(256) k_lit_reslice(SampleDev d, LitSlice s) {
-    extern __shared__ float lut_s[];
-    const int F = d.n_frames;
-    const bool in_lds = F <= kLutLds;
-    if (in_lds)
-        for (int k = threadIdx.x; k < F; k += 256) lut_s[k] = d.lut[k];
-    __syncthreads();
-    const float* __restrict__ lut = in_lds ? lut_s : d.lut;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= (int64_t)s.W * s.H) return;
-    const int j = (int)(p / s.W), i = (int)(p - (int64_t)j * s.W);
+// Pixel (i, j) of the slice: FP64 sample position c in voxel units and the voxel range of its
+// reading (box: the (2R+1)^3 voxels around the nearest one; tent: |c - v|_inf < R), clipped to
+// the grid.  False when no voxel is within reach (the pixel stays unassigned).
+__device__ inline bool pixel_range(const SampleDev& d, const LitSlice& s, int i, int j, double c[3], int lo[3],
+                                   int hi[3]) {
     const double is = (double)i * s.sx, js = (double)j * s.sy;
-    double c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double q = (s.t[a] + is * s.e0[a]) + js * s.e1[a];
@@ -240,11 +236,8 @@ __global__ void __launch_bounds__(256) k_lit_reslice(SampleDev d, LitSlice s) {
     const double R = (double)s.R;
     // nothing within reach: also keeps the integer conversions below in range
     if (!(c[0] > -R - 1.0 && c[0] < d.n[0] + R && c[1] > -R - 1.0 && c[1] < d.n[1] + R && c[2] > -R - 1.0 &&
-          c[2] < d.n[2] + R)) {
-        s.out[p] = __builtin_nanf("");
-        return;
-    }
-    int lo[3], hi[3];
+          c[2] < d.n[2] + R))
+        return false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (s.mode == 0) {
@@ -258,6 +251,30 @@ __global__ void __launch_bounds__(256) k_lit_reslice(SampleDev d, LitSlice s) {
         lo[a] = max(lo[a], 0);
         hi[a] = min(hi[a], d.n[a] - 1);
     }
+    return true;
+}
+
+// Sum of the weights and of weight x intensity over one voxel's samples, in store order (the
+// sums are exact, so any order gives the same result).
+__device__ inline void voxel_sums(const SampleDev& d, const float* __restrict__ lut, int64_t v, double& sw,
+                                  double& swi) {
+    const uint32_t o0 = d.offsets[v], o1 = d.offsets[v + 1];
+    sw = 0.0;
+    swi = 0.0;
+    for (uint32_t k = o0; k < o1; ++k) {
+        const uint32_t u = d.samples[k];
+        const double w = (double)lut[u >> 8];
+        sw += w;
+        swi += w * (double)(u & 0xFFu);
+    }
+}
+
+// The pixel's value from the per-voxel sums that `get(vx, vy, vz, sw, swi)` provides, voxels
+// visited z, y, x: box, one average over all samples; tent, voxel averages blended with tent
+// weights.  NaN when nothing contributes.
+template <class Get>
+__device__ inline float blend_range(const LitSlice& s, const double c[3], const int lo[3], const int hi[3], Get get) {
+    const double R = (double)s.R;
     double num = 0.0, den = 0.0;
     for (int vz = lo[2]; vz <= hi[2]; ++vz)
         for (int vy = lo[1]; vy <= hi[1]; ++vy)
@@ -269,15 +286,8 @@ __global__ void __launch_bounds__(256) k_lit_reslice(SampleDev d, LitSlice s) {
                     for (int a = 0; a < 3; ++a) t *= fmax(0.0, 1.0 - fabs(c[a] - (double)v[a]) / R);
                     if (!(t > 0.0)) continue;
                 }
-                const int64_t v = voxel_index(d, vx, vy, vz);
-                const uint32_t o0 = d.offsets[v], o1 = d.offsets[v + 1];
-                double sw = 0.0, swi = 0.0;
-                for (uint32_t k = o0; k < o1; ++k) {
-                    const uint32_t u = d.samples[k];
-                    const double w = (double)lut[u >> 8];
-                    sw += w;
-                    swi += w * (double)(u & 0xFFu);
-                }
+                double sw, swi;
+                get(vx, vy, vz, sw, swi);
                 if (s.mode == 0) {
                     num += swi;
                     den += sw;
@@ -286,7 +296,100 @@ __global__ void __launch_bounds__(256) k_lit_reslice(SampleDev d, LitSlice s) {
                     den += t;
                 }
             }
-    s.out[p] = den > 0.0 ? (float)(num / den) : __builtin_nanf("");
+    return den > 0.0 ? (float)(num / den) : __builtin_nanf("");
+}
+
+// One workgroup per 16 x 16 tile of output pixels.  The pixels' voxel ranges are marked in a
+// byte map over the tile's bounding box of voxels; each marked voxel's sums are computed once, by
+// one thread, into LDS; every pixel then blends from LDS in the same voxel order as above, so
+// the result is the same as summing per pixel.  A tile whose box exceeds kTileBox voxels (coarse
+// output pitch, large radius) does sum per pixel.
+__global__ void __launch_bounds__(256) k_lit_reslice_tiled(SampleDev d, LitSlice s, int tiles_x) {
+    extern __shared__ float lut_s[];
+    __shared__ double2 sums[kTileBox];
+    __shared__ uint8_t mark[kTileBox];
+    __shared__ int box[6];
+    const int tid = threadIdx.x;
+    const int F = d.n_frames;
+    const bool in_lds = F <= kLutLds;
+    if (in_lds)
+        for (int k = tid; k < F; k += 256) lut_s[k] = d.lut[k];
+    for (int k = tid; k < kTileBox; k += 256) mark[k] = 0;
+    if (tid < 3) {
+        box[tid] = INT_MAX;
+        box[3 + tid] = INT_MIN;
+    }
+    __syncthreads();
+    const float* __restrict__ lut = in_lds ? lut_s : d.lut;
+    const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+    const int i = tx * 16 + (tid & 15), j = ty * 16 + (tid >> 4);
+    const bool inside = i < s.W && j < s.H;
+    double c[3];
+    int lo[3], hi[3];
+    const bool reach = inside && pixel_range(d, s, i, j, c, lo, hi) && lo[0] <= hi[0] && lo[1] <= hi[1] &&
+                       lo[2] <= hi[2];
+    if (reach) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&box[a], lo[a]);
+            atomicMax(&box[3 + a], hi[a]);
+        }
+    }
+    __syncthreads();
+    const int b0[3] = {box[0], box[1], box[2]};
+    const int64_t bd[3] = {(int64_t)box[3] - b0[0] + 1, (int64_t)box[4] - b0[1] + 1, (int64_t)box[5] - b0[2] + 1};
+    const int64_t nbox = (bd[0] > 0 && bd[1] > 0 && bd[2] > 0) ? bd[0] * bd[1] * bd[2] : 0;
+    const int64_t p = (int64_t)j * s.W + i;
+    if (nbox > kTileBox) {   // uniform over the workgroup
+        if (inside)
+            s.out[p] = !reach ? __builtin_nanf("")
+                              : blend_range(s, c, lo, hi, [&](int vx, int vy, int vz, double& sw, double& swi) {
+                                    voxel_sums(d, lut, voxel_index(d, vx, vy, vz), sw, swi);
+                                });
+        return;
+    }
+    const int nx = (int)bd[0], ny = (int)bd[1];
+    if (reach)   // every writer stores the same byte
+        for (int vz = lo[2]; vz <= hi[2]; ++vz)
+            for (int vy = lo[1]; vy <= hi[1]; ++vy)
+                for (int vx = lo[0]; vx <= hi[0]; ++vx) mark[((vz - b0[2]) * ny + (vy - b0[1])) * nx + (vx - b0[0])] = 1;
+    __syncthreads();
+    // a thread's (up to kTileBox / 256) voxels: all row offsets loaded before any sample
+    constexpr int kPer = kTileBox / 256;
+    uint32_t o0[kPer], o1[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = tid + 256 * q;
+        o0[q] = o1[q] = 0u;
+        if (k < (int)nbox && mark[k]) {
+            const int lx = k % nx, r = k / nx, ly = r % ny, lz = r / ny;
+            const int64_t v = voxel_index(d, b0[0] + lx, b0[1] + ly, b0[2] + lz);
+            o0[q] = d.offsets[v];
+            o1[q] = d.offsets[v + 1];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int k = tid + 256 * q;
+        if (k < (int)nbox && mark[k]) {
+            double sw = 0.0, swi = 0.0;
+            for (uint32_t e = o0[q]; e < o1[q]; ++e) {
+                const uint32_t u = d.samples[e];
+                const double w = (double)lut[u >> 8];
+                sw += w;
+                swi += w * (double)(u & 0xFFu);
+            }
+            sums[k] = make_double2(sw, swi);
+        }
+    }
+    __syncthreads();
+    if (!inside) return;
+    s.out[p] = !reach ? __builtin_nanf("")
+                      : blend_range(s, c, lo, hi, [&](int vx, int vy, int vz, double& sw, double& swi) {
+                            const double2 q = sums[((vz - b0[2]) * ny + (vy - b0[1])) * nx + (vx - b0[0])];
+                            sw = q.x;
+                            swi = q.y;
+                        });
 }
 
 // Empty store: every voxel's range is [0, 0).
@@ -489,9 +592,10 @@ dare_status dare_samples_reslice(const dare_samples* st, const dare_params* p, c
         la.k_i = p->k_inplane;
         hipLaunchKernelGGL(k_lit_lut, dim3((st->d.n_frames + 255) / 256), dim3(256), 0, stream, st->d, la);
     }
-    const int64_t npx = (int64_t)s.W * s.H;
     const size_t lds = st->d.n_frames <= kLutLds ? (size_t)st->d.n_frames * sizeof(float) : 0;
-    hipLaunchKernelGGL(k_lit_reslice, dim3((unsigned)((npx + 255) / 256)), dim3(256), lds, stream, st->d, s);
+    const int tiles_x = (s.W + 15) / 16;
+    const int64_t tiles = (int64_t)tiles_x * ((s.H + 15) / 16);
+    hipLaunchKernelGGL(k_lit_reslice_tiled, dim3((unsigned)tiles), dim3(256), lds, stream, st->d, s, tiles_x);
     return hip_status(hipGetLastError());
 }
 

@@ -115,6 +115,32 @@ def test_config1_subset(dare, torch_cuda):
     assert checked > 100
 
 
+@pytest.mark.parametrize("W,H,pitch", [(48, 40, (0.25, 0.25)), (96, 80, (0.125, 0.125)), (37, 29, (1.0, 1.0))])
+def test_tile_sizes_config1(dare, torch_cuda, W, H, pitch):
+    """Slices whose 16 x 16 tiles span few voxels (sums shared in LDS) and many (coarse pitch: the
+    tile's box exceeds LDS and pixels sum their own voxels), ragged at the right and bottom, in
+    both readings, against the oracle."""
+    torch = torch_cuda
+    wl = synth.config1()
+    frames = wl.render("cpu").numpy()
+    sel = list(range(0, 100, 8)) + list(range(100, 200, 8))
+    fr = np.ascontiguousarray(frames[sel])
+    poses = np.asarray(wl.sweep.probe_poses, np.float32)[sel]
+    note(f"per-sample store, config 1 subset, {W}x{H} slices at {pitch[0]} mm")
+    st = _store(dare, torch, wl.origin, wl.spacing, wl.dims, wl.calib, poses, fr, wl.sweep.pitch)
+    ref_store = literal.SampleStore(wl.origin, wl.spacing, wl.dims, normal_axis=2)
+    ref_store.add_frames(fr, poses.astype(np.float64), wl.calib, wl.sweep.pitch)
+    prm = Params()
+    checked = 0
+    for k in (0, 5, 13):
+        P = wl.slices.probe_poses[k]
+        for mode, spatial, norm in (("box", "box", "sample"), ("tent", "tent", "two_stage")):
+            got = st.reslice(P, W, H, pitch, lib_params(prm), mode).cpu().numpy()
+            ref = literal.reslice(ref_store, wl.calib, P, W, H, pitch, prm, spatial=spatial, norm=norm)
+            checked += assert_parity(got, ref, what=f"slice {k} {mode}")
+    assert checked > 1000
+
+
 def test_tent_reading_equals_binned_volume_without_tolerance(dare, torch_cuda):
     """With bin tolerance 0 every distinct frame orientation is its own bin, so the binned
     volume's reslice is the per-sample tent reading (FP32 sums there, FP64 here)."""
