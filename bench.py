@@ -695,6 +695,43 @@ def main():
         f"device), {value:.0f} Mpixel/s")
     nan_frac = float(torch.isnan(outs).float().mean().item())
 
+    # ---- the same launches spread over two streams (slices are independent): one kernel's tail
+    # and the next one's dispatch and setup overlap; results must not change
+    concurrent = None
+    if not args.no_forms:
+        ref_outs = outs.clone()
+        s2 = torch.cuda.Stream()
+        hs = [sh, ct.c_void_p(s2.cuda_stream)]
+
+        def step2(v):
+            h = v.handle
+            for k in range(len(specs)):
+                st = reslice(h, spec_refs[k], out_ptrs[k], hs[k & 1])
+                if st != 0:
+                    raise dare.DareError(st, "dare_reslice")
+
+        def timed2(n):
+            c0, c1, c2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            torch.cuda.synchronize()
+            c0.record(stream)
+            s2.wait_event(c0)
+            for _ in range(n):
+                step2(vol)
+            c2.record(s2)
+            stream.wait_event(c2)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            return c0.elapsed_time(c1) / n
+
+        timed2(max(1, args.warmup))
+        ms2 = timed2(args.steps)
+        same2 = bool(torch.equal(torch.nan_to_num(outs, nan=-1.0), torch.nan_to_num(ref_outs, nan=-1.0)))
+        concurrent = {"streams": 2, "ms_per_step": round(ms2, 3),
+                      "Mpx_s": round(px_per_step / (ms2 * 1e-3) / 1e6, 1), "equal_to_one_stream": same2}
+        log(f"fp32 one launch per slice over 2 streams: {ms2:.2f} ms/step, {concurrent['Mpx_s']:.0f} Mpixel/s, "
+            f"same results: {same2}")
+        del ref_outs
+
     # ---- roofline of the reslice kernel over the timed launches: their average duration is the
     # event-timed device span of the timed steps divided by the launches in it (back to back on
     # one stream), and the algorithmic bytes are counted per slice by an untimed pass
@@ -1101,6 +1138,7 @@ def main():
                    "bricks_used": int(info.bricks_used), "unassigned_fraction": round(nan_frac, 4)},
         "roofline": roofline,
         "roofline_batched": roofline_batched or None,
+        "two_streams": concurrent,
         "latency_ms": {"fp32": lat32, **({"bf16": forms["bf16"]["latency_ms"]} if "bf16" in forms else {})},
         "reconstruct": {"frames": int(F), "frame_px": [Wf, Hf], "median_ms": round(1e3 * float(np.median(recon_times)), 3),
                         "frames_per_s": round(F / float(np.median(recon_times)), 1),
