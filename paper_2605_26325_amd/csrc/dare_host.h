@@ -3,11 +3,12 @@
 // applies.
 #pragma once
 
-#include <map>
 #include <vector>
 
 #include "dare_frames.h"
+#include "dare_held.h"
 #include "dare_internal.h"
+
 
 // A volume handle: the host's view of a volume whose device state lives in the caller's arena.
 struct dare_volume {
@@ -30,7 +31,7 @@ struct dare_volume {
     bool spill = false;
     uint64_t clock = 0;
     std::vector<uint64_t> stamp;
-    std::map<int64_t, std::vector<unsigned long long>> held;
+    dare::HeldStore held;
 };
 
 namespace dare {

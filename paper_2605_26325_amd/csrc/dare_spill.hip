@@ -126,9 +126,10 @@ bool meets_box(const dare_volume* v, int64_t entry, const int32_t lo[3], const i
 }
 
 void hold(dare_volume* v, int64_t entry, const unsigned long long* acc) {
-    std::vector<unsigned long long>& r = v->held[entry];
-    if (r.empty()) {
-        r.assign(acc, acc + kBrickVox);
+    bool fresh;
+    unsigned long long* r = v->held.add(entry, fresh);
+    if (fresh) {
+        memcpy(r, acc, kAccBytes);
     } else {
         for (int k = 0; k < kBrickVox; ++k) r[k] += acc[k];
     }
@@ -165,7 +166,7 @@ dare_status restore_entries(dare_volume* v, const std::vector<int64_t>& ents, hi
     unsigned long long* buf = (unsigned long long*)stage.p;
     for (size_t k0 = 0; k0 < fresh.size(); k0 += per_round) {
         const size_t m = std::min<size_t>(per_round, fresh.size() - k0);
-        for (size_t k = 0; k < m; ++k) memcpy(buf + k * kBrickVox, v->held[fresh[k0 + k]].data(), kAccBytes);
+        for (size_t k = 0; k < m; ++k) memcpy(buf + k * kBrickVox, v->held.find(fresh[k0 + k]), kAccBytes);
         HIP_TRY(hipMemcpyAsync(d.acc + (size_t)(base + k0) * kBrickVox, buf, m * kAccBytes, hipMemcpyHostToDevice,
                                stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -187,7 +188,7 @@ dare_status restore_entries(dare_volume* v, const std::vector<int64_t>& ents, hi
                                    hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         for (size_t k = 0; k < m; ++k) {
-            const std::vector<unsigned long long>& r = v->held[merge[k0 + k]];
+            const unsigned long long* r = v->held.find(merge[k0 + k]);
             for (int i = 0; i < kBrickVox; ++i) buf[k * kBrickVox + i] += r[i];
         }
         for (size_t k = 0; k < m; ++k)
@@ -296,8 +297,9 @@ dare_status dare_volume_restore_box(dare_volume* v, const int32_t lo[3], const i
     hipStream_t stream = (hipStream_t)stream_;
     HIP_TRY(hipStreamSynchronize(stream));
     std::vector<int64_t> ents;
-    for (const auto& kv : v->held)
+    for (const auto& kv : v->held.index())
         if (meets_box(v, kv.first, lo, hi)) ents.push_back(kv.first);
+    std::sort(ents.begin(), ents.end());   // fresh slots in entry order, whatever the map's order
     return restore_entries(v, ents, stream);
 }
 
