@@ -149,14 +149,23 @@ __device__ __forceinline__ void mark_entry(VolDev* vd, int64_t e) {
     }
 }
 
+// Marks the entry of each lane that has one, except where the lane before it in the wave holds
+// the same entry (neighbouring pixels mostly land in one brick): that lane marks it, which is
+// all a mark needs.  Every lane of the wave must call this.
+__device__ __forceinline__ void mark_wave(VolDev* vd, int64_t e) {
+    const int64_t prev = __shfl_up(e, 1);
+    if (e >= 0 && ((threadIdx.x & 63) == 0 || prev != e)) mark_entry(vd, e);
+}
+
 // K3a: mark every (bin, brick) that a pixel of the batch lands in.
 __global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, double sx, double sy) {
     const int f = blockIdx.y;
     const int pix = blockIdx.x * 256 + threadIdx.x;
-    if (pix >= w * h) return;
+    int64_t e = -1;
     int vx, vy, vz;
-    if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
-    mark_entry(vd, brick_entry(vd, vd->frame_bin[f], vx, vy, vz));
+    if (pix < w * h && pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz))
+        e = brick_entry(vd, vd->frame_bin[f], vx, vy, vz);
+    mark_wave(vd, e);
 }
 
 // Fan probes: one frame descriptor per (frame, sector), each with the frame's pose and the
@@ -175,12 +184,15 @@ __global__ void k_compose_fan(VolDev* vd, const float* __restrict__ poses, int n
 __global__ void __launch_bounds__(256) k_mark_fan(VolDev* vd, int w, int h, FanArgs fan) {
     const int f = blockIdx.y;
     const int pix = blockIdx.x * 256 + threadIdx.x;
-    if (pix >= w * h) return;
-    const int i = pix % w, j = pix / w;
-    const int e = f * fan.sectors + i * fan.sectors / w;
-    int vx, vy, vz;
-    if (!fan_voxel(vd->frames + e, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, fan, i, j, vx, vy, vz)) return;
-    mark_entry(vd, brick_entry(vd, vd->frame_bin[e], vx, vy, vz));
+    int64_t entry = -1;
+    if (pix < w * h) {
+        const int i = pix % w, j = pix / w;
+        const int e = f * fan.sectors + i * fan.sectors / w;
+        int vx, vy, vz;
+        if (fan_voxel(vd->frames + e, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, fan, i, j, vx, vy, vz))
+            entry = brick_entry(vd, vd->frame_bin[e], vx, vy, vz);
+    }
+    mark_wave(vd, entry);
 }
 
 // Undo the marks of a rejected batch and restore the codebook size.
