@@ -169,3 +169,36 @@ def test_spill_in_a_small_arena(dare, setup):
         rest = np.ones(nz, bool)
         rest[z] = False
         assert not C[:, rest].any(), bz
+
+
+def test_spill_with_fan_frames(dare, setup):
+    """Spilling composes with fan-probe compounding (the same batch admission): curvilinear frames
+    compounded 20 per call into an arena of 60 % of their bricks; each z half of the grid, brought
+    back alone, holds the fan oracle's sums."""
+    from oracle import compound, fan
+    torch = setup[0]
+    note("out-of-core: spill mode with fan frames")
+    wl = synth.fan_config(sectors=4)
+    fr = wl.render("cpu")
+    f = fan.Fan(apex=wl.fan["apex"], r0=wl.fan["r0"], dr=wl.fan["dr"], sectors=4)
+    g = compound.empty_grid(wl.origin, wl.spacing, wl.dims, Params().bin_tol_deg, Params().max_bins)
+    fan.compound_fan(g, fr.numpy(), wl.sweep.probe_poses, wl.calib, f, wl.beams)
+    ref = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params())
+    P = torch.from_numpy(np.ascontiguousarray(wl.sweep.probe_poses, np.float32)).cuda()
+    B = torch.from_numpy(np.ascontiguousarray(wl.beams, np.float64)).cuda()
+    frc = fr.cuda()
+    ref.reconstruct_fan(frc, P, f.apex, f.r0, f.dr, 4, B)
+    total = ref.info().bricks_used
+    vol = make_volume(wl.origin, wl.spacing, wl.dims, wl.calib, Params(), bricks=int(total * 0.6))
+    vol.set_spill(True)
+    for a in range(0, frc.shape[0], 20):
+        vol.reconstruct_fan(frc[a:a + 20].contiguous(), P[a:a + 20].contiguous(), f.apex, f.r0, f.dr, 4, B)
+    assert vol.held()[0] > 0
+    nx, ny, nz = (int(d) for d in wl.dims)
+    half = (nz // 2 // BRICK) * BRICK
+    for lo, hi, z in (((0, 0, 0), (nx - 1, ny - 1, half - 1), slice(0, half)),
+                      ((0, 0, half), (nx - 1, ny - 1, nz - 1), slice(half, nz))):
+        vol.evict_outside(lo, hi)
+        vol.restore_box(lo, hi)
+        S, C = _sums(torch, vol)
+        assert np.array_equal(S[:, z], g.S[:, z]) and np.array_equal(C[:, z], g.C[:, z]), z
