@@ -615,8 +615,8 @@ def main():
     ap.add_argument("--streaming-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures one GPU's share of the work "
-              "(--gpus 1); multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures one GPU's share of the work (--gpus 1); "
+              "sharding over several GPUs is designed, not implemented or measured.", file=sys.stderr)
         sys.exit(2)
 
     import torch
