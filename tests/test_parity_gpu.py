@@ -241,7 +241,7 @@ def test_reslice_brute_force_tiny_grids(dare, torch_cuda, seed):
     assert np.isnan(vol.reslice(P, 20, 20, (0.3, 0.3)).cpu().numpy()).all()
 
 
-@pytest.mark.parametrize("R", [2, 3, 4])
+@pytest.mark.parametrize("R", [2, 3, 4, 5, 8])
 def test_reslice_larger_radius(dare, torch_cuda, R):
     torch = torch_cuda
     note(f"reslice radius {R} on a random grid")
@@ -301,6 +301,37 @@ def test_batch_equals_alone_larger_radius(dare, torch_cuda, cfg1, cfg1_grid):
     torch.cuda.synchronize()
     for k in range(len(reqs)):
         assert np.array_equal(outs[k].cpu().numpy(), alone[k].cpu().numpy(), equal_nan=True), k
+
+
+def test_batch_equals_alone_lane_split_radius(dare, torch_cuda, cfg1, cfg1_grid):
+    """Radii above 4 (lanes of a wave share a pixel's neighbourhood): batched requests of two
+    volumes, several sizes, equal the same requests resliced alone, bit for bit."""
+    torch = torch_cuda
+    note("batched reslice at radius 6 and 8 vs one by one")
+    vols = []
+    for R, dt in ((6, "f32"), (8, "bf16")):
+        v = make_volume(cfg1.origin, cfg1.spacing, cfg1.dims, cfg1.calib, Params(radius_vox=R), dtype=dt)
+        upload_grid(v, cfg1_grid.S, cfg1_grid.C, *cfg1_grid.codebook.arrays())
+        vols.append(v)
+    sizes = [(24, 20, (0.5, 0.5)), (9, 13, (1.0, 0.8)), (1, 1, (1, 1))]
+    reqs = []
+    for k in range(6):
+        W, H, pitch = sizes[k % len(sizes)]
+        reqs.append((vols[k % 2], dare.make_spec(cfg1.slices.probe_poses[k], W, H, pitch)))
+    outs = [torch.full((s.height, s.width), -7.0, device="cuda") for _, s in reqs]
+    ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([v for v, _ in reqs], [s for _, s in reqs]),
+                     dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([v for v, _ in reqs], [s for _, s in reqs], outs, ws)
+    alone = []
+    for v, s in reqs:
+        o = torch.full((s.height, s.width), -9.0, device="cuda")
+        dare.dare_reslice(v, s, o)
+        alone.append(o)
+    torch.cuda.synchronize()
+    for k in range(len(reqs)):
+        got = outs[k].cpu().numpy()
+        assert np.array_equal(got, alone[k].cpu().numpy(), equal_nan=True), k
+        assert not (got == -7.0).any(), k
 
 
 def test_empty_volume_reslices_to_nan(dare, torch_cuda, cfg1):
