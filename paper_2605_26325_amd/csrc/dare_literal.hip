@@ -373,6 +373,7 @@ __global__ void __launch_bounds__(256) k_lit_reslice_tiled(SampleDev d, LitSlice
         const int k = tid + 256 * q;
         if (k < (int)nbox && mark[k]) {
             double sw = 0.0, swi = 0.0;
+#pragma unroll 4
             for (uint32_t e = o0[q]; e < o1[q]; ++e) {
                 const uint32_t u = d.samples[e];
                 const double w = (double)lut[u >> 8];
