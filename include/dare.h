@@ -250,7 +250,12 @@ dare_status dare_volume_upload_sums(dare_volume* v, const double* rep_n_host, co
  *   load:       creates the volume in [arena_dev, arena_dev + arena_bytes)
  *               on the current device (as dare_volume_create) and fills it;
  *               INVALID_ARG for a damaged or foreign buffer, BUDGET if the
- *               arena cannot hold the saved bricks.  Synchronous. */
+ *               arena cannot hold the saved bricks.  Synchronous.  The brick
+ *               table is checked on the host before anything is uploaded:
+ *               every entry -1 or a slot below the saved slot count, each such
+ *               slot owned by exactly one entry, no entry in the rows of bins
+ *               beyond the codebook, finite representatives; a table that
+ *               breaks any of these is INVALID_ARG (no device call made). */
 uint64_t dare_volume_save_bytes(const dare_volume* v);
 dare_status dare_volume_save(const dare_volume* v, void* host_out, uint64_t bytes);
 dare_status dare_volume_load(const void* host_in, uint64_t bytes, void* arena_dev, uint64_t arena_bytes,

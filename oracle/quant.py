@@ -108,6 +108,27 @@ def fp8_scales(S, C, brick: int = 8):
     return s_val, s_cnt
 
 
+def fp8_encode(S, C, brick: int = 8):
+    """Codes and scales of the fp8 form: (q_value, q_count, s_value, s_count).
+
+    q_value, q_count: float64 arrays of e4m3 values, 0 where C == 0;
+    s_value, s_count: per (bin, brick) float32 scales from ``fp8_scales``.
+    The voxel of a brick farthest from 127.5 encodes to +-448, and so does
+    the brick's largest count.
+    """
+    S = np.asarray(S)
+    C = np.asarray(C)
+    has = C > 0
+    a32 = mean32(S, C)
+    s_val, s_cnt = fp8_scales(S, C, brick)
+    sv = brick_expand(s_val, S.shape, brick)
+    sc = brick_expand(s_cnt, S.shape, brick)
+    x = ((a32 - F32(127.5)).astype(np.float32) / sv).astype(np.float32)
+    qv = np.where(has, rne(x, "e4m3"), 0.0)
+    qc = np.where(has, rne((_f32(C) / sc).astype(np.float32), "e4m3"), 0.0)
+    return qv, qc, s_val, s_cnt
+
+
 def storage(S, C, form: str, brick: int = 8):
     """Dequantised (a', c') float32 arrays exactly as a reader of ``form`` sees them."""
     S = np.asarray(S)
@@ -123,14 +144,11 @@ def storage(S, C, form: str, brick: int = 8):
         cc = np.minimum(C32, F32(65504.0)) if form == "fp16" else C32
         c = rne(cc, fmt).astype(np.float32)
     elif form == "fp8":
-        s_val, s_cnt = fp8_scales(S, C, brick)
+        qv, qc, s_val, s_cnt = fp8_encode(S, C, brick)
         sv = brick_expand(s_val, S.shape, brick)
         sc = brick_expand(s_cnt, S.shape, brick)
-        x = ((a32 - F32(127.5)).astype(np.float32) / sv).astype(np.float32)
-        q = rne(x, "e4m3").astype(np.float32)
-        a = ((q * sv).astype(np.float32) + F32(127.5)).astype(np.float32)
-        qc = rne((C32 / sc).astype(np.float32), "e4m3").astype(np.float32)
-        c = (qc * sc).astype(np.float32)
+        a = ((qv.astype(np.float32) * sv).astype(np.float32) + F32(127.5)).astype(np.float32)
+        c = (qc.astype(np.float32) * sc).astype(np.float32)
     else:
         raise ValueError(form)
     a = np.where(has, a, F32(0.0)).astype(np.float32)

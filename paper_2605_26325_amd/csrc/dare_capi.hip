@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -855,6 +856,28 @@ uint64_t saved_total(const SavedHeader& h) {
     return sizeof(SavedHeader) + h.table_bytes + h.acc_bytes + h.data_bytes + h.scales_bytes;
 }
 
+// A saved brick table is used as gather and atomic addresses on the device, so it is checked in
+// full before anything is uploaded: every entry -1 or a slot below `used`, each slot owned by
+// exactly one entry (the pool is compact), no entry in the rows of bins >= K, and finite
+// representatives for the bins in use.
+bool saved_table_ok(const SavedHeader& h, const int32_t* table) {
+    const uint64_t n = h.table_bytes / sizeof(int32_t);
+    const uint64_t nbricks = n / (uint64_t)h.p.max_bins;
+    std::vector<uint8_t> owned(h.used, 0);
+    for (uint64_t k = 0; k < n; ++k) {
+        const int32_t e = table[k];
+        if (e == -1) continue;
+        if (e < 0 || (uint32_t)e >= h.used || (int64_t)(k / nbricks) >= h.K || owned[e]) return false;
+        owned[e] = 1;
+    }
+    for (uint32_t s = 0; s < h.used; ++s)
+        if (!owned[s]) return false;
+    for (int b = 0; b < h.K; ++b)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(h.rep_n[b][a]) || !std::isfinite(h.rep_x[b][a])) return false;
+    return true;
+}
+
 }  // namespace
 
 uint64_t dare_volume_save_bytes(const dare_volume* v) {
@@ -916,6 +939,9 @@ dare_status dare_volume_load(const void* host_in, uint64_t bytes, void* arena_de
     saved_sizes(&h.g, &h.p, h.dtype, h.used, &sz);
     if (sz.table_bytes != h.table_bytes || sz.acc_bytes != h.acc_bytes || sz.data_bytes != h.data_bytes ||
         sz.scales_bytes != h.scales_bytes || bytes < saved_total(h))
+        return DARE_ERR_INVALID_ARG;
+    if ((h.saturated != 0 && h.saturated != 1) ||
+        !saved_table_ok(h, (const int32_t*)((const char*)host_in + sizeof(SavedHeader))))
         return DARE_ERR_INVALID_ARG;
     dare_volume* v = nullptr;
     dare_status st = dare_volume_create(&h.g, &h.p, (dare_dtype)h.dtype, arena_dev, arena_bytes, &v);

@@ -13,7 +13,7 @@
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -34,7 +34,6 @@ class Workload:
     sweep: Sweep
     slices: SliceSet
     frame_seed: int
-    params: dict = field(default_factory=dict)
     frames: object = None         # torch uint8 (F,H,W), filled by ``render``
     fan: dict = None              # fan probes: apex (a0, a1), r0, dr, sectors, width, height
     beams: np.ndarray = None      # fan probes: (width, 2) unit beam direction per column
@@ -54,8 +53,6 @@ class Workload:
         return self.frames
 
 
-DEFAULT_PARAMS = dict(k_normal=10.0, k_inplane=5.0, thr_normal_deg=25.0, thr_inplane_deg=15.0,
-                      radius_vox=1.0, bin_tol_deg=3.0, max_bins=64, normal_axis=2)
 
 
 def config1(n_slices: int = 16, n_near: int = 12) -> Workload:
@@ -65,7 +62,7 @@ def config1(n_slices: int = 16, n_near: int = 12) -> Workload:
     sw = linear_tilted_sweeps(N, h, 100, w, w, pitch, (20.0, -20.0), C)
     sl = slice_poses(101, sw, n_slices, n_near, 128, 128, (0.25, 0.25), N, h, C)
     return Workload("config1: 64^3 @0.5mm, 2x100 frames 128^2, 16 slices 128^2", (N, N, N), h,
-                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=1, params=dict(DEFAULT_PARAMS))
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=1)
 
 
 def fan_beams(width: int, step_deg: float) -> np.ndarray:
@@ -86,7 +83,7 @@ def fan_config(sectors: int = 8, n_slices: int = 16, n_near: int = 12) -> Worklo
     sl = slice_poses(101, sw, n_slices, n_near, 128, 128, (0.25, 0.25), N, h, C)
     fan = dict(apex=((w - 1) * pitch[0] / 2.0, -6.0), r0=8.0, dr=0.2, sectors=int(sectors), width=96, height=128)
     return Workload(f"fan: 64^3 @0.5mm, 2x100 curvilinear frames 96x128, {sectors} sectors", (N, N, N), h,
-                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=11, params=dict(DEFAULT_PARAMS), fan=fan,
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=11, fan=fan,
                     beams=fan_beams(96, 0.5))
 
 
@@ -101,7 +98,7 @@ def fan_config2(sectors: int = 8, n_slices: int = 100, n_near: int = 80) -> Work
     sl = slice_poses(203, sw, n_slices, n_near, 512, 512, (0.0625, 0.0625), N, h, C)
     fan = dict(apex=((w - 1) * pitch[0] / 2.0, -3.0), r0=4.0, dr=0.1, sectors=int(sectors), width=192, height=256)
     return Workload(f"fan config2: 256^3 @0.125mm, 3x600 curvilinear frames 192x256, {sectors} sectors", (N, N, N),
-                    h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=12, params=dict(DEFAULT_PARAMS), fan=fan,
+                    h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=12, fan=fan,
                     beams=fan_beams(192, 0.25))
 
 
@@ -112,7 +109,7 @@ def config2(n_slices: int = 1000, n_near: int = 800) -> Workload:
     sw = azimuth_sweeps(N, h, 600, w, w, pitch, (0.0, 120.0, 240.0), 1.0, 2.0, seed=202, calib=C)
     sl = slice_poses(203, sw, n_slices, n_near, 512, 512, (0.0625, 0.0625), N, h, C)
     return Workload("config2: 256^3 @0.125mm, 3x600 frames 256^2, 1000 slices 512^2", (N, N, N), h,
-                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=2, params=dict(DEFAULT_PARAMS))
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=2)
 
 
 def config3_slices(wl1: Workload, n_slices: int = 1000, n_near: int = 800) -> SliceSet:
@@ -130,7 +127,7 @@ def serving_volume(N: int, seed: int, n_frames: int = 600, n_slices: int = 64) -
     sl = slice_poses(seed * 100 + 2, sw, n_slices, int(0.8 * n_slices), 512, 512,
                      (N * h / 512, N * h / 512), N, h, C)
     return Workload(f"serving volume {N}^3 @0.125mm", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph,
-                    sw, sl, frame_seed=seed, params=dict(DEFAULT_PARAMS))
+                    sw, sl, frame_seed=seed)
 
 
 def config5(seconds: float = 6.0, rate_hz: float = 30.0, N: int = 512) -> Workload:
@@ -143,7 +140,7 @@ def config5(seconds: float = 6.0, rate_hz: float = 30.0, N: int = 512) -> Worklo
     sw = random_walk_sweep(N, h, int(round(seconds * rate_hz)), w, w, pitch, rate_hz, seed=501, calib=C)
     sl = slice_poses(502, sw, 64, 51, 512, 512, pitch, N, h, C)
     return Workload(f"config5: {N}^3 @0.125mm streamed from {w}^2 frames at {rate_hz:g} Hz", (N, N, N), h,
-                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=5, params=dict(DEFAULT_PARAMS))
+                    WORLD_OFFSET_MM.copy(), C, ph, sw, sl, frame_seed=5)
 
 
 def tiny_workload(seed: int, N: int = 8, n_frames: int = 6, w: int = 6, n_slices: int = 4,
@@ -160,4 +157,4 @@ def tiny_workload(seed: int, N: int = 8, n_frames: int = 6, w: int = 6, n_slices
     sl = slice_poses(seed * 7 + 5, sw, n_slices, max(1, n_slices - 1), slice_w, slice_h,
                      (N * h / slice_w, N * h / slice_h), N, h, C, max_rot_deg=20.0)
     return Workload(f"tiny {N}^3 seed {seed}", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl,
-                    frame_seed=seed, params=dict(DEFAULT_PARAMS))
+                    frame_seed=seed)

@@ -10,6 +10,7 @@ per-sample formulation.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,7 +18,7 @@ import scipy.ndimage as ndi
 import torch
 
 import synth
-from helpers import (pose_from_axes, random_grid, random_reps, read_golden_rows, rodrigues,
+from helpers import (GOLDEN, pose_from_axes, random_grid, random_reps, read_golden_rows, rodrigues,
                      random_unit)
 from oracle import bins, compound, geometry, literal, quant, reslice
 from oracle.reslice import Params
@@ -536,6 +537,122 @@ def test_storage_forms_error_bounds():
     a16, c16 = quant.storage(S, Cn, "fp16")
     small = has & (Cn <= 256)
     np.testing.assert_array_equal(c16[small], Cn[small])
+
+
+# FP8 storage form: codes and per-(bin, brick) scales, pinned independently of the oracle's
+# own scale computation (hand-worked brick, and properties of the construction).
+
+def _fp8_golden():
+    rows = read_golden_rows("fp8_brick.txt")
+    scales = {}
+    with open(os.path.join(GOLDEN, "fp8_brick.txt")) as fh:
+        for line in fh:
+            if line.startswith("#S"):
+                b, sv, sc = line.split()[1:]
+                scales[int(b)] = (float(sv), float(sc))
+    return rows, scales
+
+
+def _fp8_pin_failures(encode):
+    """Names of the fp8 pins that ``encode(S, C) -> (qv, qc, s_val, s_cnt)`` breaks."""
+    bad = []
+    rows, scales = _fp8_golden()
+    S = np.zeros((2, 8, 8, 8), np.int64)
+    C = np.zeros_like(S)
+    for b, x, y, z, s_, c_, _, _ in rows:
+        S[int(b), int(z), int(y), int(x)] = int(s_)
+        C[int(b), int(z), int(y), int(x)] = int(c_)
+    qv, qc, sv, sc = encode(S, C)
+    for b, x, y, z, _, _, q_val, q_cnt in rows:
+        at = (int(b), int(z), int(y), int(x))
+        if qv[at] != q_val or qc[at] != q_cnt:
+            bad.append("hand-worked codes")
+            break
+    for b, (s_val, s_cnt) in scales.items():
+        if abs(float(sv[b, 0, 0, 0]) / s_val - 1) > 1e-7 or abs(float(sc[b, 0, 0, 0]) / s_cnt - 1) > 1e-7:
+            bad.append("hand-worked scales")
+            break
+    # random grids whose values stay near mid-grey (so an empty voxel, read as 0, would be the
+    # farthest from 127.5) and whose counts vary per brick
+    rng = np.random.default_rng(81)
+    K, n = 3, 24
+    C = rng.integers(1, 40, size=(K, n, n, n)) * (rng.random((K, n, n, n)) > 0.4)
+    C[:, :8, :8, :8] = 0                        # whole empty bricks
+    a = rng.uniform(100.0, 160.0, C.shape)
+    S = np.where(C > 0, np.floor(a * C), 0).astype(np.int64)
+    qv, qc, sv, sc = encode(S, C)
+    has = C > 0
+    if np.any(qv[~has] != 0) or np.any(qc[~has] != 0):
+        bad.append("empty voxels encode to 0")
+    for b in range(K):
+        for bz in range(0, n, 8):
+            for by in range(0, n, 8):
+                for bx in range(0, n, 8):
+                    sl = (b, slice(bz, bz + 8), slice(by, by + 8), slice(bx, bx + 8))
+                    occ = has[sl]
+                    if not occ.any():
+                        continue
+                    # brute force, from the voxels' own means
+                    amean = np.float32(S[sl][occ]) / np.float32(C[sl][occ])
+                    dev = np.abs(amean.astype(np.float64) - 127.5)
+                    if dev.max() > 1e-3 and np.abs(qv[sl][occ]).max() != 448.0:
+                        bad.append("farthest voxel encodes to 448")
+                        return bad
+                    if qc[sl][occ].max() != 448.0 or qc[sl][occ][np.argmax(C[sl][occ])] != 448.0:
+                        bad.append("largest count encodes to 448")
+                        return bad
+                    if np.any(qc[sl][occ] <= 0) or np.any(np.abs(qv[sl][occ]) > 448):
+                        bad.append("code range")
+                        return bad
+                    # 3 mantissa bits: relative half-quantum 2^-4 of the value's distance from 127.5
+                    dec = qv[sl][occ] * float(sv[b, bz // 8, by // 8, bx // 8]) + 127.5
+                    err = np.abs(dec - amean)
+                    if np.any(err > dev * 2.0 ** -4 + 1e-4):
+                        bad.append("value error within e4m3 precision")
+                        return bad
+    return bad
+
+
+def _fp8_mutant(value_div=448.0, scale_over_empty=False, count_div=448.0):
+    """The fp8 encoding with one planted mistake (used only to show that the pins catch it)."""
+    def enc(S, C):
+        has = np.asarray(C) > 0
+        a32 = quant.mean32(S, C)
+        dev = np.abs((a32 - np.float32(127.5)).astype(np.float32)).astype(np.float64)
+        if not scale_over_empty:
+            dev = np.where(has, dev, -np.inf)
+        m = quant.brick_reduce_max(dev)
+        m = np.where(np.isfinite(m), m, 0.0).astype(np.float32)
+        s_val = np.maximum((m / np.float32(value_div)).astype(np.float32), np.float32(2.0 ** -20))
+        cm = quant.brick_reduce_max(np.where(has, np.asarray(C, np.float64), -np.inf))
+        cm = np.where(np.isfinite(cm), cm, 448.0).astype(np.float32)
+        s_cnt = (cm / np.float32(count_div)).astype(np.float32)
+        sv = quant.brick_expand(s_val, S.shape)
+        sc = quant.brick_expand(s_cnt, S.shape)
+        x = ((a32 - np.float32(127.5)).astype(np.float32) / sv).astype(np.float32)
+        qv = np.where(has, quant.rne(x, "e4m3"), 0.0)
+        qc = np.where(has, quant.rne((np.asarray(C, np.float32) / sc).astype(np.float32), "e4m3"), 0.0)
+        return qv, qc, s_val, s_cnt
+    return enc
+
+
+def test_fp8_codes_and_scales_pinned():
+    assert _fp8_pin_failures(quant.fp8_encode) == []
+    # the same construction written again with no mistake passes, each planted mistake fails
+    assert _fp8_pin_failures(_fp8_mutant()) == []
+    for kw in ({"value_div": 224.0}, {"scale_over_empty": True}, {"count_div": 224.0}, {"count_div": 512.0}):
+        assert _fp8_pin_failures(_fp8_mutant(**kw)), kw
+
+
+def test_fp8_storage_decodes_the_codes():
+    rng = np.random.default_rng(82)
+    S, Cn = random_grid(rng, 2, (16, 16, 16), p_empty=0.3, max_count=60)
+    qv, qc, sv, sc = quant.fp8_encode(S, Cn)
+    a, c = quant.storage(S, Cn, "fp8")
+    has = Cn > 0
+    svx, scx = quant.brick_expand(sv, S.shape), quant.brick_expand(sc, S.shape)
+    np.testing.assert_array_equal(a[has], ((qv * svx).astype(np.float32) + np.float32(127.5))[has])
+    np.testing.assert_array_equal(c[has], (qc * scx).astype(np.float32)[has])
 
 
 # ---------------------------------------------------------------- evaluation metrics (Sec. 3)
