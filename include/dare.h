@@ -174,11 +174,13 @@ dare_status dare_reconstruct_fan(dare_volume* v, const uint8_t* frames_dev, int3
                                  const dare_fan* fan, const double* beams_dev, const float* probe_poses_dev,
                                  void* stream);
 
-/* Reslice one plane (Sec. 2.1 "Reslicing", Eq. 1, Eq. 2): for each output
- * pixel, the FP64 sample position, its neighbourhood |c - v|_inf < R with
- * tent weights prod(1 - |c_a - v_a| / R), per-voxel direction blending with
- * the angular weight of each bin that passes both thresholds, then the
- * distance-weighted average over valid voxels.
+/* Reslice one plane (Sec. 2.1 "Reslicing", Eq. 1, Eq. 2): the slice pose
+ * composed with the calibration in FP64 on the device, Eq. 1 for every bin of
+ * the codebook, both angular thresholds and Eq. 2 for the survivors (FP64 on
+ * the device); then for each output pixel the FP64 sample position, its
+ * neighbourhood |c - v|_inf < R with tent weights prod(1 - |c_a - v_a| / R),
+ * per-voxel direction blending with the angular weight of each surviving bin,
+ * and the distance-weighted average over valid voxels.
  *   out_dev   height * width float32, row-major; NaN marks an unassigned pixel.
  * Enqueues a single kernel; allocates nothing.  Errors: INVALID_ARG,
  * BAD_POSE (slice pose not rigid), HIP. */
@@ -293,7 +295,8 @@ dare_status dare_volume_held(const dare_volume* v, int64_t* bricks, uint64_t* by
 
 /* The direction bins that survive both thresholds for this slice pose and
  * their Eq. 2 weights (Sec. 2.1, Eq. 1 and Eq. 2), evaluated on the host in
- * FP64 from the volume's codebook.  bins_out / weights_out (may be NULL)
+ * FP64 from the volume's codebook: a query for callers (and for counting a
+ * slice's compulsory bytes); the reslices evaluate the same on the device.  bins_out / weights_out (may be NULL)
  * receive up to 64 entries; *count the number.  Synchronises the device.
  * Errors: INVALID_ARG, BAD_POSE, HIP. */
 dare_status dare_slice_active_bins(const dare_volume* v, const dare_slice_spec* spec, int32_t* bins_out,
@@ -380,19 +383,20 @@ dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of reslice requests from many consoles (the
  * expert consoles of Sec. 1 each reslice the shared volume at their own
- * pose).  A server owns a caller-supplied device arena (its HBM budget: one
- * request table per stream, result slots and, at radius 1, the per-request
- * slabs of blended voxels, which are taken only where room is left: a request
- * without one gathers per pixel, with the same result), up to `n_streams` (1..4) HIP
- * streams of default priority, and a host thread that groups waiting
- * requests into ticks.  A request is admitted, first come first served, when
- * a result slot of its size can be allocated in the arena; each tick uploads
- * its request table, replays a captured graph of the batched reslice on a
- * free stream (ticks on different streams overlap on the device), then
- * copies every result into its `host_out` buffer (pinned host memory keeps
- * the copy asynchronous).  All volumes of one server share one storage dtype
- * and radius.  Volumes must not be reconstructed while the server can
- * reslice them.
+ * pose).  A server owns a caller-supplied device arena (the HBM budget of its
+ * results: one workspace per stream, laid out when the first volume is added,
+ * and the result slots), up to `n_streams` (1..4) HIP streams of default
+ * priority, and a host thread that groups waiting requests into ticks.  A
+ * request is admitted, first come first served, when a result slot of its
+ * size can be allocated in the arena; each tick uploads its request table,
+ * replays a captured graph of the batched reslice on a free stream (ticks on
+ * different streams overlap on the device), then copies every result into its
+ * `host_out` buffer (pinned host memory keeps the copy asynchronous).
+ * Volumes are admitted against a second budget, `volume_budget_bytes`: the
+ * device bytes of the resident volumes' arenas (Sec. 4 names dataset size
+ * against GPU memory as the limit to plan for); a removed volume returns its
+ * bytes.  All volumes of one server share one storage dtype and radius.
+ * Volumes must not be reconstructed while the server can reslice them.
  * ------------------------------------------------------------------------ */
 typedef struct dare_server dare_server;
 
@@ -402,6 +406,7 @@ typedef struct {
     int32_t n_streams;        /* 1..4                                                        */
     int32_t max_queue;        /* waiting requests before submit returns QUEUE_FULL          */
     int32_t use_graphs;       /* 1: replay captured graphs per tick; 0: plain launches       */
+    uint64_t volume_budget_bytes; /* device bytes of resident volumes' arenas; 0 = no limit   */
 } dare_server_config;
 
 typedef struct {
@@ -417,15 +422,28 @@ typedef struct {
     double t_submit, t_admit, t_launch, t_device_done, t_host_done; /* seconds, steady clock */
 } dare_request_times;
 
-/* Defaults: 8 Mpixel and 64 requests per tick, 3 streams, 4096 queued, graphs on. */
+/* Defaults: 8 Mpixel and 64 requests per tick, 3 streams, 4096 queued, graphs on, no volume
+ * budget. */
 void dare_default_server_config(dare_server_config* c);
-/* arena_dev: 256-byte aligned device memory, kept allocated until destroy. */
+/* arena_dev: 256-byte aligned device memory of at least 512 bytes, kept allocated until
+ * destroy. */
 dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, uint64_t arena_bytes,
                                dare_server** out);
-/* Register a volume; INVALID_ARG if its dtype or radius differs from the first one's.  The
- * server may compound frames into it (dare_server_submit_frames); outside the server the
- * volume must not be reconstructed while the server can reslice it. */
+/* Register a volume (it stays owned by the caller).  INVALID_ARG if its dtype or radius
+ * differs from the first one's, if it lives on another device or is registered already;
+ * BUDGET if its arena's bytes would take the resident volumes beyond volume_budget_bytes (the
+ * server is unchanged); BUDGET or HIP if the first volume's workspaces cannot be laid out in
+ * the arena.  The server may compound frames into it (dare_server_submit_frames); outside the
+ * server the volume must not be reconstructed while the server can reslice it. */
 dare_status dare_server_add_volume(dare_server* s, dare_volume* v, int32_t* volume_id);
+/* Unregister a volume and return its bytes to the volume budget.  New requests for it are
+ * refused (INVALID_ARG) from the call on; requests and frames jobs already queued still run.
+ * The call waits up to wait_seconds for them to complete; if some are still pending then, it
+ * returns NOT_READY and the volume stays registered.  INVALID_ARG for an unknown or removed id.
+ * Ids are never reused; after OK the caller may destroy the volume. */
+dare_status dare_server_remove_volume(dare_server* s, int32_t volume_id, double wait_seconds);
+/* Device bytes and number of the volumes currently registered. */
+dare_status dare_server_volume_bytes(dare_server* s, uint64_t* resident_bytes, int32_t* resident_volumes);
 /* Queue a request.  host_out (required) receives height*width float32,
  * row-major, NaN where unassigned, once the request completes.  Returns
  * QUEUE_FULL when max_queue requests wait, and INVALID_ARG when the request

@@ -55,7 +55,7 @@ class Fan(ct.Structure):
 
 class ServerConfig(ct.Structure):
     _fields_ = [("max_tick_pixels", ct.c_int64), ("max_tick_requests", ct.c_int32), ("n_streams", ct.c_int32),
-                ("max_queue", ct.c_int32), ("use_graphs", ct.c_int32)]
+                ("max_queue", ct.c_int32), ("use_graphs", ct.c_int32), ("volume_budget_bytes", ct.c_uint64)]
 
 
 class ServerStats(ct.Structure):
@@ -124,6 +124,8 @@ def _load():
         "dare_default_server_config": (None, [ct.POINTER(ServerConfig)]),
         "dare_server_create": (ct.c_int, [ct.POINTER(ServerConfig), P, U64, ct.POINTER(V)]),
         "dare_server_add_volume": (ct.c_int, [V, V, ct.POINTER(I32)]),
+        "dare_server_remove_volume": (ct.c_int, [V, I32, D]),
+        "dare_server_volume_bytes": (ct.c_int, [V, ct.POINTER(U64), ct.POINTER(I32)]),
         "dare_server_submit": (ct.c_int, [V, I32, ct.POINTER(SliceSpec), P, ct.POINTER(U64)]),
         "dare_server_poll": (ct.c_int, [V, U64, ct.POINTER(RequestTimes)]),
         "dare_server_submit_many": (ct.c_int, [V, I32, P, P, P, P, ct.POINTER(I32)]),
@@ -507,8 +509,9 @@ def default_server_config(**over) -> ServerConfig:
 class Server:
     """Continuous-batching reslice server (C++ scheduler thread inside the library).
 
-    ``arena_bytes`` of device memory hold one request table per stream and the
-    result slots; requests wait in FIFO order until a slot of their size fits."""
+    ``arena_bytes`` of device memory hold one workspace per stream and the
+    result slots; requests wait in FIFO order until a slot of their size fits.
+    Volumes are admitted against ``volume_budget_bytes`` (0: no limit)."""
 
     def __init__(self, arena_bytes: int, device="cuda", **cfg):
         import torch
@@ -525,6 +528,17 @@ class Server:
         _check(lib.dare_server_add_volume(self.handle, vol.handle, ct.byref(vid)), "dare_server_add_volume")
         self._volumes.append(vol)
         return vid.value
+
+    def remove_volume(self, volume_id: int, wait_seconds: float = 60.0):
+        """Unregister a volume once its queued requests have completed (dare_server_remove_volume)."""
+        _check(lib.dare_server_remove_volume(self.handle, int(volume_id), float(wait_seconds)),
+               "dare_server_remove_volume")
+
+    def volume_bytes(self):
+        """(resident volume bytes, resident volumes)."""
+        b, n = ct.c_uint64(), ct.c_int32()
+        _check(lib.dare_server_volume_bytes(self.handle, ct.byref(b), ct.byref(n)), "dare_server_volume_bytes")
+        return int(b.value), int(n.value)
 
     def submit(self, volume_id: int, probe_pose, width, height, pitch, host_out):
         """Queue a request; returns its ticket, or None when the queue is full."""

@@ -1,73 +1,74 @@
-// Batched reslice: request table, device setup records and their flat index spaces, shared by
-// the batch kernels and the host planners (the C ABI's batch call and the server).
+// Batched reslice: request table, device setup records and work units, shared by the batch
+// kernels and the host planners (the C ABI's batch call and the server).
 #pragma once
 
 #include "dare_internal.h"
 
 namespace dare {
 
+// One request as the host uploads it: the volume's device header and the slice.
 struct BatchReq {
     const VolDev* vol;
     SliceArgs s;
-    SliceCore core;                       // radius 1: the per-slice setup, computed on the host
-    // Radius-1 passes run over two flat index spaces: the requests' slabs back to back
-    // (v_beg: first index of this request's slab) and their pixels (p_beg), each request's
-    // range padded to whole blocks of kFlatBlock.  The slab itself lives at float offset v_off
-    // of the scratch; v_cap floats (a multiple of kFlatBlock), 0 for none.
-    int64_t v_beg, v_off, v_cap;
-    int64_t p_beg;
 };
 
-// Batch header at the start of a workspace: int32 {units, requests, 0, 0}, then int64
-// {slab index total, pixel index total}, both multiples of kFlatBlock.  counts[2] must be uploaded
-// as 0: the setup pass counts there the requests that gather per pixel.
+// Batch header at the start of a workspace: int32 {units, requests, units at the list's back,
+// 0}.  At radius 1 the units are appended on the device, so counts[0] and counts[2] must be
+// uploaded as 0; at other radii the host uploads the unit list and its length in counts[0].
 struct BatchHeader {
     int32_t counts[4];
-    int64_t totals[2];
 };
 
-constexpr int kFlatShift = 10;            // batched passes: elements per workgroup iteration ...
-constexpr int kFlatBlock = 1 << kFlatShift;   // ... (4 per thread)
-constexpr int kBatchMaxReq = 4096;        // requests per launch group (LDS request tables of the passes)
-constexpr int kSlabDepthMax = 10;         // deepest slab run (a plane tilted 45 deg in both axes needs 9)
-constexpr int kSlabTileP = 8;             // slab column tile: 8 along p (a brick row when p is x) ...
-constexpr int kSlabTileQ = 4;             // ... by 4 along q
-constexpr int kSlabPerPixel = 12;         // slab floats per output pixel beyond which pixels gather directly
+constexpr int kBatchMaxReq = 4096;        // requests per launch group (grid of the setup pass)
 
-// Per-request setup record written by the batch setup pass.
-struct SliceSetup : SliceCore {
-    // slab of the whole slice: voxels within the trilinear support of the slice
-    // plane, enumerated as runs of `depth` voxels along the dominant axis, one run per column
-    // of the other two axes (pax fastest) over the slice's bounding box
-    int pax, qax;
-    int lo_p, lo_q, dim_p, dim_q;
-    int depth;
-    int ntp;                              // column tiles along p
-    int ncand;                            // tiles * depth * tile columns, 0 when nothing to stage
-    int staged;                           // 1: slab staged; 0: gather per pixel
-    float c0[3];                          // voxel coordinates of pixel (0, 0)
-    float thr_n, thr_u, thr_v, len_u, len_v, inv_md, half;
-    // copies of the request and its volume (batched passes)
-    int64_t act_off[kMaxBins];            // act_bin[k] * bricks per bin: table offset of bin k
-    double inv_depth, inv_ntp;            // FP64 reciprocals for exact index division
+// Per-request record of a radius-1 reslice, written on the device by the request setup (FP64
+// pose, Eq. 1 gates and Eq. 2 weights in the SliceCore part).
+struct SliceRec : SliceCore {
+    double c00[3], ex[3], ey[3];          // voxel coordinates of pixel (i, j): c00 + i ex + j ey
     VolView vol;
-    double sx, sy;
-    int32_t W, H;
     float* out;
-    int64_t v_off;
+    int32_t W, H;
+    int32_t mode;                         // 0: every pixel NaN, 1: staged tiles, 2: per-pixel gather
+    int32_t tile;                         // tile edge in pixels (16 unless staged in 32 x 32 tiles)
+    int32_t tiles_x, ntiles;
+    float half, slop;                     // slab half-depth along the dominant axis; FP32 test slop
+    int32_t depth;                        // voxels per slab run
+    int32_t pad;
 };
 
-// nreq_max bounds the requests of any batch launched with these arguments (the count itself is
-// read from `counts` on the device, so a captured graph can be replayed with fewer).
-hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceSetup* setups, const int2* units,
-                                const int* counts, float* scratch, int nreq_max, int grid, hipStream_t stream);
-// Slab floats to reserve for a radius-1 request (0 when its pixels should gather directly):
-// the slice's voxel bounding box, two voxels of margin, padded to whole column tiles, over
-// the largest pair of axes, times the deepest run, capped at kSlabPerPixel per pixel.
-// Defined with the C ABI.
-int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec);
-// The per-slice setup of a radius-1 reslice (pose, surviving bins and weights, plane frame),
-// computed on the host from its copy of the volume's codebook.  Defined with the C ABI.
-void host_core(const dare_volume* v, const dare_slice_spec* spec, SliceCore* core);
+// Per-tile record of a staged radius-1 request, written by the batch setup pass (one lane per
+// tile): the tile's pixels, its voxel box and run geometry, and the divisions the staging phases
+// need (multiplier m and divisor d of an exact small-integer division).
+struct TileRec {
+    int32_t r;                            // request
+    int32_t mode;                         // 0: every pixel NaN, 1: staged
+    int32_t i0, j0, ni, nj;               // first pixel and pixel counts
+    int32_t lo[3], hi[3];                 // voxel box, clipped to [-1, n]
+    int32_t bp, bq, ncols, depth;         // box columns along p and q, their number, run depth
+    int32_t blo[3], bdim[3], nbb, kactp;  // in-grid bricks of the box; bins per slot row
+    uint32_t m_bp, m_kactp, m_bdx, m_bdy; // division multipliers for bp, kactp, bdim[0], bdim[1]
+    float c0[3];                          // voxel coordinates of the tile's first pixel
+    float thr_n, thr_u, thr_v, hi_u, hi_v, inv_md, half;
+};
+
+// Radius 1, one request: one workgroup per 16 x 16 tile, each evaluating the request setup.
+hipError_t launch_reslice_tile(const VolDev* vd, int dtype, const SliceArgs& s, hipStream_t stream);
+// Radius 1, a batch: setup pass (one wave per request: the request record, then one tile record
+// per lane) + persistent tile kernel + the per-pixel kernel for requests too coarse to stage.
+// `counts[0]` and `counts[2]` must hold 0 and `counts[1]` the number of requests when the stream
+// reaches the launch; `units` and `tiles` hold `cap` entries, at least tile_units_max() per
+// request in all.
+hipError_t launch_tiles_batch(int dtype, const BatchReq* reqs, SliceRec* recs, int2* units, TileRec* tiles,
+                              int* counts, int nreq_max, int cap, hipStream_t stream);
+// Largest number of units of a W x H radius-1 request (16 x 16 tiles).
+int64_t tile_units_max(int W, int H);
+
+// Any radius: radius 1 runs the setup pass and the tile kernels over device-built units and tile
+// records (`cap` entries of `units` and `tiles`; grids sized to the device, `grid` unused); other
+// radii run the host-built (request, unit) table (`counts[0]` units) over `grid` workgroups.  nreq_max bounds the
+// requests of any batch launched with these arguments (the counts are read on the device, so a
+// captured graph can be replayed with fewer).
+hipError_t launch_reslice_batch(int dtype, int radius, const BatchReq* reqs, SliceRec* recs, int2* units,
+                                TileRec* tiles, int* counts, int nreq_max, int cap, int grid, hipStream_t stream);
 
 }  // namespace dare

@@ -116,8 +116,8 @@ Layout layout(const dare_geometry* g, const dare_params* p, int dtype, uint64_t 
     return L;
 }
 
-// Device header at a sync point: the state, and the codebook the host keeps a copy of (the
-// per-slice setup is computed on the host from it).
+// Device header at a sync point: the state, and the codebook the host keeps a copy of (for the
+// codebook and active-bin queries; reslices read the codebook on the device).
 dare_status read_state(dare_volume* v, hipStream_t stream, VolState* out) {
     HIP_TRY(hipMemcpyAsync(v->hdr_pinned, v->dev, sizeof(VolDev), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -179,45 +179,6 @@ SliceArgs make_args(const dare_slice_spec* s, float* out) {
 
 namespace dare {
 
-// The per-slice part of a radius-1 reslice, computed once per request: FP64 pose, surviving bins
-// and FP32 weights, and the FP32 plane frame (unit normal, in-plane axes and steps in voxel units,
-// dominant normal axis) that drives the footprint tests.
-void host_core(const dare_volume* v, const dare_slice_spec* spec, SliceCore* c) {
-    double T[16];
-    compose_host(spec->probe_pose, v->g.calib, T);
-    for (int k = 0; k < 12; ++k) c->T[k] = T[k];
-    int32_t bins[kMaxBins];
-    double w[kMaxBins];
-    const int n = gate_bins(v, T, bins, w);
-    c->kact = n;
-    for (int k = 0; k < kMaxBins; ++k) {
-        c->act_bin[k] = k < n ? bins[k] : 0;
-        c->act_w[k] = k < n ? (float)w[k] : 0.0f;
-    }
-    const double inv_h = v->host.inv_h;
-    float u[3], vv[3];
-    for (int a = 0; a < 3; ++a) {
-        u[a] = (float)(T[a * 4 + 0] * spec->pitch_mm[0] * inv_h);
-        vv[a] = (float)(T[a * 4 + 1] * spec->pitch_mm[1] * inv_h);
-    }
-    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const float lv = sqrtf(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
-    float nm[3] = {u[1] * vv[2] - u[2] * vv[1], u[2] * vv[0] - u[0] * vv[2], u[0] * vv[1] - u[1] * vv[0]};
-    const float rm = 1.0f / sqrtf(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
-    int dax = 0;
-    for (int a = 0; a < 3; ++a) nm[a] *= rm;
-    if (fabsf(nm[1]) > fabsf(nm[dax])) dax = 1;
-    if (fabsf(nm[2]) > fabsf(nm[dax])) dax = 2;
-    for (int a = 0; a < 3; ++a) {
-        c->fm[a] = nm[a];
-        c->fu[a] = u[a] / lu;
-        c->fw[a] = vv[a] / lv;
-    }
-    c->lu = lu;
-    c->lw = lv;
-    c->dax = dax;
-}
-
 }  // namespace dare
 
 namespace dare {
@@ -225,6 +186,7 @@ const VolDev* volume_device(const dare_volume* v) { return v->dev; }
 int volume_dtype(const dare_volume* v) { return v->dtype; }
 int volume_radius(const dare_volume* v) { return (int)v->p.radius_vox; }
 int volume_device_id(const dare_volume* v) { return v->device; }
+uint64_t volume_arena_size(const dare_volume* v) { return v->arena_bytes; }
 dare_status check_slice_spec(const dare_slice_spec* s) { return check_spec(s); }
 bool rigid_pose(const double* M) { return rigid(M); }
 void compose_pose(const double* P, const double* C, double* T) { compose_host(P, C, T); }
@@ -236,24 +198,25 @@ namespace {
 
 struct Group {
     std::vector<BatchReq> reqs;
-    std::vector<int2> units;
-    int64_t vox = 0, pix = 0;     // flat totals (radius 1)
+    std::vector<int2> units;      // radii above 1: built here; radius 1: built on the device
+    int64_t nunits = 0;           // units (radius 1: the most the device may append)
 };
 
-// Batch workspace of one launch group: [header] [requests] [units] [setup records] [slabs].
-// Header, requests and units are uploaded; setup records and slabs are written on the device.
+// Batch workspace of one launch group: [header] [requests] [units] [tile records] [request
+// records].  The header and requests are uploaded, and the units when built on the host (radii
+// above 1, which have no records); at radius 1 units and records are written on the device.
 struct GroupLayout {
-    uint64_t o_req, o_units, o_setup, o_slab, upload, total;
+    uint64_t o_req, o_units, o_tiles, o_rec, upload, total;
 };
 
-GroupLayout group_layout(size_t nreq, size_t nunits, int64_t slab_floats_total) {
+GroupLayout group_layout(size_t nreq, size_t nunits, bool host_units) {
     GroupLayout L;
     L.o_req = align_up(sizeof(BatchHeader));
     L.o_units = L.o_req + align_up(nreq * sizeof(BatchReq));
-    L.o_setup = L.o_units + align_up(nunits * sizeof(int2));
-    L.upload = L.o_setup;
-    L.o_slab = L.o_setup + align_up(nreq * sizeof(SliceSetup));
-    L.total = L.o_slab + align_up((uint64_t)slab_floats_total * sizeof(float));
+    L.o_tiles = L.o_units + align_up(nunits * sizeof(int2));
+    L.o_rec = L.o_tiles + (host_units ? 0 : align_up(nunits * sizeof(TileRec)));
+    L.upload = host_units ? L.o_tiles : L.o_units;
+    L.total = L.o_rec + (host_units ? 0 : align_up(nreq * sizeof(SliceRec)));
     return L;
 }
 
@@ -345,7 +308,6 @@ StagingPool& staging_pool(int device) {
 
 struct GroupSize {
     size_t nreq = 0, nunits = 0;
-    int64_t slab = 0;
 };
 
 // Launch group of each request: (storage dtype, radius, piece), a piece being each run of
@@ -370,8 +332,8 @@ std::map<GroupKey, GroupSize> group_sizes(const dare_volume* const* vols, const 
         const int R = (int)vols[k]->p.radius_vox;
         GroupSize& c = cnt[keys[k]];
         c.nreq += 1;
-        if (R <= 1) c.slab += slab_floats(vols[k], specs + k);
-        else c.nunits += (size_t)batch_units(R, specs[k].width, specs[k].height);
+        c.nunits += (size_t)(R <= 1 ? tile_units_max(specs[k].width, specs[k].height)
+                                    : batch_units(R, specs[k].width, specs[k].height));
     }
     return cnt;
 }
@@ -379,36 +341,6 @@ std::map<GroupKey, GroupSize> group_sizes(const dare_volume* const* vols, const 
 }  // namespace
 
 namespace dare {
-
-int64_t slab_floats(const dare_volume* v, const dare_slice_spec* spec) {
-    double T[16];
-    compose_host(spec->probe_pose, v->g.calib, T);
-    const int W = spec->width, H = spec->height;
-    const double sx = spec->pitch_mm[0], sy = spec->pitch_mm[1], inv_h = 1.0 / v->g.spacing_mm;
-    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int k = 0; k < 4; ++k) {
-        const double is = (double)((k & 1) ? W - 1 : 0) * sx, js = (double)((k & 2) ? H - 1 : 0) * sy;
-        for (int a = 0; a < 3; ++a) {
-            const double c = (((T[a * 4 + 3] + is * T[a * 4 + 0]) + js * T[a * 4 + 1]) - v->g.origin_mm[a]) * inv_h;
-            mn[a] = std::min(mn[a], c);
-            mx[a] = std::max(mx[a], c);
-        }
-    }
-    int64_t d[3];
-    for (int a = 0; a < 3; ++a) {
-        if (!std::isfinite(mn[a]) || !std::isfinite(mx[a])) return 0;
-        const double lo = std::max(floor(mn[a]) - 2.0, 0.0);
-        const double hi = std::min(floor(mx[a]) + 3.0, (double)v->g.dims[a] - 1.0);
-        if (lo > hi) return 0;
-        d[a] = (int64_t)(hi - lo) + 1;
-    }
-    // either axis of a pair may be the tile's p (8) or q (4): pad both by 7
-    const int64_t e[3] = {d[0] + kSlabTileP - 1, d[1] + kSlabTileP - 1, d[2] + kSlabTileP - 1};
-    const int64_t cols = std::max(e[0] * e[1], std::max(e[0] * e[2], e[1] * e[2]));
-    const int64_t cap = std::min(cols * kSlabDepthMax, (int64_t)kSlabPerPixel * W * H);
-    // within a request, slab elements are indexed in 32 bits
-    return std::min((cap + kFlatBlock - 1) / kFlatBlock * kFlatBlock, (int64_t)1 << 30);
-}
 
 }  // namespace dare
 
@@ -655,27 +587,8 @@ dare_status dare_reslice(const dare_volume* v, const dare_slice_spec* spec, floa
     const SliceArgs a = make_args(spec, out_dev);
     const int R = (int)v->p.radius_vox;
     if (staged_radius(R)) return hip_status(launch_reslice_staged(v->dev, v->dtype, R, a, (hipStream_t)stream));
-    SliceCore core;
-    VolView view{};
-    if (R <= 1) {
-        host_core(v, spec, &core);
-        const VolDev& h = v->host;
-        view.table = h.table;
-        view.data = h.data;
-        view.scales = h.scales;
-        view.nbricks = h.nbricks;
-        view.n[0] = h.nx;
-        view.n[1] = h.ny;
-        view.n[2] = h.nz;
-        view.nbx = h.nbx;
-        view.nby = h.nby;
-        for (int k = 0; k < 3; ++k) view.origin[k] = h.origin[k];
-        view.inv_h = h.inv_h;
-    }
-    return hip_status(launch_reslice(v->dev, v->dtype, R, a, core, view, (hipStream_t)stream));
+    return hip_status(launch_reslice(v->dev, v->dtype, R, a, (hipStream_t)stream));
 }
-
-
 
 uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, const dare_slice_spec* specs, int32_t n) {
     if (!vols || !specs || n <= 0) return 0;
@@ -683,27 +596,37 @@ uint64_t dare_reslice_batch_workspace_bytes(const dare_volume* const* vols, cons
         if (!vols[k] || check_spec(specs + k) != DARE_OK) return 0;
     uint64_t total = 0;
     for (auto& kv : group_sizes(vols, specs, n))
-        total += group_layout(kv.second.nreq, kv.second.nunits, kv.second.slab).total;
+        total += group_layout(kv.second.nreq, kv.second.nunits, std::get<1>(kv.first) > 1).total;
     return total;
 }
 
-dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_spec* specs, float* const* outs_dev,
-                               int32_t n, void* workspace_dev, uint64_t workspace_bytes, void* stream_) {
-    if (!vols || !specs || !outs_dev || n < 0) return DARE_ERR_INVALID_ARG;
-    if (n == 0) return DARE_OK;
-    if (!workspace_dev) return DARE_ERR_INVALID_ARG;
-    int device = -1;
+}  // extern "C"
+
+namespace {
+
+// Arguments of a batch call checked, and the device they share; `needed` receives the
+// workspace bytes the batch takes.
+dare_status check_batch(const dare_volume* const* vols, const dare_slice_spec* specs, float* const* outs_dev,
+                        int32_t n, int* device, uint64_t* needed) {
+    if (!vols || !specs || !outs_dev || n <= 0) return DARE_ERR_INVALID_ARG;
+    *device = -1;
     for (int k = 0; k < n; ++k) {
         if (!vols[k] || !outs_dev[k]) return DARE_ERR_INVALID_ARG;
         const dare_status st = check_spec(specs + k);
         if (st != DARE_OK) return st;
-        if (device < 0) device = vols[k]->device;
-        if (vols[k]->device != device) return DARE_ERR_INVALID_ARG;
+        if (*device < 0) *device = vols[k]->device;
+        if (vols[k]->device != *device) return DARE_ERR_INVALID_ARG;
     }
-    if (workspace_bytes < dare_reslice_batch_workspace_bytes(vols, specs, n)) return DARE_ERR_INVALID_ARG;
-    if (((uintptr_t)workspace_dev % kAlign) != 0) return DARE_ERR_INVALID_ARG;
-    DeviceGuard dg(device);
-    hipStream_t stream = (hipStream_t)stream_;
+    *needed = dare_reslice_batch_workspace_bytes(vols, specs, n);
+    return DARE_OK;
+}
+
+// Plan every launch group of a checked batch and launch it into the device workspace `ws`:
+// `upload(dst_dev, src_host, bytes)` enqueues the copy of a group's uploaded part on `stream`
+// and returns false on failure.  Groups are laid out back to back in call order.
+template <class Upload>
+dare_status run_batch(const dare_volume* const* vols, const dare_slice_spec* specs, float* const* outs_dev,
+                      int32_t n, char* ws, hipStream_t stream, Upload&& upload) {
     std::map<GroupKey, Group> groups;
     const std::vector<GroupKey> keys = group_keys(vols, n);
     for (int k = 0; k < n; ++k) {
@@ -714,53 +637,67 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
         q.vol = vols[k]->dev;
         q.s = make_args(specs + k, outs_dev[k]);
         if (R <= 1) {
-            host_core(vols[k], specs + k, &q.core);
-            // flat ranges padded to whole blocks (slab capacities already are)
-            q.v_cap = slab_floats(vols[k], specs + k);
-            q.v_beg = g.vox;
-            q.v_off = g.vox;
-            q.p_beg = g.pix;
-            g.vox += q.v_cap;
-            g.pix += ((int64_t)specs[k].width * specs[k].height + kFlatBlock - 1) / kFlatBlock * kFlatBlock;
+            g.nunits += tile_units_max(specs[k].width, specs[k].height);
         } else {
             const int64_t u = batch_units(R, specs[k].width, specs[k].height);
             for (int64_t t = 0; t < u; ++t) g.units.push_back(make_int2(r, (int)t));
+            g.nunits += u;
         }
         g.reqs.push_back(q);
     }
-    for (auto& kv : groups)   // flat blocks are indexed in 32 bits on the device
-        if ((kv.second.vox >> kFlatShift) >= INT32_MAX || (kv.second.pix >> kFlatShift) >= INT32_MAX)
-            return DARE_ERR_INVALID_ARG;
-    char* ws = (char*)workspace_dev;
+    for (auto& kv : groups)   // units are indexed in 32 bits on the device
+        if (kv.second.nunits >= INT32_MAX) return DARE_ERR_INVALID_ARG;
+    std::vector<char> host;
     for (auto& kv : groups) {
         Group& g = kv.second;
-        const int nunits = (int)g.units.size();
-        const int nreq = (int)g.reqs.size();
-        const GroupLayout L = group_layout(g.reqs.size(), g.units.size(), g.vox);
-        StagingPool& pool = staging_pool(device);
-        const StagingPool::Lease lease = pool.acquire(L.upload);
-        if (!lease.p) return DARE_ERR_HIP;
-        char* host = lease.p;
-        memset(host, 0, L.o_req);
-        BatchHeader hd{};
-        hd.counts[0] = nunits;
-        hd.counts[1] = nreq;
-        hd.totals[0] = g.vox;
-        hd.totals[1] = g.pix;
-        memcpy(host, &hd, sizeof(hd));
-        memcpy(host + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
-        if (nunits) memcpy(host + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
-        const hipError_t ce = hipMemcpyAsync(ws, host, L.upload, hipMemcpyHostToDevice, stream);
-        const hipError_t re = pool.release(lease, stream);
-        if (ce != hipSuccess || re != hipSuccess) return DARE_ERR_HIP;
         const int R = std::get<1>(kv.first);
-        const int grid = R <= 1 ? kBatchGrid : std::min(nunits, 65535);
+        const bool host_units = R > 1;
+        const int nreq = (int)g.reqs.size();
+        const GroupLayout L = group_layout(g.reqs.size(), (size_t)g.nunits, host_units);
+        host.assign(L.upload, 0);
+        BatchHeader hd{};
+        hd.counts[0] = host_units ? (int)g.nunits : 0;
+        hd.counts[1] = nreq;
+        memcpy(host.data(), &hd, sizeof(hd));
+        memcpy(host.data() + L.o_req, g.reqs.data(), g.reqs.size() * sizeof(BatchReq));
+        if (host_units && !g.units.empty())
+            memcpy(host.data() + L.o_units, g.units.data(), g.units.size() * sizeof(int2));
+        if (!upload(ws, host.data(), L.upload)) return DARE_ERR_HIP;
+        const int grid = R <= 1 ? kBatchGrid : (int)std::min<int64_t>(g.nunits, 65535);
         HIP_TRY(launch_reslice_batch(std::get<0>(kv.first), R, (const BatchReq*)(ws + L.o_req),
-                                     (SliceSetup*)(ws + L.o_setup), (const int2*)(ws + L.o_units), (const int*)ws,
-                                     (float*)(ws + L.o_slab), nreq, grid, stream));
+                                     (SliceRec*)(ws + L.o_rec), (int2*)(ws + L.o_units), (TileRec*)(ws + L.o_tiles),
+                                     (int*)ws, nreq, (int)g.nunits, grid, stream));
         ws += L.total;
     }
     return DARE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_spec* specs, float* const* outs_dev,
+                               int32_t n, void* workspace_dev, uint64_t workspace_bytes, void* stream_) {
+    if (n == 0 && vols && specs && outs_dev) return DARE_OK;
+    int device = -1;
+    uint64_t needed = 0;
+    const dare_status st = check_batch(vols, specs, outs_dev, n, &device, &needed);
+    if (st != DARE_OK) return st;
+    if (!workspace_dev || workspace_bytes < needed || ((uintptr_t)workspace_dev % kAlign) != 0)
+        return DARE_ERR_INVALID_ARG;
+    DeviceGuard dg(device);
+    hipStream_t stream = (hipStream_t)stream_;
+    StagingPool& pool = staging_pool(device);
+    // uploads go through pinned staging, so the call does not wait for the stream
+    auto upload = [&](char* dst, const char* src, uint64_t bytes) {
+        const StagingPool::Lease lease = pool.acquire(bytes);
+        if (!lease.p) return false;
+        memcpy(lease.p, src, bytes);
+        const hipError_t ce = hipMemcpyAsync(dst, lease.p, bytes, hipMemcpyHostToDevice, stream);
+        const hipError_t re = pool.release(lease, stream);
+        return ce == hipSuccess && re == hipSuccess;
+    };
+    return run_batch(vols, specs, outs_dev, n, (char*)workspace_dev, stream, upload);
 }
 
 dare_status dare_bounds_from_frames(const float* poses, int32_t n, int32_t w, int32_t h, const double pitch_mm[2],

@@ -6,6 +6,8 @@
 // accumulated with 64-bit atomics, so the result is independent of order.
 #include <math.h>
 
+#include <algorithm>
+
 #include "dare_codec.h"
 #include "dare_frames.h"
 #include "dare_internal.h"
@@ -28,6 +30,25 @@ __device__ __forceinline__ bool pixel_voxel(const VolDev* __restrict__ vd, const
 
 __device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, int vy, int vz) {
     return (int64_t)b * vd->nbricks + ((int64_t)(vz >> 3) * vd->nby + (vy >> 3)) * vd->nbx + (vx >> 3);
+}
+
+// Pixel block and frame of this workgroup in a flat grid of nbx blocks per frame.  Workgroups
+// are dealt to the 8 XCDs round-robin; when nbx is a multiple of 8, XCD x takes the x-th eighth
+// of every frame's pixel blocks (a band of image rows).  Frames of a sweep are near-parallel, so
+// a band of rows falls on the same part of the volume frame after frame, and each XCD's L2 keeps
+// the accumulators of its own part instead of all eight sharing every line.
+// The launch covers frames f0, f0 + 1, ...
+__device__ __forceinline__ void frame_block(int nbx, int f0, int& bx, int& f) {
+    const int g = blockIdx.x;
+    if ((nbx & 7) == 0) {
+        const int per = nbx >> 3, k = g >> 3;
+        f = k / per;
+        bx = (g & 7) * per + (k - f * per);
+    } else {
+        f = g / nbx;
+        bx = g - f * nbx;
+    }
+    f += f0;
 }
 
 }  // namespace
@@ -158,9 +179,10 @@ __device__ __forceinline__ void mark_wave(VolDev* vd, int64_t e) {
 }
 
 // K3a: mark every (bin, brick) that a pixel of the batch lands in.
-__global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, double sx, double sy) {
-    const int f = blockIdx.y;
-    const int pix = blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, double sx, double sy, int f0) {
+    int bx, f;
+    frame_block((w * h + 255) >> 8, f0, bx, f);
+    const int pix = bx * 256 + threadIdx.x;
     int64_t e = -1;
     int vx, vy, vz;
     if (pix < w * h && pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz))
@@ -181,9 +203,10 @@ __global__ void k_compose_fan(VolDev* vd, const float* __restrict__ poses, int n
 }
 
 // K3a for fan frames: the pixel's (frame, sector) descriptor gives its pose and bin.
-__global__ void __launch_bounds__(256) k_mark_fan(VolDev* vd, int w, int h, FanArgs fan) {
-    const int f = blockIdx.y;
-    const int pix = blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(256) k_mark_fan(VolDev* vd, int w, int h, FanArgs fan, int f0) {
+    int bx, f;
+    frame_block((w * h + 255) >> 8, f0, bx, f);
+    const int pix = bx * 256 + threadIdx.x;
     int64_t entry = -1;
     if (pix < w * h) {
         const int i = pix % w, j = pix / w;
@@ -232,9 +255,10 @@ __global__ void __launch_bounds__(256) k_alloc(VolDev* vd, uint32_t new_count, u
 
 // K4: add each pixel's intensity and a count to its (bin, voxel).
 __global__ void __launch_bounds__(256) k_accumulate(const VolDev* __restrict__ vd, const uint8_t* __restrict__ frames,
-                                                    int w, int h, double sx, double sy) {
-    const int f = blockIdx.y;
-    const int pix = blockIdx.x * 256 + threadIdx.x;
+                                                    int w, int h, double sx, double sy, int f0) {
+    int bx, f;
+    frame_block((w * h + 255) >> 8, f0, bx, f);
+    const int pix = bx * 256 + threadIdx.x;
     if (pix >= w * h) return;
     int vx, vy, vz;
     if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
@@ -246,9 +270,11 @@ __global__ void __launch_bounds__(256) k_accumulate(const VolDev* __restrict__ v
 
 // K4 for fan frames.
 __global__ void __launch_bounds__(256) k_accumulate_fan(const VolDev* __restrict__ vd,
-                                                        const uint8_t* __restrict__ frames, int w, int h, FanArgs fan) {
-    const int f = blockIdx.y;
-    const int pix = blockIdx.x * 256 + threadIdx.x;
+                                                        const uint8_t* __restrict__ frames, int w, int h, FanArgs fan,
+                                                        int f0) {
+    int bx, f;
+    frame_block((w * h + 255) >> 8, f0, bx, f);
+    const int pix = bx * 256 + threadIdx.x;
     if (pix >= w * h) return;
     const int i = pix % w, j = pix / w;
     const int e = f * fan.sectors + i * fan.sectors / w;
@@ -441,6 +467,14 @@ static inline int grid_for(int64_t n, int block, int cap = 65536) {
     return (int)(g > cap ? cap : g);
 }
 
+// Frames per launch of the per-pixel passes (flat grids of pixel blocks x frames), so that a
+// grid stays below 2^24 workgroups.
+int frames_per_launch(int n, int w, int h) {
+    const int64_t nbx = ((int64_t)w * h + 255) / 256;
+    const int64_t fc = ((int64_t)1 << 24) / nbx;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(n, fc));
+}
+
 hipError_t launch_compose_frames(const VolDev* vd, const float* poses, int n, hipStream_t stream) {
     hipLaunchKernelGGL(k_compose_frames, dim3((n + 63) / 64), dim3(64), 0, stream, const_cast<VolDev*>(vd), poses, n);
     return hipGetLastError();
@@ -452,8 +486,10 @@ hipError_t launch_assign_bins(VolDev* vd, int n, int K0, hipStream_t stream) {
 }
 
 hipError_t launch_mark_pixels(const VolDev* vd, int n, int w, int h, double sx, double sy, hipStream_t stream) {
-    hipLaunchKernelGGL(k_mark_pixels, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, const_cast<VolDev*>(vd),
-                       w, h, sx, sy);
+    const int nbx = (w * h + 255) / 256, fc = frames_per_launch(n, w, h);
+    for (int f0 = 0; f0 < n; f0 += fc)
+        hipLaunchKernelGGL(k_mark_pixels, dim3(nbx * std::min(fc, n - f0)), dim3(256), 0, stream,
+                           const_cast<VolDev*>(vd), w, h, sx, sy, f0);
     return hipGetLastError();
 }
 
@@ -466,14 +502,19 @@ hipError_t launch_compose_fan(const VolDev* vd, const float* poses, int n, const
 }
 
 hipError_t launch_mark_fan(const VolDev* vd, int n, int w, int h, const FanArgs& fan, hipStream_t stream) {
-    hipLaunchKernelGGL(k_mark_fan, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, const_cast<VolDev*>(vd), w, h,
-                       fan);
+    const int nbx = (w * h + 255) / 256, fc = frames_per_launch(n, w, h);
+    for (int f0 = 0; f0 < n; f0 += fc)
+        hipLaunchKernelGGL(k_mark_fan, dim3(nbx * std::min(fc, n - f0)), dim3(256), 0, stream,
+                           const_cast<VolDev*>(vd), w, h, fan, f0);
     return hipGetLastError();
 }
 
 hipError_t launch_accumulate_fan(const VolDev* vd, const uint8_t* frames, int n, int w, int h, const FanArgs& fan,
                                  hipStream_t stream) {
-    hipLaunchKernelGGL(k_accumulate_fan, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, vd, frames, w, h, fan);
+    const int nbx = (w * h + 255) / 256, fc = frames_per_launch(n, w, h);
+    for (int f0 = 0; f0 < n; f0 += fc)
+        hipLaunchKernelGGL(k_accumulate_fan, dim3(nbx * std::min(fc, n - f0)), dim3(256), 0, stream, vd, frames, w, h,
+                           fan, f0);
     return hipGetLastError();
 }
 
@@ -493,7 +534,10 @@ hipError_t launch_alloc(VolDev* vd, uint32_t new_count, uint32_t used, uint32_t 
 
 hipError_t launch_accumulate(const VolDev* vd, const uint8_t* frames, int n, int w, int h, double sx, double sy,
                              hipStream_t stream) {
-    hipLaunchKernelGGL(k_accumulate, dim3((w * h + 255) / 256, n), dim3(256), 0, stream, vd, frames, w, h, sx, sy);
+    const int nbx = (w * h + 255) / 256, fc = frames_per_launch(n, w, h);
+    for (int f0 = 0; f0 < n; f0 += fc)
+        hipLaunchKernelGGL(k_accumulate, dim3(nbx * std::min(fc, n - f0)), dim3(256), 0, stream, vd, frames, w, h, sx,
+                           sy, f0);
     return hipGetLastError();
 }
 

@@ -153,10 +153,9 @@ hipError_t launch_download_sums(const VolDev* vd, uint32_t* S, uint32_t* C, int 
                                 hipStream_t stream);
 hipError_t launch_download_storage(const VolDev* vd, int dtype, float* A, float* C, int K, int nx, int ny,
                                    int nz, hipStream_t stream);
-// Radius 1 takes the per-slice setup computed on the host (`core`) and the volume's view;
-// radius > 4 reads the volume header `vd` and ignores both.
-hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, const SliceCore& core,
-                          const VolView& view, hipStream_t stream);
+// One request at radius 1 or above 4; every kernel reads the volume header `vd` and evaluates
+// the slice setup on the device.
+hipError_t launch_reslice(const VolDev* vd, int dtype, int radius, const SliceArgs& s, hipStream_t stream);
 hipError_t launch_copy_probe(const void* src, void* dst, uint64_t n, hipStream_t stream);
 
 // Reslice work decomposition: lanes per output pixel (1 for radius 1) and the

@@ -1,16 +1,18 @@
 // Serving: continuous batching of reslice requests from many consoles.
 //
 // A scheduler thread turns the FIFO of waiting requests into ticks.  A tick
-// takes requests from the head of the queue while they fit its pixel and tile
+// takes requests from the head of the queue while they fit its pixel and unit
 // budget and while a result slot of their size can be allocated in the
-// server's arena (the HBM budget); the head request waits until slots free up,
-// so admission is first come, first served.  Each tick goes to one of up to
-// four streams: its request table is uploaded from pinned staging, a captured
-// graph runs the batched reslice (per-request setup pre-pass + persistent tile
-// kernel), the results are copied to the callers' host buffers and an event
-// marks completion.  Ticks on different streams overlap on the device, and
-// requests that arrive meanwhile are admitted into the next tick whose stream
-// is free.
+// server's arena (the HBM budget of results); the head request waits until
+// slots free up, so admission is first come, first served.  Volumes are
+// admitted against a second budget, the device bytes of the resident volumes'
+// arenas, and can be removed once their requests have completed.  Each tick
+// goes to one of up to four streams: its request table is uploaded from pinned
+// staging, a captured graph runs the batched reslice (per-request setup pass +
+// persistent tile kernel), the results are copied to the callers' host buffers
+// and an event marks completion.  Ticks on different streams overlap on the
+// device, and requests that arrive meanwhile are admitted into the next tick
+// whose stream is free.
 #include <string.h>
 
 #include <algorithm>
@@ -34,6 +36,8 @@ const VolDev* volume_device(const dare_volume* v);
 int volume_dtype(const dare_volume* v);
 int volume_radius(const dare_volume* v);
 int volume_device_id(const dare_volume* v);
+uint64_t volume_arena_size(const dare_volume* v);
+int reslice_lanes(int radius);
 dare_status check_slice_spec(const dare_slice_spec* s);
 }  // namespace dare
 
@@ -49,8 +53,10 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Workgroup units of a request: the radius-1 passes index pixels and slabs directly.
-int64_t units_of(int radius, int W, int H) { return radius <= 1 ? 0 : batch_units(radius, W, H); }
+// Work units of a request (radius 1: the most the device may append, 16 x 16 tiles).
+int64_t units_of(int radius, int W, int H) {
+    return radius <= 1 ? tile_units_max(W, H) : batch_units(radius, W, H);
+}
 
 enum ReqState { kWaiting = 0, kInFlight = 1, kDone = 2, kFailed = 3 };
 
@@ -62,8 +68,6 @@ struct Request {
     uint64_t out_off = UINT64_MAX;
     uint64_t bytes = 0;
     int64_t units = 0;
-    int64_t slab = 0;                 // slab floats wanted (radius 1); granted only if the arena has room
-    uint64_t slab_off = UINT64_MAX;
     int state = kWaiting;
     dare_request_times t{};
     // frames job: dare_reconstruct_frames arguments and its status
@@ -79,6 +83,7 @@ struct Slot {
     hipEvent_t ev_kernels = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
     char* ws = nullptr;           // device workspace: header, requests, units, setup records
+    uint64_t ws_off = UINT64_MAX; // its place in the arena
     char* staging = nullptr;      // pinned host copy of the uploaded part
     bool busy = false;
     bool kernels_seen = false;
@@ -87,17 +92,26 @@ struct Slot {
 
 }  // namespace
 
+// A registered volume: its device bytes count against the volume budget while it is resident.
+struct VolEntry {
+    dare_volume* v = nullptr;         // null once removed (ids are never reused)
+    uint64_t bytes = 0;
+    int64_t pending = 0;              // queued or in-flight requests and frames jobs
+    bool closing = false;             // being removed: new requests are refused
+};
+
 struct dare_server {
     dare_server_config cfg{};
     int device = 0;
     char* arena = nullptr;
     uint64_t arena_bytes = 0;
-    // workspace layout (identical in every slot, sized for a full tick)
-    uint64_t o_req = 0, o_units = 0, o_setup = 0, ws_bytes = 0;
+    // workspace layout (identical in every slot, sized for a full tick), set by the first volume
+    uint64_t o_req = 0, o_units = 0, o_tiles = 0, o_rec = 0, ws_bytes = 0;
     int64_t max_units = 0;
     Slot slots[kMaxStreams];
-    RangeAlloc outs;
-    std::vector<dare_volume*> vols;
+    RangeAlloc outs;                  // result slots and the slots' workspaces
+    std::vector<VolEntry> vols;
+    uint64_t vol_bytes = 0;           // resident volumes' bytes
     int dtype = -1, radius = -1;
     std::mutex mu;
     std::condition_variable cv;       // scheduler: new work or stop
@@ -116,10 +130,11 @@ namespace {
 
 // Launch the tick's kernels on the slot's stream (captured once into a graph when enabled).
 hipError_t enqueue_kernels(dare_server* S, Slot& sl) {
-    return launch_reslice_batch(S->dtype, S->radius, (const BatchReq*)(sl.ws + S->o_req),
-                                (SliceSetup*)(sl.ws + S->o_setup), (const int2*)(sl.ws + S->o_units),
-                                (const int*)sl.ws, (float*)S->arena, S->cfg.max_tick_requests,
-                                S->radius <= 1 ? kServerGrid : 4096, sl.stream);
+    return launch_reslice_batch(S->dtype, S->radius, (const BatchReq*)(sl.ws + S->o_req), (SliceRec*)(sl.ws + S->o_rec),
+                                (int2*)(sl.ws + S->o_units), (TileRec*)(sl.ws + S->o_tiles), (int*)sl.ws,
+                                S->cfg.max_tick_requests, (int)S->max_units,
+                                S->radius <= 1 ? kServerGrid : 4096,
+                                sl.stream);
 }
 
 hipError_t ensure_graph(dare_server* S, Slot& sl) {
@@ -135,10 +150,11 @@ hipError_t ensure_graph(dare_server* S, Slot& sl) {
     return e;
 }
 
+// A request leaves the device: its result slot is returned and its volume's count drops.
 void release_request(dare_server* S, Request& r) {
-    S->outs.release(r.out_off, r.bytes);
-    if (r.slab_off != UINT64_MAX) S->outs.release(r.slab_off, (uint64_t)r.slab * sizeof(float));
-    r.slab_off = UINT64_MAX;
+    if (r.out_off != UINT64_MAX) S->outs.release(r.out_off, r.bytes);
+    r.out_off = UINT64_MAX;
+    S->vols[r.vol].pending -= 1;
 }
 
 // Complete finished ticks.  Caller holds the lock.
@@ -181,8 +197,9 @@ int busy_slots(dare_server* S) {
 bool launch_tick(dare_server* S, Slot& sl) {
     if (S->queue.empty()) return false;
     const double t_admit = now_s();
-    int64_t pixels = 0, units = 0, vox = 0, pflat = 0;
+    int64_t pixels = 0, units = 0;
     int nreq = 0;
+    const bool host_units = S->radius > 1;
     std::vector<BatchReq> breqs;
     std::vector<int2> bunits;
     while (!S->queue.empty() && nreq < S->cfg.max_tick_requests) {
@@ -196,7 +213,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
         r.state = kInFlight;
         r.t.t_admit = t_admit;
         BatchReq q{};
-        q.vol = volume_device(S->vols[r.vol]);
+        q.vol = volume_device(S->vols[r.vol].v);
         q.s.sx = r.spec.pitch_mm[0];
         q.s.sy = r.spec.pitch_mm[1];
         memcpy(q.s.P, r.spec.probe_pose, sizeof(q.s.P));
@@ -205,22 +222,9 @@ bool launch_tick(dare_server* S, Slot& sl) {
         q.s.tiles_x = (r.spec.width + kTile - 1) / kTile;
         q.s.tiles = q.s.tiles_x * ((r.spec.height + kTile - 1) / kTile);
         q.s.out = (float*)(S->arena + off);
-        if (S->radius <= 1) host_core(S->vols[r.vol], &r.spec, &q.core);
-        // the slab is optional: without room for it the request gathers per pixel, same result
-        if (r.slab > 0) {
-            const uint64_t so = S->outs.alloc((uint64_t)r.slab * sizeof(float));
-            if (so != UINT64_MAX) {
-                r.slab_off = so;
-                q.v_cap = r.slab;
-                q.v_off = (int64_t)(so / sizeof(float));
-            }
-        }
-        q.v_beg = vox;
-        q.p_beg = pflat;
-        vox += q.v_cap;
-        pflat += (px + kFlatBlock - 1) / kFlatBlock * kFlatBlock;   // flat ranges in whole blocks
         breqs.push_back(q);
-        for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
+        if (host_units)
+            for (int64_t t = 0; t < r.units; ++t) bunits.push_back(make_int2(nreq, (int)t));
         sl.tickets.push_back(S->queue.front());
         S->queue.pop_front();
         pixels += px;
@@ -229,14 +233,13 @@ bool launch_tick(dare_server* S, Slot& sl) {
     }
     if (nreq == 0) return false;
     BatchHeader hd{};
-    hd.counts[0] = (int)units;
+    hd.counts[0] = host_units ? (int)units : 0;   // radius 1: the setup pass appends the units
     hd.counts[1] = nreq;
-    hd.totals[0] = vox;
-    hd.totals[1] = pflat;
     memcpy(sl.staging, &hd, sizeof(hd));
     memcpy(sl.staging + S->o_req, breqs.data(), breqs.size() * sizeof(BatchReq));
-    memcpy(sl.staging + S->o_units, bunits.data(), bunits.size() * sizeof(int2));
-    const uint64_t upload = S->o_units + bunits.size() * sizeof(int2);
+    if (host_units) memcpy(sl.staging + S->o_units, bunits.data(), bunits.size() * sizeof(int2));
+    const uint64_t upload = host_units ? S->o_units + bunits.size() * sizeof(int2)
+                                       : S->o_req + breqs.size() * sizeof(BatchReq);
     hipError_t e = hipMemcpyAsync(sl.ws, sl.staging, upload, hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) e = S->cfg.use_graphs ? hipGraphLaunch(sl.graph, sl.stream) : enqueue_kernels(S, sl);
     if (e == hipSuccess) e = hipEventRecord(sl.ev_kernels, sl.stream);
@@ -276,7 +279,7 @@ bool run_frames_job(dare_server* S, std::unique_lock<std::mutex>& lk) {
     if (!r.frames_job) return false;
     r.state = kInFlight;
     r.t.t_admit = r.t.t_launch = now_s();
-    dare_volume* v = S->vols[r.vol];
+    dare_volume* v = S->vols[r.vol].v;
     const uint8_t* frames = r.frames;
     const float* poses = r.poses;
     const int32_t n = r.nframes, w = r.fw, h = r.fh;
@@ -296,6 +299,7 @@ bool run_frames_job(dare_server* S, std::unique_lock<std::mutex>& lk) {
     S->stats.compound_seconds += t1 - t0;
     if (rr.state == kDone) S->stats.frames += n;
     S->stats.completed += 1;
+    S->vols[rr.vol].pending -= 1;
     S->queue.pop_front();
     S->done_cv.notify_all();
     return true;
@@ -330,19 +334,61 @@ void scheduler(dare_server* S) {
     }
 }
 
+// A registered volume that still takes requests.  Caller holds the lock.
+bool volume_open(const dare_server* S, int32_t id) {
+    return id >= 0 && id < (int32_t)S->vols.size() && S->vols[id].v && !S->vols[id].closing;
+}
+
+// The slots' workspaces, laid out once the radius is known (the first volume): header,
+// request table, unit table (sized for a full tick at this radius) and setup records.
+dare_status layout_workspaces(dare_server* S, int radius) {
+    const dare_server_config& c = S->cfg;
+    // pixels per unit: 16 x 16 tiles up to radius 4, 256 / (lanes per pixel) beyond; a request
+    // adds at most one partial tile per row and column of tiles
+    const int64_t ppu = radius <= 4 ? 256 : 256 / reslice_lanes(radius);
+    int64_t mu = c.max_tick_pixels / ppu + (radius <= 4 ? 300 : 1) * (int64_t)c.max_tick_requests;
+    S->max_units = std::min<int64_t>(mu, (int64_t)1 << 28);
+    S->o_req = aup(sizeof(BatchHeader));
+    S->o_units = S->o_req + aup((uint64_t)c.max_tick_requests * sizeof(BatchReq));
+    S->o_tiles = S->o_units + aup((uint64_t)S->max_units * sizeof(int2));
+    S->o_rec = S->o_tiles + (radius <= 1 ? aup((uint64_t)S->max_units * sizeof(TileRec)) : 0);
+    S->ws_bytes = S->o_rec + aup((uint64_t)c.max_tick_requests * sizeof(SliceRec));
+    for (int k = 0; k < c.n_streams; ++k) {
+        Slot& sl = S->slots[k];
+        const uint64_t off = S->outs.alloc(S->ws_bytes);
+        if (off == UINT64_MAX) return DARE_ERR_BUDGET;
+        sl.ws_off = off;
+        sl.ws = S->arena + off;
+        if (hipHostMalloc((void**)&sl.staging, S->o_tiles, hipHostMallocDefault) != hipSuccess) return DARE_ERR_HIP;
+    }
+    return DARE_OK;
+}
+
+void release_workspaces(dare_server* S) {
+    for (int k = 0; k < S->cfg.n_streams; ++k) {
+        Slot& sl = S->slots[k];
+        if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+        sl.graph = nullptr;
+        if (sl.staging) (void)hipHostFree(sl.staging);
+        sl.staging = nullptr;
+        if (sl.ws_off != UINT64_MAX) S->outs.release(sl.ws_off, S->ws_bytes);
+        sl.ws_off = UINT64_MAX;
+        sl.ws = nullptr;
+    }
+}
+
 // Validate and queue one request.  Caller holds the lock.
 dare_status submit_locked(dare_server* S, int32_t volume_id, const dare_slice_spec* spec, float* host_out,
                           uint64_t* ticket) {
     const dare_status st = check_slice_spec(spec);
     if (st != DARE_OK) return st;
-    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
+    if (!volume_open(S, volume_id)) return DARE_ERR_INVALID_ARG;
     Request r;
     r.vol = volume_id;
     r.spec = *spec;
     r.host_out = host_out;
     r.bytes = (uint64_t)spec->width * spec->height * sizeof(float);
     r.units = units_of(S->radius, spec->width, spec->height);
-    r.slab = S->radius <= 1 ? slab_floats(S->vols[volume_id], spec) : 0;
     if (!S->outs.fits_ever(r.bytes) || r.units > S->max_units ||
         (int64_t)spec->width * spec->height > S->cfg.max_tick_pixels)
         return DARE_ERR_INVALID_ARG;
@@ -355,6 +401,7 @@ dare_status submit_locked(dare_server* S, int32_t volume_id, const dare_slice_sp
     S->reqs.emplace(id, r);
     S->queue.push_back(id);
     S->stats.submitted += 1;
+    S->vols[volume_id].pending += 1;
     *ticket = id;
     return DARE_OK;
 }
@@ -386,6 +433,7 @@ void dare_default_server_config(dare_server_config* c) {
     c->n_streams = 3;
     c->max_queue = 4096;
     c->use_graphs = 1;
+    c->volume_budget_bytes = 0;
 }
 
 dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, uint64_t arena_bytes,
@@ -396,22 +444,11 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
         cfg->max_tick_requests > 4096 || cfg->max_tick_pixels < 1 || cfg->max_tick_pixels > ((int64_t)1 << 32) ||
         cfg->max_queue < 1)
         return DARE_ERR_INVALID_ARG;
-    if (((uintptr_t)arena_dev % kAlignS) != 0) return DARE_ERR_INVALID_ARG;
+    if (((uintptr_t)arena_dev % kAlignS) != 0 || arena_bytes < 2 * kAlignS) return DARE_ERR_INVALID_ARG;
     dare_server* S = new dare_server();
     S->cfg = *cfg;
     S->arena = (char*)arena_dev;
     S->arena_bytes = arena_bytes;
-    S->max_units = cfg->max_tick_pixels / 256 + 64 * (int64_t)cfg->max_tick_requests;
-    if (S->max_units > (1 << 28)) S->max_units = 1 << 28;
-    S->o_req = aup(sizeof(BatchHeader));
-    S->o_units = S->o_req + aup((uint64_t)cfg->max_tick_requests * sizeof(BatchReq));
-    S->o_setup = S->o_units + aup((uint64_t)S->max_units * sizeof(int2));
-    S->ws_bytes = S->o_setup + aup((uint64_t)cfg->max_tick_requests * sizeof(SliceSetup));
-    const uint64_t ws_total = S->ws_bytes * cfg->n_streams;
-    if (arena_bytes <= ws_total + kAlignS) {
-        delete S;
-        return DARE_ERR_INVALID_ARG;
-    }
     if (hipGetDevice(&S->device) != hipSuccess) {
         delete S;
         return DARE_ERR_HIP;
@@ -419,17 +456,15 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
     hipError_t e = hipSuccess;
     for (int k = 0; k < cfg->n_streams && e == hipSuccess; ++k) {
         Slot& sl = S->slots[k];
-        sl.ws = S->arena + k * S->ws_bytes;
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_kernels, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&sl.staging, S->o_setup, hipHostMallocDefault);
     }
     if (e != hipSuccess) {
         dare_server_destroy(S);
         return DARE_ERR_HIP;
     }
-    S->outs.reset(ws_total, arena_bytes - ws_total, kAlignS);
+    S->outs.reset(0, arena_bytes, kAlignS);
     S->th = std::thread(scheduler, S);
     *out = S;
     return DARE_OK;
@@ -439,22 +474,67 @@ dare_status dare_server_add_volume(dare_server* S, dare_volume* v, int32_t* volu
     if (!S || !v || !volume_id) return DARE_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     if (volume_device_id(v) != S->device) return DARE_ERR_INVALID_ARG;
+    for (const VolEntry& e : S->vols)
+        if (e.v == v) return DARE_ERR_INVALID_ARG;   // registered already
     const int dt = volume_dtype(v), R = volume_radius(v);
+    const uint64_t bytes = volume_arena_size(v);
+    if (S->dtype >= 0 && (dt != S->dtype || R != S->radius))
+        return DARE_ERR_INVALID_ARG;   // one storage dtype and radius per server (one graph per stream)
+    if (S->cfg.volume_budget_bytes > 0 && S->vol_bytes + bytes > S->cfg.volume_budget_bytes)
+        return DARE_ERR_BUDGET;        // admitting it would exceed the resident-volume budget
     if (S->dtype < 0) {
+        dare_status st = layout_workspaces(S, R);
         S->dtype = dt;
         S->radius = R;
-        for (int k = 0; k < S->cfg.n_streams; ++k) {
-            if (ensure_graph(S, S->slots[k]) != hipSuccess) {
-                S->dtype = -1;
-                S->radius = -1;
-                return DARE_ERR_HIP;
-            }
+        for (int k = 0; k < S->cfg.n_streams && st == DARE_OK; ++k)
+            if (ensure_graph(S, S->slots[k]) != hipSuccess) st = DARE_ERR_HIP;
+        if (st != DARE_OK) {
+            release_workspaces(S);
+            S->dtype = -1;
+            S->radius = -1;
+            return st;
         }
-    } else if (dt != S->dtype || R != S->radius) {
-        return DARE_ERR_INVALID_ARG;   // one storage dtype and radius per server (one graph per stream)
     }
-    S->vols.push_back(v);
+    VolEntry e;
+    e.v = v;
+    e.bytes = bytes;
+    S->vols.push_back(e);
+    S->vol_bytes += bytes;
     *volume_id = (int32_t)S->vols.size() - 1;
+    return DARE_OK;
+}
+
+dare_status dare_server_remove_volume(dare_server* S, int32_t volume_id, double wait_seconds) {
+    if (!S) return DARE_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!volume_open(S, volume_id)) return DARE_ERR_INVALID_ARG;
+    VolEntry& e = S->vols[volume_id];
+    e.closing = true;                  // no new requests; the queued ones still run
+    const auto deadline = std::chrono::steady_clock::now() +
+                          std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                              std::chrono::duration<double>(wait_seconds > 0.0 ? std::min(wait_seconds, 3600.0) : 0.0));
+    while (S->vols[volume_id].pending > 0) {
+        if (!(wait_seconds > 0.0) || S->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            if (S->vols[volume_id].pending == 0) break;
+            S->vols[volume_id].closing = false;   // still in use: it stays registered
+            return DARE_ERR_NOT_READY;
+        }
+    }
+    VolEntry& f = S->vols[volume_id];
+    S->vol_bytes -= f.bytes;
+    f.v = nullptr;
+    f.bytes = 0;
+    f.closing = false;
+    return DARE_OK;
+}
+
+dare_status dare_server_volume_bytes(dare_server* S, uint64_t* resident_bytes, int32_t* resident_volumes) {
+    if (!S || !resident_bytes || !resident_volumes) return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *resident_bytes = S->vol_bytes;
+    int32_t n = 0;
+    for (const VolEntry& e : S->vols) n += e.v != nullptr;
+    *resident_volumes = n;
     return DARE_OK;
 }
 
@@ -475,7 +555,7 @@ dare_status dare_server_submit_frames(dare_server* S, int32_t volume_id, const u
     if ((int64_t)w * h > (int64_t)1 << 30 || !(pitch_mm[0] > 0.0) || !(pitch_mm[1] > 0.0))
         return DARE_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
-    if (volume_id < 0 || volume_id >= (int32_t)S->vols.size()) return DARE_ERR_INVALID_ARG;
+    if (!volume_open(S, volume_id)) return DARE_ERR_INVALID_ARG;
     if ((int32_t)S->queue.size() >= S->cfg.max_queue) {
         S->stats.rejected += 1;
         return DARE_ERR_QUEUE_FULL;
@@ -495,6 +575,7 @@ dare_status dare_server_submit_frames(dare_server* S, int32_t volume_id, const u
     S->reqs.emplace(id, r);
     S->queue.push_back(id);
     S->stats.submitted += 1;
+    S->vols[volume_id].pending += 1;
     *ticket = id;
     S->cv.notify_one();
     return DARE_OK;
@@ -580,12 +661,11 @@ dare_status dare_server_destroy(dare_server* S) {
             const hipError_t q = hipStreamSynchronize(sl.stream);
             if (q != hipSuccess) e = q;
         }
-        if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
         if (sl.ev_kernels) (void)hipEventDestroy(sl.ev_kernels);
         if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.staging) (void)hipHostFree(sl.staging);
     }
+    release_workspaces(S);
     delete S;
     return e == hipSuccess ? DARE_OK : DARE_ERR_HIP;
 }

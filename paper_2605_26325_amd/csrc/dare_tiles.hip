@@ -1,0 +1,743 @@
+// Directionality-aware reslice at interpolation radius 1 (Sec. 2.1 "Reslicing", Eq. 1, Eq. 2,
+// Fig. 2): the trilinear cell of every pixel, each cell voxel blended over the direction bins
+// that pass the angular gates.
+//
+// The per-request part runs on the device in FP64 (`request_setup`, one wave): the slice pose
+// T = P.C, Eq. 1 for every bin, the two gates and Eq. 2 for the survivors, the plane frame in
+// voxel units, and the choice of tile edge.  A request is then cut into square tiles of output
+// pixels, each with a record of its voxel box (`compute_tile`).  One workgroup takes one
+// (request, tile) unit and runs three phases out of LDS:
+//   slots   the brick-table entries of every surviving bin over the bricks of the tile's voxel
+//           box (one table read per (bin, brick), not per voxel), issued first so that their
+//           latency overlaps the next phase;
+//   voxels  every voxel within the trilinear support of the tile's piece of plane, enumerated
+//           as short runs along the plane normal's dominant axis (one thread per column of the
+//           other two axes), tested and listed; then every listed voxel gathers its surviving
+//           bins' pairs and blends them into V_v = sum_b w_b c_vb a_vb / sum_b w_b c_vb, kept in
+//           LDS as (V_v, 1), or (0, 0) when no surviving bin holds a sample (or the voxel lies
+//           outside the grid);
+//   pixels  FP64 position, the 8 cell values from LDS, tent weights, num / den or NaN.
+// Storing (V, valid) lets a pixel add w V and w valid with two multiply-adds per corner: an
+// invalid or out-of-grid corner adds exactly nothing, as the sums over valid voxels require.
+//
+// A single reslice launches one workgroup per 16 x 16 tile; each workgroup evaluates the
+// request setup and its tile's record itself (wave 0), since no other memory holds them.  A batch
+// runs the request setup once per request and the tile records once per tile (`k_tiles_setup`:
+// one wave per request, one lane per tile; it also appends the units to a list), then one
+// persistent kernel over all staged units (`k_tiles`), which reads both records through scalar
+// loads, with tiles of 32 x 32 pixels wherever their voxel box fits the LDS budget.  The
+// per-voxel and per-pixel arithmetic does not depend on the tile, so a request gives the same
+// bits alone and in a batch.  Requests whose pixels are too coarse for staging to pay (a 16 x 16
+// tile's box beyond the budget) gather per pixel.
+#include <algorithm>
+
+#include "dare_batch.h"
+#include "dare_reslice_dev.h"
+
+namespace dare {
+
+namespace {
+
+constexpr int kItemsMax = 2048;      // staged voxels (box columns x run depth) per tile
+constexpr int kColsMax = 1024;       // box columns per tile
+constexpr int kSlotsMax = 1280;      // (box brick, bin) table entries per tile
+constexpr int kTileBig = 32;         // batched tile edge where the box fits
+constexpr int kFillRun = 4096;       // pixels per unit of a batched request that is all NaN
+
+// Listed voxels per thread per gather round, and surviving bins whose pair loads a thread issues
+// together for all of them.
+template <int DT>
+constexpr int items_per_round() { return 2; }
+template <int DT>
+constexpr int bins_per_round() { return DT == DARE_FP8_E4M3 ? 4 : 8; }
+
+// LDS of a workgroup working on one staged tile.
+template <int DT>
+struct TileLds {
+    alignas(16) int slot[kSlotsMax];                      // [box brick][bin], rows of kactp
+    float2 scale[DT == DARE_FP8_E4M3 ? kSlotsMax : 1];    // FP8 value and count scales per slot
+    short rs[kColsMax];                                   // first voxel of each column's run, less lo_d
+    float2 V[kItemsMax];                                  // (V_v, 1) or (0, 0), [column][run]
+    int list[kItemsMax];                                  // voxels to gather: e | local << 11 | brick << 20
+    int nlist;
+};
+
+// Pointers in the global address space, so that loads and stores through them are global (not
+// flat) operations, whose waits do not wait for LDS and vice versa.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> global(T* p) {
+    return (gptr<T>)(p);
+}
+
+// Workgroup-uniform values, moved to scalar registers.
+__device__ __forceinline__ int ui(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uf(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ double ud(double x) { return uniform_f64(x); }
+__device__ __forceinline__ SmallDiv usd(uint32_t m, int d) { return SmallDiv{(uint32_t)ui((int)m), ui(d)}; }
+
+// Upper bound of a tile's box edge along one axis (T pixels per side): the corner cells'
+// floors differ by at most ceil of the tile's extent, and the box adds one voxel below and two
+// above (the upper cell voxel and a margin for rounding).
+__device__ __forceinline__ int box_edge_bound(int T, double ex, double ey) {
+    const double ext = (double)(T - 1) * (fabs(ex) + fabs(ey));
+    return (int)floor(ext * (1.0 + 1e-9) + 1e-6) + 5;
+}
+
+// Does a T x T tile of this request fit the LDS budget wherever it falls?
+__device__ __forceinline__ bool tile_fits(const SliceRec& rec, int T) {
+    const int dax = rec.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    int e[3];
+    int64_t nbb = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        e[a] = box_edge_bound(T, rec.ex[a], rec.ey[a]);
+        nbb *= e[a] / 8 + 2;
+    }
+    const int64_t cols = (int64_t)e[pax] * e[qax];
+    const int kactp = (rec.kact + 7) & ~7;
+    return cols <= kColsMax && cols * rec.depth <= kItemsMax && nbb * kactp <= kSlotsMax;
+}
+
+// One wave: the per-request setup of a radius-1 reslice, in FP64 on the device, into `rec`.
+// Lane 0 returns the number of work units (tiles) of the request and its mode in *mode_out.
+__device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SliceRec& rec, int max_tile,
+                             int* mode_out) {
+    double T[12];
+    const int kact = slice_setup(vd, s, rec, T);
+    const int lane = threadIdx.x & 63;
+    if (lane >= kact) {          // bins past the survivors: no slots, zero weight
+        rec.act_bin[lane] = 0;
+        rec.act_w[lane] = 0.0f;
+    }
+    if (lane != 0) return 0;
+    const double inv_h = vd->inv_h;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rec.c00[a] = (T[a * 4 + 3] - vd->origin[a]) * inv_h;
+        rec.ex[a] = (s.sx * T[a * 4 + 0]) * inv_h;
+        rec.ey[a] = (s.sy * T[a * 4 + 1]) * inv_h;
+    }
+    rec.vol = view_of(vd);
+    rec.out = s.out;
+    rec.W = s.W;
+    rec.H = s.H;
+    // the slab of a tile: voxels with |m.(v - c0)| < |m|_1 (plus slop for FP32 rounding of
+    // coordinates up to the grid's size) form runs of at most ceil(2 half) voxels along dax
+    const int nmax = max(vd->nx, max(vd->ny, vd->nz));
+    const float slop = 2e-3f + 1e-6f * (float)(nmax + 64);
+    const float l1m = fabsf(rec.fm[0]) + fabsf(rec.fm[1]) + fabsf(rec.fm[2]);
+    rec.slop = slop;
+    rec.half = (l1m + slop) * fabsf(1.0f / rec.fm[rec.dax]);
+    rec.depth = (int)ceilf(2.0f * rec.half);
+    int mode = kact > 0 ? 2 : 0, tile = 16;
+    if (kact > 0) {
+        if (max_tile >= kTileBig && tile_fits(rec, kTileBig)) {
+            mode = 1;
+            tile = kTileBig;
+        } else if (tile_fits(rec, 16)) {
+            mode = 1;
+        }
+    }
+    rec.mode = mode;
+    *mode_out = mode;
+    rec.tile = tile;
+    rec.tiles_x = (s.W + tile - 1) / tile;
+    rec.ntiles = rec.tiles_x * ((s.H + tile - 1) / tile);
+    return rec.ntiles;
+}
+
+// One thread: the record of tile t of a staged request.  The box is the four corner pixels'
+// cells with one voxel of margin (positions are affine in (i, j), so the corners' cells bound
+// every pixel's cell; the margin absorbs rounding), clipped to [-1, n].
+__device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
+    const int T = rec.tile, W = rec.W, H = rec.H;
+    const int ty = t / rec.tiles_x, tx = t - ty * rec.tiles_x;
+    const int i0 = tx * T, j0 = ty * T;
+    const int i1 = min(i0 + T - 1, W - 1), j1 = min(j0 + T - 1, H - 1);
+    const int n[3] = {rec.vol.n[0], rec.vol.n[1], rec.vol.n[2]};
+    int lo[3], hi[3];
+    float c0[3];
+    bool empty = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int mn = 0, mx = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double ci = (double)((k & 1) ? i1 : i0), cj = (double)((k & 2) ? j1 : j0);
+            const double c = fma(cj, rec.ey[a], fma(ci, rec.ex[a], rec.c00[a]));
+            const int f = (int)fmin(fmax(floor(c), -1048576.0), 1048576.0);
+            mn = k == 0 ? f : min(mn, f);
+            mx = k == 0 ? f : max(mx, f);
+            if (k == 0) c0[a] = (float)c;
+        }
+        lo[a] = max(mn - 1, -1);
+        hi[a] = min(mx + 2, n[a]);
+        // no in-grid voxel in reach: every pixel of the tile is unassigned
+        empty = empty || max(lo[a], 0) > min(hi[a], n[a] - 1);
+    }
+    const int dax = rec.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    const int bp = hi[pax] - lo[pax] + 1, bq = hi[qax] - lo[qax] + 1;
+    const int depth = rec.depth, kactp = (rec.kact + 7) & ~7;
+    int blo[3], bdim[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        blo[a] = max(lo[a], 0) >> 3;
+        bdim[a] = (min(hi[a], n[a] - 1) >> 3) - blo[a] + 1;
+    }
+    const int nbb = bdim[0] * bdim[1] * bdim[2];
+    // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
+    // check only keeps the LDS accesses in bounds
+    const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kItemsMax && bp * bq <= kColsMax &&
+                      bp * bq * depth <= kItemsMax && nbb * kactp <= kSlotsMax;
+    tr.r = r;
+    tr.mode = (!empty && fits) ? 1 : 0;
+    tr.i0 = i0;
+    tr.j0 = j0;
+    tr.ni = i1 - i0 + 1;
+    tr.nj = j1 - j0 + 1;
+    float l1u = 0.0f, l1w = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        tr.lo[a] = lo[a];
+        tr.hi[a] = hi[a];
+        tr.blo[a] = blo[a];
+        tr.bdim[a] = bdim[a];
+        tr.c0[a] = c0[a];
+        l1u += fabsf(rec.fu[a]);
+        l1w += fabsf(rec.fw[a]);
+    }
+    tr.bp = bp;
+    tr.bq = bq;
+    tr.ncols = bp * bq;
+    tr.depth = depth;
+    tr.nbb = nbb;
+    tr.kactp = kactp;
+    tr.m_bp = small_div(max(bp, 1)).m;
+    tr.m_kactp = small_div(max(kactp, 1)).m;
+    tr.m_bdx = small_div(max(bdim[0], 1)).m;
+    tr.m_bdy = small_div(max(bdim[1], 1)).m;
+    // every voxel with weight for a pixel of the tile lies within |m.(v - c0)| < |m|_1 and,
+    // along the in-plane axes, within the tile's extent widened by |u|_1, |w|_1 (the margins
+    // cover FP32 rounding and the pose rigidity tolerance)
+    const float slop = rec.slop;
+    tr.thr_n = fabsf(rec.fm[0]) + fabsf(rec.fm[1]) + fabsf(rec.fm[2]) + slop;
+    tr.thr_u = l1u + 0.02f + slop;
+    tr.thr_v = l1w + 0.02f + slop;
+    tr.hi_u = (float)(i1 - i0) * rec.lu + tr.thr_u;
+    tr.hi_v = (float)(j1 - j0) * rec.lw + tr.thr_v;
+    tr.inv_md = 1.0f / rec.fm[dax];
+    tr.half = rec.half;
+}
+
+// Slots phase: the table entry of every (box brick, bin) pair, -1 past the surviving bins.  The
+// table reads are issued first (`load_slots`, into registers) and written to LDS after the
+// classification (`store_slots`), so that their latency overlaps that ALU work.
+constexpr int kSlotsPerThread = kSlotsMax / 256;
+static_assert(kSlotsMax % 256 == 0, "slot rows are spread evenly over 256 threads");
+
+__device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& tr, int (&sl)[kSlotsPerThread]) {
+    const int kact = ui(rec.kact), kactp = ui(tr.kactp), n = ui(tr.nbb) * kactp;
+    const int bdx = ui(tr.bdim[0]), bdy = ui(tr.bdim[1]);
+    const int bx0 = ui(tr.blo[0]), by0 = ui(tr.blo[1]), bz0 = ui(tr.blo[2]);
+    const SmallDiv dk = usd(tr.m_kactp, kactp), dx = usd(tr.m_bdx, bdx), dy = usd(tr.m_bdy, bdy);
+    const gptr<const int32_t> table = global(rec.vol.table);
+    const int64_t nbricks = rec.vol.nbricks;
+    const int nbx = ui(rec.vol.nbx), nby = ui(rec.vol.nby);
+#pragma unroll
+    for (int i = 0; i < kSlotsPerThread; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        const int bb = sdiv(e, dk), k = e - bb * kactp;
+        sl[i] = -1;
+        if (e < n && k < kact) {
+            const int byz = sdiv(bb, dx), bx = bb - byz * bdx;
+            const int bz = sdiv(byz, dy), by = byz - bz * bdy;
+            const int64_t brick = ((int64_t)(bz0 + bz) * nby + (by0 + by)) * nbx + (bx0 + bx);
+            sl[i] = table[(int64_t)rec.act_bin[k] * nbricks + brick];
+        }
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void store_slots(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl,
+                                            const int (&sl)[kSlotsPerThread]) {
+    const int n = ui(tr.nbb) * ui(tr.kactp);
+    float2 sc[kSlotsPerThread];
+    if constexpr (DT == DARE_FP8_E4M3) {
+        const gptr<const float2> scales = global(rec.vol.scales);
+#pragma unroll
+        for (int i = 0; i < kSlotsPerThread; ++i) {
+            sc[i] = make_float2(0.0f, 0.0f);
+            if (sl[i] >= 0) sc[i] = *(const float2*)&scales[sl[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kSlotsPerThread; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e < n) {
+            tl.slot[e] = sl[i];
+            if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = sc[i];
+        }
+    }
+}
+
+// A stored pair read in the folded form of its storage: the blend runs on the coded value and
+// the affine map of the storage is applied once to the blended value (the blend is a convex
+// combination, so this is the blend of the decoded values).
+template <int DT>
+__device__ __forceinline__ void folded(typename Pair<DT>::T p, float2 sc, float& v, float& c) {
+    if constexpr (DT == DARE_F32) {
+        v = p.x;
+        c = p.y;
+    } else if constexpr (DT == DARE_BF16) {
+        v = __uint_as_float(p << 16);
+        c = __uint_as_float(p & 0xFFFF0000u);
+    } else if constexpr (DT == DARE_F16) {
+        v = f16_to_f32(p & 0xFFFFu);
+        c = f16_to_f32(p >> 16);
+    } else {
+        v = e4m3_to_f32(p & 0xFFu) * sc.x;
+        c = e4m3_to_f32(p >> 8) * sc.y;
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ float unfold(float q) {
+    if constexpr (DT == DARE_F32) return q;
+    else if constexpr (DT == DARE_FP8_E4M3) return q + 127.5f;
+    else return q * 127.5f + 127.5f;
+}
+
+// First voxel of the run of column (vp, vq): the first whole voxel above centre - half, where
+// centre is the plane's coordinate along DAX at the column (FP32 about the tile's origin c0).
+// The column's voxels with |m.(v - c0)| < thr_n are among the depth voxels from there.
+template <int DAX>
+__device__ __forceinline__ int run_start(const float (&c0)[3], const float (&m)[3], float inv_md, float half, int vp,
+                                         int vq) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const float centre = c0[DAX] - (m[PAX] * ((float)vp - c0[PAX]) + m[QAX] * ((float)vq - c0[QAX])) * inv_md;
+    return (int)floorf(centre - half) + 1;
+}
+
+// Voxels phase, first part: one thread per box column (p, q) walks the column's run along the
+// dominant axis; each voxel is tested against the tile's slab and lateral extent (the test terms
+// of the column computed once, the axis term added per voxel).  Voxels outside (or outside the
+// grid) get (0, 0); the others are appended to the gather list (one LDS counter update per wave
+// and voxel of the run).
+template <int DT, int DAX>
+__device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const int ncols = ui(tr.ncols), depth = ui(tr.depth), bp = ui(tr.bp);
+    const SmallDiv dbp = usd(tr.m_bp, bp);
+    const int lo_p = ui(tr.lo[PAX]), lo_q = ui(tr.lo[QAX]), lo_d = ui(tr.lo[DAX]), hi_d = ui(tr.hi[DAX]);
+    const int n[3] = {ui(rec.vol.n[0]), ui(rec.vol.n[1]), ui(rec.vol.n[2])};
+    const int blo[3] = {ui(tr.blo[0]), ui(tr.blo[1]), ui(tr.blo[2])};
+    const int bdx = ui(tr.bdim[0]), bdy = ui(tr.bdim[1]);
+    float m[3], fu[3], fw[3], c0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m[a] = uf(rec.fm[a]);
+        fu[a] = uf(rec.fu[a]);
+        fw[a] = uf(rec.fw[a]);
+        c0[a] = uf(tr.c0[a]);
+    }
+    const float thr_n = uf(tr.thr_n), thr_u = uf(tr.thr_u), thr_v = uf(tr.thr_v), hi_u = uf(tr.hi_u), hi_v = uf(tr.hi_v);
+    const float inv_md = uf(tr.inv_md), half = uf(tr.half);
+    const int lane = (int)threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int cb = 0; cb < ncols; cb += 256) {
+        const int col = cb + (int)threadIdx.x;
+        const bool live = col < ncols;
+        const int cq = sdiv(col, dbp), cp = col - (int)__umul24((uint32_t)cq, (uint32_t)bp);
+        const int vp = lo_p + cp, vq = lo_q + cq;
+        const int rs = run_start<DAX>(c0, m, inv_md, half, vp, vq);
+        if (live) tl.rs[col] = (short)(rs - lo_d);
+        const bool col_in = live && (unsigned)vp < (unsigned)n[PAX] && (unsigned)vq < (unsigned)n[QAX];
+        const float dp = (float)vp - c0[PAX], dq = (float)vq - c0[QAX];
+        const float bn = m[PAX] * dp + m[QAX] * dq;
+        const float bu = fu[PAX] * dp + fu[QAX] * dq;
+        const float bw = fw[PAX] * dp + fw[QAX] * dq;
+        int vb[3];
+        vb[PAX] = vp;
+        vb[QAX] = vq;
+        vb[DAX] = 0;
+        const int e0 = (int)__umul24((uint32_t)col, (uint32_t)depth);
+        for (int k = 0; k < depth; ++k) {
+            const int vd = rs + k;
+            vb[DAX] = vd;
+            const float dd = (float)vd - c0[DAX];
+            const float dn = bn + m[DAX] * dd, du = bu + fu[DAX] * dd, dv = bw + fw[DAX] * dd;
+            const bool pass = col_in && vd >= lo_d && vd <= hi_d && (unsigned)vd < (unsigned)n[DAX] &&
+                              fabsf(dn) < thr_n && du > -thr_u && du < hi_u && dv > -thr_v && dv < hi_v;
+            const int e = e0 + k;
+            if (live && !pass) tl.V[e] = make_float2(0.0f, 0.0f);
+            const unsigned long long mask = __ballot(pass);
+            if (mask == 0ull) continue;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&tl.nlist, (int)__popcll(mask));
+            base = __shfl(base, 0);
+            if (pass) {
+                const int bb = (int)__umul24((uint32_t)((int)__umul24((uint32_t)((vb[2] >> 3) - blo[2]), (uint32_t)bdy) +
+                                                        ((vb[1] >> 3) - blo[1])),
+                                             (uint32_t)bdx) +
+                               ((vb[0] >> 3) - blo[0]);
+                tl.list[base + (int)__popcll(mask & below)] =
+                    e | (brick_local(vb[0], vb[1], vb[2]) << 11) | (bb << 20);
+            }
+        }
+    }
+}
+
+// Pairs of every surviving bin for U listed voxels of a thread: the slot rows of NB bins are
+// read from LDS 4 at a time, then the NB x U pair loads are issued before any is used.  A pair
+// that is not loaded (no slot, or no voxel) stays zero and adds nothing.
+template <int DT, int U>
+__device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& tl, const bool (&ok)[U],
+                                       const int (&row)[U], const int (&loc)[U], float (&A)[U], float (&B)[U]) {
+    using PT = Pair<DT>;
+    using T = typename PT::T;
+    constexpr int NB = bins_per_round<DT>();
+    const gptr<const T> data = global((const T*)rec.vol.data);
+    const int kact = ui(rec.kact);
+#pragma unroll
+    for (int u = 0; u < U; ++u) A[u] = B[u] = 0.0f;
+    for (int k0 = 0; k0 < kact; k0 += NB) {
+        int sl[U][NB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int g = 0; g < NB; g += 4) {
+                int4 s4 = make_int4(-1, -1, -1, -1);
+                if (ok[u]) s4 = *reinterpret_cast<const int4*>(&tl.slot[row[u] + k0 + g]);
+                sl[u][g] = s4.x;
+                sl[u][g + 1] = s4.y;
+                sl[u][g + 2] = s4.z;
+                sl[u][g + 3] = s4.w;
+            }
+        T pr[U][NB];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int g = 0; g < NB; ++g) {
+                pr[u][g] = T{};
+                if (sl[u][g] >= 0) pr[u][g] = *(const T*)&data[((uint32_t)sl[u][g] << 9) | (uint32_t)loc[u]];
+            }
+#pragma unroll
+        for (int g = 0; g < NB; ++g) {
+            const float w = uf(rec.act_w[k0 + g]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                float2 sc = make_float2(0.0f, 0.0f);
+                if constexpr (DT == DARE_FP8_E4M3) sc = tl.scale[row[u] + k0 + g];
+                float v, c;
+                folded<DT>(pr[u][g], sc, v, c);
+                const float wc = w * c;
+                A[u] = __builtin_fmaf(wc, v, A[u]);
+                B[u] = B[u] + wc;
+            }
+        }
+    }
+}
+
+// Voxels phase, second part: every listed voxel's surviving bins gathered and blended into
+// (V_v, 1), or (0, 0) when none holds a sample.
+template <int DT>
+__device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
+    constexpr int U = items_per_round<DT>();
+    const int nlist = ui(tl.nlist), kactp = ui(tr.kactp);
+    for (int base = 0; base < nlist; base += U * 256) {
+        bool ok[U];
+        int row[U], loc[U], ent[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            ok[u] = i < nlist;
+            ent[u] = ok[u] ? tl.list[i] : 0;
+            row[u] = (int)__umul24((uint32_t)ent[u] >> 20, (uint32_t)kactp);
+            loc[u] = (ent[u] >> 11) & 511;
+        }
+        float A[U], B[U];
+        gather<DT, U>(rec, tl, ok, row, loc, A, B);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const bool valid = B[u] > 0.0f;
+            tl.V[ent[u] & 2047] =
+                valid ? make_float2(unfold<DT>(A[u] * __builtin_amdgcn_rcpf(B[u])), 1.0f) : make_float2(0.0f, 0.0f);
+        }
+    }
+}
+
+// Pixels phase of a staged tile: FP64 position, the cell's 8 (V, valid) values from LDS (two
+// adjacent run entries per cell column), tent weights.
+template <int DT, int DAX>
+__device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec& tr, const TileLds<DT>& tl) {
+    constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
+    const int T = ui(rec.tile), W = ui(rec.W);
+    const int i0 = ui(tr.i0), j0 = ui(tr.j0), ni = ui(tr.ni), nj = ui(tr.nj);
+    const int lo_p = ui(tr.lo[PAX]), lo_q = ui(tr.lo[QAX]), lo_d = ui(tr.lo[DAX]);
+    const int bp = ui(tr.bp), bq = ui(tr.bq), depth = ui(tr.depth);
+    const int n[3] = {ui(rec.vol.n[0]), ui(rec.vol.n[1]), ui(rec.vol.n[2])};
+    const gptr<float> outp = global(rec.out);
+    double c00[3], ex[3], ey[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c00[a] = ud(rec.c00[a]);
+        ex[a] = ud(rec.ex[a]);
+        ey[a] = ud(rec.ey[a]);
+    }
+    const int shift = T == kTileBig ? 5 : 4;
+    const int per = (T * T) >> 8;
+    for (int r = 0; r < per; ++r) {
+        const int idx = (int)threadIdx.x + (r << 8);
+        const int li = idx & (T - 1), lj = idx >> shift;
+        if (li >= ni || lj >= nj) continue;
+        const int i = i0 + li, j = j0 + lj;
+        const gptr<float> out = outp + (size_t)j * W + i;
+        const double di = (double)i, dj = (double)j;
+        double c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] = fma(dj, ey[a], fma(di, ex[a], c00[a]));
+        if (!(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] && c[2] >= -1.0 &&
+              c[2] < (double)n[2])) {
+            *out = __builtin_nanf("");
+            continue;
+        }
+        int b[3];
+        float fr[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double f = floor(c[a]);
+            b[a] = (int)f;
+            fr[a] = (float)(c[a] - f);
+        }
+        // the cell's columns lie in the box and its two layers in each column's run; the clamps
+        // only keep the LDS reads in bounds
+        const int cp = min(max(b[PAX] - lo_p, 0), bp - 2), cq = min(max(b[QAX] - lo_q, 0), bq - 2);
+        const int col0 = (int)__umul24((uint32_t)cq, (uint32_t)bp) + cp;
+        const int cols[4] = {col0, col0 + 1, col0 + bp, col0 + bp + 1};
+        float2 lov[4], hiv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = min(max(b[DAX] - lo_d - (int)tl.rs[cols[q]], 0), depth - 2);
+            const int e = (int)__umul24((uint32_t)cols[q], (uint32_t)depth) + k;
+            lov[q] = tl.V[e];
+            hiv[q] = tl.V[e + 1];
+        }
+        const float wp[2] = {1.0f - fr[PAX], fr[PAX]}, wq[2] = {1.0f - fr[QAX], fr[QAX]};
+        const float wd[2] = {1.0f - fr[DAX], fr[DAX]};
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float wpq = wp[q & 1] * wq[q >> 1];
+            const float t0 = wpq * wd[0], t1 = wpq * wd[1];
+            num = __builtin_fmaf(t0, lov[q].x, num);
+            den = __builtin_fmaf(t0, lov[q].y, den);
+            num = __builtin_fmaf(t1, hiv[q].x, num);
+            den = __builtin_fmaf(t1, hiv[q].y, den);
+        }
+        *out = den > 0.0f ? num * __builtin_amdgcn_rcpf(den) : __builtin_nanf("");
+    }
+}
+
+// A 16 x 16 tile of a request that gathers per pixel (mode 2) or has no surviving bin (mode 0):
+// one pixel per thread.
+template <int DT>
+__device__ __forceinline__ void direct_tile(const SliceRec& rec, int t) {
+    const int tiles_x = ui(rec.tiles_x);
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int i = tx * 16 + ((int)threadIdx.x & 15), j = ty * 16 + ((int)threadIdx.x >> 4);
+    if (i >= rec.W || j >= rec.H) return;
+    const gptr<float> out = global(rec.out) + (size_t)j * rec.W + i;
+    const int n[3] = {rec.vol.n[0], rec.vol.n[1], rec.vol.n[2]};
+    double c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = fma((double)j, rec.ey[a], fma((double)i, rec.ex[a], rec.c00[a]));
+    if (rec.mode == 0 || !(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] &&
+                           c[2] >= -1.0 && c[2] < (double)n[2])) {
+        *out = __builtin_nanf("");
+        return;
+    }
+    *out = pixel_direct<DT, 1>(rec.vol, rec, rec.kact, c);
+}
+
+// Every pixel of a staged tile that has nothing in reach: NaN.
+__device__ __forceinline__ void nan_tile(const SliceRec& rec, const TileRec& tr) {
+    const int T = ui(rec.tile), shift = T == kTileBig ? 5 : 4, per = (T * T) >> 8;
+    const int i0 = ui(tr.i0), j0 = ui(tr.j0), ni = ui(tr.ni), nj = ui(tr.nj), W = ui(rec.W);
+    const gptr<float> out = global(rec.out);
+    for (int r = 0; r < per; ++r) {
+        const int idx = (int)threadIdx.x + (r << 8);
+        const int li = idx & (T - 1), lj = idx >> shift;
+        if (li < ni && lj < nj) out[(size_t)(j0 + lj) * W + (i0 + li)] = __builtin_nanf("");
+    }
+}
+
+// One staged tile; `rec` and `tr` are the request's and the tile's records (LDS or global).
+template <int DT>
+__device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
+    if (ui(tr.mode) != 1) {
+        nan_tile(rec, tr);
+        return;
+    }
+    int sl[kSlotsPerThread];
+    load_slots(rec, tr, sl);
+    if (threadIdx.x == 0) tl.nlist = 0;
+    __syncthreads();
+    const int dax = ui(rec.dax);
+    switch (dax) {
+        case 0: classify_voxels<DT, 0>(rec, tr, tl); break;
+        case 1: classify_voxels<DT, 1>(rec, tr, tl); break;
+        default: classify_voxels<DT, 2>(rec, tr, tl); break;
+    }
+    store_slots<DT>(rec, tr, tl, sl);
+    __syncthreads();
+    gather_voxels<DT>(rec, tr, tl);
+    __syncthreads();
+    switch (dax) {
+        case 0: stage_pixels<DT, 0>(rec, tr, tl); break;
+        case 1: stage_pixels<DT, 1>(rec, tr, tl); break;
+        default: stage_pixels<DT, 2>(rec, tr, tl); break;
+    }
+}
+
+// Single reslice: one workgroup per 16 x 16 tile; wave 0 evaluates the request setup, then lane
+// 0 the tile's record.
+template <int DT>
+__global__ void __launch_bounds__(256) k_reslice_tile(const VolDev* __restrict__ vd, SliceArgs s) {
+    __shared__ TileLds<DT> tl;
+    __shared__ SliceRec rec;
+    __shared__ TileRec tr;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    if (threadIdx.x < 64) {
+        int mode = 0;
+        (void)request_setup(vd, s, rec, 16, &mode);
+        if (threadIdx.x == 0 && mode == 1) compute_tile(rec, 0, t, tr);
+    }
+    __syncthreads();
+    if (ui(rec.mode) == 1) run_tile<DT>(rec, tr, tl);
+    else direct_tile<DT>(rec, t);
+}
+
+// Batch setup: one wave per request.  The request record, then the records of its tiles (one
+// lane each) when it stages them; the units are appended: staged tiles' records from the front
+// of `tiles` (counts[0]), the other requests' units (request, tile) from the back of `units`
+// (counts[2]: entry k at cap - 1 - k), so that each kind runs in a kernel of its own.
+__global__ void __launch_bounds__(64) k_tiles_setup(const BatchReq* __restrict__ reqs, SliceRec* __restrict__ recs,
+                                                    int2* __restrict__ units, TileRec* __restrict__ tiles,
+                                                    int* __restrict__ counts, int cap) {
+    __shared__ SliceRec rec;
+    const int nreq = counts[1];
+    for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
+        int mode = 0;
+        int nt = request_setup(reqs[r].vol, reqs[r].s, rec, kTileBig, &mode);
+        nt = __shfl(nt, 0);
+        mode = __shfl(mode, 0);
+        __syncthreads();
+        {   // the record to global memory (the tile kernels read it)
+            const int* src = reinterpret_cast<const int*>(&rec);
+            int* dst = reinterpret_cast<int*>(recs + r);
+            for (int w = threadIdx.x; w < (int)(sizeof(SliceRec) / sizeof(int)); w += 64) dst[w] = src[w];
+        }
+        // a request with no surviving bin is filled with NaN in flat runs of kFillRun pixels
+        // (fewer units than its tiles), marked by a negative tile index
+        if (mode == 0) nt = (int)(((int64_t)reqs[r].s.W * reqs[r].s.H + kFillRun - 1) / kFillRun);
+        int base = 0;
+        if (threadIdx.x == 0) base = atomicAdd(counts + (mode == 1 ? 0 : 2), nt);
+        base = __shfl(base, 0);
+        for (int k = threadIdx.x; k < nt; k += 64) {
+            if (mode == 1) compute_tile(rec, r, k, tiles[base + k]);
+            else units[cap - 1 - (base + k)] = make_int2(r, mode == 0 ? ~k : k);
+        }
+        __syncthreads();
+    }
+}
+
+// Batch tiles: a persistent grid over the staged tiles.  XCD x (workgroups are dealt to the 8
+// XCDs round-robin) takes the x-th eighth of the list, in order, so that neighbouring tiles of a
+// request, which share the voxels along their edges, are read through one L2.  Both records are
+// read through scalar loads.
+template <int DT>
+__global__ void __launch_bounds__(256) k_tiles(const SliceRec* __restrict__ recs, const TileRec* __restrict__ tiles,
+                                               const int* __restrict__ counts) {
+    __shared__ TileLds<DT> tl;
+    const int n = counts[0];
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int beg = (int)((int64_t)n * xcd >> 3), end = (int)((int64_t)n * (xcd + 1) >> 3);
+    for (int u = beg + (int)(blockIdx.x >> 3); u < end; u += per) {
+        const TileRec& tr = tiles[u];
+        const SliceRec& rec = recs[ui(tr.r)];
+        run_tile<DT>(rec, tr, tl);
+        __syncthreads();
+    }
+}
+
+// Batch units of requests that gather per pixel (16 x 16 tiles) or have no surviving bin (runs of
+// kFillRun pixels, negative tile index): the back of the unit list.
+template <int DT>
+__global__ void __launch_bounds__(256) k_tiles_direct(const SliceRec* __restrict__ recs,
+                                                      const int2* __restrict__ units, const int* __restrict__ counts,
+                                                      int cap) {
+    const int n = counts[2];
+    for (int u = blockIdx.x; u < n; u += gridDim.x) {
+        const int2 un = units[cap - 1 - u];
+        const int r = ui(un.x), t = ui(un.y);
+        const SliceRec& rec = recs[r];
+        if (t < 0) {
+            const int64_t npx = (int64_t)rec.W * rec.H, p0 = (int64_t)(~t) * kFillRun;
+            const int64_t p1 = p0 + kFillRun < npx ? p0 + kFillRun : npx;
+            const gptr<float> out = global(rec.out);
+            for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) out[p] = __builtin_nanf("");
+        } else {
+            direct_tile<DT>(rec, t);
+        }
+    }
+}
+
+// Workgroups of the persistent tile kernel: as many as the device holds at once (a static
+// share of the units per workgroup), rounded down to whole rounds over the 8 XCDs.
+template <int DT>
+int tiles_grid() {
+    static int grid[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (grid[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiles<DT>, 256, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 8;
+        grid[dev] = std::max(8, per_cu * cus / 8 * 8);
+    }
+    return grid[dev];
+}
+
+}  // namespace
+
+static_assert(sizeof(SliceRec) % sizeof(int) == 0, "the record is copied in 4-byte words");
+
+hipError_t launch_reslice_tile(const VolDev* vd, int dtype, const SliceArgs& s, hipStream_t stream) {
+    const int64_t units = (int64_t)((s.W + 15) / 16) * ((s.H + 15) / 16);
+    if (units > INT32_MAX) return hipErrorInvalidValue;
+#define L(D) hipLaunchKernelGGL(k_reslice_tile<D>, dim3((unsigned)units), dim3(256), 0, stream, vd, s)
+    DARE_DISPATCH_DT(dtype, L)
+#undef L
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_batch(int dtype, const BatchReq* reqs, SliceRec* recs, int2* units, TileRec* tiles,
+                              int* counts, int nreq_max, int cap, hipStream_t stream) {
+    const int sgrid = nreq_max < 1024 ? (nreq_max > 0 ? nreq_max : 1) : 1024;
+    hipLaunchKernelGGL(k_tiles_setup, dim3(sgrid), dim3(64), 0, stream, reqs, recs, units, tiles, counts, cap);
+#define L(D)                                                                                                   \
+    hipLaunchKernelGGL(k_tiles<D>, dim3(tiles_grid<D>()), dim3(256), 0, stream, recs, tiles, counts);          \
+    hipLaunchKernelGGL(k_tiles_direct<D>, dim3(1024), dim3(256), 0, stream, recs, units, counts, cap)
+    DARE_DISPATCH_DT(dtype, L)
+#undef L
+    return hipGetLastError();
+}
+
+int64_t tile_units_max(int W, int H) { return (int64_t)((W + 15) / 16) * ((H + 15) / 16); }
+
+}  // namespace dare

@@ -95,7 +95,7 @@ def test_small_budget_queues_and_completes(env):
     ref = _alone(dare, torch, vols, reqs)
     cfg = dict(n_streams=2, max_tick_requests=4, max_tick_pixels=1 << 16, max_queue=64)
     largest = max(W * H for (_, _, W, H, _) in reqs) * 4
-    arena = _table_bytes(dare, cfg) + 2 * largest + 4096
+    arena = _table_bytes(dare, cfg, vols[0]) + 2 * largest + 4096
     got, times, st = _serve(dare, torch, vols, reqs, arena, **cfg)
     for k in range(len(reqs)):
         assert np.array_equal(got[k], ref[k], equal_nan=True), k
@@ -106,15 +106,20 @@ def test_small_budget_queues_and_completes(env):
     assert n_ticks >= total // (2 * largest + 4096), (n_ticks, total, largest)
 
 
-def _table_bytes(dare, cfg):
-    """Smallest arena that the server accepts, found by bisection on creation."""
-    lo, hi = 1 << 12, 1 << 28
+def _table_bytes(dare, cfg, vol):
+    """Smallest arena in which a server takes its first volume (the streams' workspaces are laid
+    out then), found by bisection."""
+    lo, hi = 1 << 10, 1 << 28
     while lo < hi:
         mid = (lo + hi) // 2
         try:
             s = dare.Server(mid, **cfg)
+            try:
+                s.add_volume(vol)
+                hi = mid
+            except dare.DareError:
+                lo = mid + 1
             s.close()
-            hi = mid
         except dare.DareError:
             lo = mid + 1
     return lo
@@ -124,7 +129,7 @@ def test_submit_rejects_what_can_never_fit(env):
     dare, torch, wl, vols = env
     note("server rejects oversized requests")
     cfg = dict(n_streams=1, max_tick_requests=2, max_tick_pixels=4096)
-    srv = dare.Server(_table_bytes(dare, cfg) + 64 * 64 * 4 + 1024, **cfg)
+    srv = dare.Server(_table_bytes(dare, cfg, vols[0]) + 64 * 64 * 4 + 1024, **cfg)
     vid = srv.add_volume(vols[0])
     big = torch.empty((128, 128), dtype=torch.float32, pin_memory=True)
     with pytest.raises(dare.DareError) as e:
