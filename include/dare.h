@@ -205,6 +205,23 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
                                float* const* outs_dev, int32_t n, void* workspace_dev,
                                uint64_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): dare_reslice_batch
+ * with its workspace in a device buffer the library holds, of
+ * DARE_NOALLOC_WORKSPACE_BYTES on each device it runs on, kept until the
+ * process ends (its address is taken once per device, on the first call there).
+ * The call allocates nothing; the request table is copied from pageable host
+ * memory, so the call returns once the copy has read it.  Every call on a device
+ * shares that device's buffer: calls that overlap on one device (other streams,
+ * other threads) race and must not be issued; successive calls on one stream
+ * are safe.  Results are those of dare_reslice_batch, bit for bit.
+ * Errors: as dare_reslice_batch; BUDGET (nothing launched) when the batch needs
+ * more than DARE_NOALLOC_WORKSPACE_BYTES of workspace (see
+ * dare_reslice_batch_workspace_bytes). */
+#define DARE_NOALLOC_WORKSPACE_BYTES (32ull << 20)
+dare_status dare_reslice_batch_noalloc(const dare_volume* const* vols, const dare_slice_spec* specs,
+                                       float* const* outs_dev, int32_t n, void* stream);
+
 /* Bounding box of the frames (Sec. 2.1: computed from the collected
  * transducer positions): the axis-aligned box of every frame's four corner
  * pixel centres, origin = its minimum corner, dims = ceil(extent / h) + 1.

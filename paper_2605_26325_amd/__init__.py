@@ -110,6 +110,7 @@ def _load():
         "dare_reslice": (ct.c_int, [V, ct.POINTER(SliceSpec), P, P]),
         "dare_reslice_batch_workspace_bytes": (U64, [ct.POINTER(V), ct.POINTER(SliceSpec), I32]),
         "dare_reslice_batch": (ct.c_int, [ct.POINTER(V), ct.POINTER(SliceSpec), ct.POINTER(P), I32, P, U64, P]),
+        "dare_reslice_batch_noalloc": (ct.c_int, [ct.POINTER(V), ct.POINTER(SliceSpec), ct.POINTER(P), I32, P]),
         "dare_bounds_from_frames": (ct.c_int, [P, I32, I32, I32, ct.POINTER(D), ct.POINTER(D), D,
                                                ct.POINTER(Geometry)]),
         "dare_volume_get_info": (ct.c_int, [V, ct.POINTER(VolumeInfo)]),
@@ -244,6 +245,18 @@ def dare_reslice_batch_workspace_bytes(vols, specs) -> int:
     hv = (ct.c_void_p * n)(*[v.handle for v in vols])
     hs = (SliceSpec * n)(*specs)
     return int(lib.dare_reslice_batch_workspace_bytes(hv, hs, n))
+
+
+NOALLOC_WORKSPACE_BYTES = 32 << 20     # DARE_NOALLOC_WORKSPACE_BYTES
+
+
+def dare_reslice_batch_noalloc(vols, specs, outs, stream=None) -> int:
+    """dare_reslice_batch with the library's own per-device workspace (allocates nothing)."""
+    n = len(vols)
+    hv = (ct.c_void_p * n)(*[v.handle for v in vols])
+    hs = (SliceSpec * n)(*specs)
+    ho = (ct.c_void_p * n)(*[o.data_ptr() for o in outs])
+    return _check(lib.dare_reslice_batch_noalloc(hv, hs, ho, n, _stream(stream)), "dare_reslice_batch_noalloc")
 
 
 def dare_reslice_batch(vols, specs, outs, workspace, stream=None) -> int:

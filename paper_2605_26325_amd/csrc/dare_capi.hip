@@ -700,6 +700,57 @@ dare_status dare_reslice_batch(const dare_volume* const* vols, const dare_slice_
     return run_batch(vols, specs, outs_dev, n, (char*)workspace_dev, stream, upload);
 }
 
+}  // extern "C"
+
+// Workspace of dare_reslice_batch_noalloc: one copy per device, in device memory until the
+// process ends.  In host code this name is not a device address: every use goes through the
+// per-device address taken with hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[DARE_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on `device` (current), taken on the first call there.
+dare_status scratch_address(int device, char** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {nullptr};
+    if (device < 0 || device >= kMaxDevices) return DARE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DARE_ERR_HIP;
+        addr[device] = p;
+    }
+    *out = (char*)addr[device];
+    return DARE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dare_status dare_reslice_batch_noalloc(const dare_volume* const* vols, const dare_slice_spec* specs,
+                                       float* const* outs_dev, int32_t n, void* stream_) {
+    if (n == 0 && vols && specs && outs_dev) return DARE_OK;
+    int device = -1;
+    uint64_t needed = 0;
+    dare_status st = check_batch(vols, specs, outs_dev, n, &device, &needed);
+    if (st != DARE_OK) return st;
+    if (needed == 0) return DARE_ERR_INVALID_ARG;
+    if (needed > DARE_NOALLOC_WORKSPACE_BYTES) return DARE_ERR_BUDGET;
+    DeviceGuard dg(device);
+    char* ws = nullptr;
+    st = scratch_address(device, &ws);
+    if (st != DARE_OK) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    // the request table goes from pageable host memory: no pinned staging to allocate
+    auto upload = [&](char* dst, const char* src, uint64_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+    };
+    return run_batch(vols, specs, outs_dev, n, ws, stream, upload);
+}
+
 dare_status dare_bounds_from_frames(const float* poses, int32_t n, int32_t w, int32_t h, const double pitch_mm[2],
                                     const double calib[16], double spacing_mm, dare_geometry* out) {
     if (!poses || n <= 0 || w <= 0 || h <= 0 || !pitch_mm || !calib || !out || !(spacing_mm > 0.0))
