@@ -41,6 +41,8 @@ namespace {
 constexpr int kItemsMax = 2048;      // staged voxels (box columns x run depth) per tile
 constexpr int kColsMax = 1024;       // box columns per tile
 constexpr int kSlotsMax = 1280;      // (box brick, bin) table entries per tile
+constexpr int kRunSpan = 127;        // box voxels along the dominant axis, less one, at most
+constexpr int kThreadsBatch = 256;   // threads of a batch workgroup
 constexpr int kTileBig = 32;         // batched tile edge where the box fits
 constexpr int kFillRun = 4096;       // pixels per unit of a batched request that is all NaN
 
@@ -56,8 +58,8 @@ template <int DT>
 struct TileLds {
     alignas(16) int slot[kSlotsMax];                      // [box brick][bin], rows of kactp
     float2 scale[DT == DARE_FP8_E4M3 ? kSlotsMax : 1];    // FP8 value and count scales per slot
-    short rs[kColsMax];                                   // first voxel of each column's run, less lo_d
-    float2 V[kItemsMax];                                  // (V_v, 1) or (0, 0), [column][run]
+    signed char rs[kColsMax];                             // first voxel of each column's run, less lo_d
+    float V[kItemsMax];                                   // V_v, or NaN where not valid, [column][run]
     int list[kItemsMax];                                  // voxels to gather: e | local << 11 | brick << 20
     int nlist;
 };
@@ -97,7 +99,8 @@ __device__ __forceinline__ bool tile_fits(const SliceRec& rec, int T) {
     }
     const int64_t cols = (int64_t)e[pax] * e[qax];
     const int kactp = (rec.kact + 7) & ~7;
-    return cols <= kColsMax && cols * rec.depth <= kItemsMax && nbb * kactp <= kSlotsMax;
+    return cols <= kColsMax && cols * rec.depth <= kItemsMax && nbb * kactp <= kSlotsMax && e[dax] <= kRunSpan &&
+           rec.depth <= kRunSpan;
 }
 
 // One wave: the per-request setup of a radius-1 reslice, in FP64 on the device, into `rec`.
@@ -189,8 +192,8 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
     const int nbb = bdim[0] * bdim[1] * bdim[2];
     // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
     // check only keeps the LDS accesses in bounds
-    const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kItemsMax && bp * bq <= kColsMax &&
-                      bp * bq * depth <= kItemsMax && nbb * kactp <= kSlotsMax;
+    const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kRunSpan && bp * bq <= kColsMax &&
+                      bp * bq * depth <= kItemsMax && nbb * kactp <= kSlotsMax && hi[dax] - lo[dax] <= kRunSpan;
     tr.r = r;
     tr.mode = (!empty && fits) ? 1 : 0;
     tr.i0 = i0;
@@ -234,10 +237,11 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
 // Slots phase: the table entry of every (box brick, bin) pair, -1 past the surviving bins.  The
 // table reads are issued first (`load_slots`, into registers) and written to LDS after the
 // classification (`store_slots`), so that their latency overlaps that ALU work.
-constexpr int kSlotsPerThread = kSlotsMax / 256;
-static_assert(kSlotsMax % 256 == 0, "slot rows are spread evenly over 256 threads");
+template <int NT>
+constexpr int slots_per_thread() { return (kSlotsMax + NT - 1) / NT; }
 
-__device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& tr, int (&sl)[kSlotsPerThread]) {
+template <int NT>
+__device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& tr, int (&sl)[slots_per_thread<NT>()]) {
     const int kact = ui(rec.kact), kactp = ui(tr.kactp), n = ui(tr.nbb) * kactp;
     const int bdx = ui(tr.bdim[0]), bdy = ui(tr.bdim[1]);
     const int bx0 = ui(tr.blo[0]), by0 = ui(tr.blo[1]), bz0 = ui(tr.blo[2]);
@@ -246,8 +250,8 @@ __device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& t
     const int64_t nbricks = rec.vol.nbricks;
     const int nbx = ui(rec.vol.nbx), nby = ui(rec.vol.nby);
 #pragma unroll
-    for (int i = 0; i < kSlotsPerThread; ++i) {
-        const int e = (int)threadIdx.x + 256 * i;
+    for (int i = 0; i < slots_per_thread<NT>(); ++i) {
+        const int e = (int)threadIdx.x + NT * i;
         const int bb = sdiv(e, dk), k = e - bb * kactp;
         sl[i] = -1;
         if (e < n && k < kact) {
@@ -259,22 +263,23 @@ __device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& t
     }
 }
 
-template <int DT>
+template <int DT, int NT>
 __device__ __forceinline__ void store_slots(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl,
-                                            const int (&sl)[kSlotsPerThread]) {
+                                            const int (&sl)[slots_per_thread<NT>()]) {
+    constexpr int SP = slots_per_thread<NT>();
     const int n = ui(tr.nbb) * ui(tr.kactp);
-    float2 sc[kSlotsPerThread];
+    float2 sc[SP];
     if constexpr (DT == DARE_FP8_E4M3) {
         const gptr<const float2> scales = global(rec.vol.scales);
 #pragma unroll
-        for (int i = 0; i < kSlotsPerThread; ++i) {
+        for (int i = 0; i < SP; ++i) {
             sc[i] = make_float2(0.0f, 0.0f);
             if (sl[i] >= 0) sc[i] = *(const float2*)&scales[sl[i]];
         }
     }
 #pragma unroll
-    for (int i = 0; i < kSlotsPerThread; ++i) {
-        const int e = (int)threadIdx.x + 256 * i;
+    for (int i = 0; i < SP; ++i) {
+        const int e = (int)threadIdx.x + NT * i;
         if (e < n) {
             tl.slot[e] = sl[i];
             if constexpr (DT == DARE_FP8_E4M3) tl.scale[e] = sc[i];
@@ -325,7 +330,7 @@ __device__ __forceinline__ int run_start(const float (&c0)[3], const float (&m)[
 // of the column computed once, the axis term added per voxel).  Voxels outside (or outside the
 // grid) get (0, 0); the others are appended to the gather list (one LDS counter update per wave
 // and voxel of the run).
-template <int DT, int DAX>
+template <int DT, int DAX, int NT>
 __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
     const int ncols = ui(tr.ncols), depth = ui(tr.depth), bp = ui(tr.bp);
@@ -346,13 +351,14 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
     const float inv_md = uf(tr.inv_md), half = uf(tr.half);
     const int lane = (int)threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int cb = 0; cb < ncols; cb += 256) {
+    for (int cb = 0; cb < ncols; cb += NT) {
         const int col = cb + (int)threadIdx.x;
         const bool live = col < ncols;
         const int cq = sdiv(col, dbp), cp = col - (int)__umul24((uint32_t)cq, (uint32_t)bp);
         const int vp = lo_p + cp, vq = lo_q + cq;
         const int rs = run_start<DAX>(c0, m, inv_md, half, vp, vq);
-        if (live) tl.rs[col] = (short)(rs - lo_d);
+        // a column that a pixel's cell uses has its run start within [lo_d - depth, lo_d + kRunSpan]
+        if (live) tl.rs[col] = (signed char)min(max(rs - lo_d, -128), 127);
         const bool col_in = live && (unsigned)vp < (unsigned)n[PAX] && (unsigned)vq < (unsigned)n[QAX];
         const float dp = (float)vp - c0[PAX], dq = (float)vq - c0[QAX];
         const float bn = m[PAX] * dp + m[QAX] * dq;
@@ -371,7 +377,7 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
             const bool pass = col_in && vd >= lo_d && vd <= hi_d && (unsigned)vd < (unsigned)n[DAX] &&
                               fabsf(dn) < thr_n && du > -thr_u && du < hi_u && dv > -thr_v && dv < hi_v;
             const int e = e0 + k;
-            if (live && !pass) tl.V[e] = make_float2(0.0f, 0.0f);
+            if (live && !pass) tl.V[e] = __builtin_nanf("");
             const unsigned long long mask = __ballot(pass);
             if (mask == 0ull) continue;
             int base = 0;
@@ -442,16 +448,16 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
 
 // Voxels phase, second part: every listed voxel's surviving bins gathered and blended into
 // (V_v, 1), or (0, 0) when none holds a sample.
-template <int DT>
+template <int DT, int NT>
 __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     constexpr int U = items_per_round<DT>();
     const int nlist = ui(tl.nlist), kactp = ui(tr.kactp);
-    for (int base = 0; base < nlist; base += U * 256) {
+    for (int base = 0; base < nlist; base += U * NT) {
         bool ok[U];
         int row[U], loc[U], ent[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = base + u * 256 + (int)threadIdx.x;
+            const int i = base + u * NT + (int)threadIdx.x;
             ok[u] = i < nlist;
             ent[u] = ok[u] ? tl.list[i] : 0;
             row[u] = (int)__umul24((uint32_t)ent[u] >> 20, (uint32_t)kactp);
@@ -463,15 +469,14 @@ __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
             const bool valid = B[u] > 0.0f;
-            tl.V[ent[u] & 2047] =
-                valid ? make_float2(unfold<DT>(A[u] * __builtin_amdgcn_rcpf(B[u])), 1.0f) : make_float2(0.0f, 0.0f);
+            tl.V[ent[u] & 2047] = valid ? unfold<DT>(A[u] * __builtin_amdgcn_rcpf(B[u])) : __builtin_nanf("");
         }
     }
 }
 
 // Pixels phase of a staged tile: FP64 position, the cell's 8 (V, valid) values from LDS (two
 // adjacent run entries per cell column), tent weights.
-template <int DT, int DAX>
+template <int DT, int DAX, int NT>
 __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec& tr, const TileLds<DT>& tl) {
     constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
     const int T = ui(rec.tile), W = ui(rec.W);
@@ -488,9 +493,7 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         ey[a] = ud(rec.ey[a]);
     }
     const int shift = T == kTileBig ? 5 : 4;
-    const int per = (T * T) >> 8;
-    for (int r = 0; r < per; ++r) {
-        const int idx = (int)threadIdx.x + (r << 8);
+    for (int idx = (int)threadIdx.x; idx < T * T; idx += NT) {
         const int li = idx & (T - 1), lj = idx >> shift;
         if (li >= ni || lj >= nj) continue;
         const int i = i0 + li, j = j0 + lj;
@@ -517,7 +520,7 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         const int cp = min(max(b[PAX] - lo_p, 0), bp - 2), cq = min(max(b[QAX] - lo_q, 0), bq - 2);
         const int col0 = (int)__umul24((uint32_t)cq, (uint32_t)bp) + cp;
         const int cols[4] = {col0, col0 + 1, col0 + bp, col0 + bp + 1};
-        float2 lov[4], hiv[4];
+        float lov[4], hiv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = min(max(b[DAX] - lo_d - (int)tl.rs[cols[q]], 0), depth - 2);
@@ -527,15 +530,34 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         }
         const float wp[2] = {1.0f - fr[PAX], fr[PAX]}, wq[2] = {1.0f - fr[QAX], fr[QAX]};
         const float wd[2] = {1.0f - fr[DAX], fr[DAX]};
-        float num = 0.0f, den = 0.0f;
+        // all 8 corners valid: plain sums (a NaN corner makes num NaN); otherwise the sums over
+        // the valid corners, as w * 0 and w * 1 terms, which give the same bits where all are valid
+        float t[8];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float wpq = wp[q & 1] * wq[q >> 1];
-            const float t0 = wpq * wd[0], t1 = wpq * wd[1];
-            num = __builtin_fmaf(t0, lov[q].x, num);
-            den = __builtin_fmaf(t0, lov[q].y, den);
-            num = __builtin_fmaf(t1, hiv[q].x, num);
-            den = __builtin_fmaf(t1, hiv[q].y, den);
+            t[2 * q] = wpq * wd[0];
+            t[2 * q + 1] = wpq * wd[1];
+        }
+        float num = 0.0f, den = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            num = __builtin_fmaf(t[2 * q], lov[q], num);
+            den = den + t[2 * q];
+            num = __builtin_fmaf(t[2 * q + 1], hiv[q], num);
+            den = den + t[2 * q + 1];
+        }
+        if (__builtin_isnan(num)) {
+            num = 0.0f;
+            den = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool v0 = !__builtin_isnan(lov[q]), v1 = !__builtin_isnan(hiv[q]);
+                num = __builtin_fmaf(t[2 * q], v0 ? lov[q] : 0.0f, num);
+                den = __builtin_fmaf(t[2 * q], v0 ? 1.0f : 0.0f, den);
+                num = __builtin_fmaf(t[2 * q + 1], v1 ? hiv[q] : 0.0f, num);
+                den = __builtin_fmaf(t[2 * q + 1], v1 ? 1.0f : 0.0f, den);
+            }
         }
         *out = den > 0.0f ? num * __builtin_amdgcn_rcpf(den) : __builtin_nanf("");
     }
@@ -563,42 +585,42 @@ __device__ __forceinline__ void direct_tile(const SliceRec& rec, int t) {
 }
 
 // Every pixel of a staged tile that has nothing in reach: NaN.
+template <int NT>
 __device__ __forceinline__ void nan_tile(const SliceRec& rec, const TileRec& tr) {
-    const int T = ui(rec.tile), shift = T == kTileBig ? 5 : 4, per = (T * T) >> 8;
+    const int T = ui(rec.tile), shift = T == kTileBig ? 5 : 4;
     const int i0 = ui(tr.i0), j0 = ui(tr.j0), ni = ui(tr.ni), nj = ui(tr.nj), W = ui(rec.W);
     const gptr<float> out = global(rec.out);
-    for (int r = 0; r < per; ++r) {
-        const int idx = (int)threadIdx.x + (r << 8);
+    for (int idx = (int)threadIdx.x; idx < T * T; idx += NT) {
         const int li = idx & (T - 1), lj = idx >> shift;
         if (li < ni && lj < nj) out[(size_t)(j0 + lj) * W + (i0 + li)] = __builtin_nanf("");
     }
 }
 
 // One staged tile; `rec` and `tr` are the request's and the tile's records (LDS or global).
-template <int DT>
+template <int DT, int NT>
 __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     if (ui(tr.mode) != 1) {
-        nan_tile(rec, tr);
+        nan_tile<NT>(rec, tr);
         return;
     }
-    int sl[kSlotsPerThread];
-    load_slots(rec, tr, sl);
+    int sl[slots_per_thread<NT>()];
+    load_slots<NT>(rec, tr, sl);
     if (threadIdx.x == 0) tl.nlist = 0;
     __syncthreads();
     const int dax = ui(rec.dax);
     switch (dax) {
-        case 0: classify_voxels<DT, 0>(rec, tr, tl); break;
-        case 1: classify_voxels<DT, 1>(rec, tr, tl); break;
-        default: classify_voxels<DT, 2>(rec, tr, tl); break;
+        case 0: classify_voxels<DT, 0, NT>(rec, tr, tl); break;
+        case 1: classify_voxels<DT, 1, NT>(rec, tr, tl); break;
+        default: classify_voxels<DT, 2, NT>(rec, tr, tl); break;
     }
-    store_slots<DT>(rec, tr, tl, sl);
+    store_slots<DT, NT>(rec, tr, tl, sl);
     __syncthreads();
-    gather_voxels<DT>(rec, tr, tl);
+    gather_voxels<DT, NT>(rec, tr, tl);
     __syncthreads();
     switch (dax) {
-        case 0: stage_pixels<DT, 0>(rec, tr, tl); break;
-        case 1: stage_pixels<DT, 1>(rec, tr, tl); break;
-        default: stage_pixels<DT, 2>(rec, tr, tl); break;
+        case 0: stage_pixels<DT, 0, NT>(rec, tr, tl); break;
+        case 1: stage_pixels<DT, 1, NT>(rec, tr, tl); break;
+        default: stage_pixels<DT, 2, NT>(rec, tr, tl); break;
     }
 }
 
@@ -616,7 +638,7 @@ __global__ void __launch_bounds__(256) k_reslice_tile(const VolDev* __restrict__
         if (threadIdx.x == 0 && mode == 1) compute_tile(rec, 0, t, tr);
     }
     __syncthreads();
-    if (ui(rec.mode) == 1) run_tile<DT>(rec, tr, tl);
+    if (ui(rec.mode) == 1) run_tile<DT, 256>(rec, tr, tl);
     else direct_tile<DT>(rec, t);
 }
 
@@ -659,8 +681,9 @@ __global__ void __launch_bounds__(64) k_tiles_setup(const BatchReq* __restrict__
 // request, which share the voxels along their edges, are read through one L2.  Both records are
 // read through scalar loads.
 template <int DT>
-__global__ void __launch_bounds__(256) k_tiles(const SliceRec* __restrict__ recs, const TileRec* __restrict__ tiles,
-                                               const int* __restrict__ counts) {
+__global__ void __launch_bounds__(kThreadsBatch) k_tiles(const SliceRec* __restrict__ recs,
+                                                         const TileRec* __restrict__ tiles,
+                                                         const int* __restrict__ counts) {
     __shared__ TileLds<DT> tl;
     const int n = counts[0];
     const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
@@ -668,7 +691,7 @@ __global__ void __launch_bounds__(256) k_tiles(const SliceRec* __restrict__ recs
     for (int u = beg + (int)(blockIdx.x >> 3); u < end; u += per) {
         const TileRec& tr = tiles[u];
         const SliceRec& rec = recs[ui(tr.r)];
-        run_tile<DT>(rec, tr, tl);
+        run_tile<DT, kThreadsBatch>(rec, tr, tl);
         __syncthreads();
     }
 }
@@ -704,7 +727,8 @@ int tiles_grid() {
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     if (grid[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiles<DT>, 256, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tiles<DT>, kThreadsBatch, 0) != hipSuccess ||
+            per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 8;
@@ -731,7 +755,7 @@ hipError_t launch_tiles_batch(int dtype, const BatchReq* reqs, SliceRec* recs, i
     const int sgrid = nreq_max < 1024 ? (nreq_max > 0 ? nreq_max : 1) : 1024;
     hipLaunchKernelGGL(k_tiles_setup, dim3(sgrid), dim3(64), 0, stream, reqs, recs, units, tiles, counts, cap);
 #define L(D)                                                                                                   \
-    hipLaunchKernelGGL(k_tiles<D>, dim3(tiles_grid<D>()), dim3(256), 0, stream, recs, tiles, counts);          \
+    hipLaunchKernelGGL(k_tiles<D>, dim3(tiles_grid<D>()), dim3(kThreadsBatch), 0, stream, recs, tiles, counts); \
     hipLaunchKernelGGL(k_tiles_direct<D>, dim3(1024), dim3(256), 0, stream, recs, units, counts, cap)
     DARE_DISPATCH_DT(dtype, L)
 #undef L
