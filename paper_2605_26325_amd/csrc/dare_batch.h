@@ -53,8 +53,8 @@ struct TileRec {
 
 // Radius 1, one request: one workgroup per 16 x 16 tile, each evaluating the request setup.
 hipError_t launch_reslice_tile(const VolDev* vd, int dtype, const SliceArgs& s, hipStream_t stream);
-// Radius 1, a batch: setup pass (one wave per request: the request record, then one tile record
-// per lane) + persistent tile kernel + the per-pixel kernel for requests too coarse to stage.
+// Radius 1, a batch: setup pass (one workgroup per request: the request record, then one tile
+// record per thread) + persistent tile kernel + the per-pixel kernel for requests too coarse to stage.
 // `counts[0]` and `counts[2]` must hold 0 and `counts[1]` the number of requests when the stream
 // reaches the launch; `units` and `tiles` hold `cap` entries, at least tile_units_max() per
 // request in all.

@@ -30,11 +30,8 @@ __device__ __forceinline__ double uniform_f64(double x) {
 
 __device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Wave 0 only: slice pose, Eq. 1 / thresholds / Eq. 2 per bin, survivors compacted.
-// Returns the number of surviving bins; T receives the composed pose (rows 0..2).
-__device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SetupLds& sh,
-                                           double T[12]) {
-    const int lane = threadIdx.x;
+// The slice pose T = P.C, rows 0..2 (every lane the same).
+__device__ __forceinline__ void slice_pose(const VolDev* __restrict__ vd, const SliceArgs& s, double T[12]) {
     const double* P = s.P;
     const double* C = vd->calib;
 #pragma unroll
@@ -47,6 +44,15 @@ __device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const 
             acc = acc + P[r * 4 + 3] * C[3 * 4 + c];
             T[r * 4 + c] = acc;
         }
+}
+
+// One wave: the slice pose, and Eq. 1 / thresholds / Eq. 2 per bin (lane b takes bin b), the
+// survivors compacted into act_bin / act_w.  Returns the number of surviving bins (every lane);
+// lane 0 stores T and kact.
+__device__ __forceinline__ int slice_gates(const VolDev* __restrict__ vd, const SliceArgs& s, SetupLds& sh,
+                                           double T[12]) {
+    const int lane = threadIdx.x & 63;
+    slice_pose(vd, s, T);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) sh.T[k] = T[k];
@@ -62,25 +68,34 @@ __device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const 
     const int ax = vd->normal_axis;
     const double e0[3] = {T[0], T[4], T[8]};
     const double en[3] = {T[ax], T[4 + ax], T[8 + ax]};
+    // cosines against the slice's unit in-plane axis and normal: the dot products with the raw
+    // columns divided by the columns' lengths
     const double l0 = sqrt(dot3(e0, e0));
     const double ln = sqrt(dot3(en, en));
-    const double xr[3] = {e0[0] / l0, e0[1] / l0, e0[2] / l0};
-    const double nr[3] = {en[0] / ln, en[1] / ln, en[2] / ln};
     bool keep = false;
-    double w = 0.0;
+    float w = 0.0f;
     if (lane < K) {
-        const double dn = dot3(rn, nr);
-        const double di = fabs(dot3(rx, xr));
+        const double dn = dot3(rn, en) / ln;
+        const double di = fabs(dot3(rx, e0)) / l0;
         keep = dn >= vd->cos_normal && di >= vd->cos_inplane;
-        if (keep) w = exp(vd->k_normal * (dn - 1.0) + vd->k_inplane * (di - 1.0));
+        // Eq. 2's exponent in FP64, the weight itself in FP32 (it is stored in FP32)
+        if (keep) w = expf((float)(vd->k_normal * (dn - 1.0) + vd->k_inplane * (di - 1.0)));
     }
     const unsigned long long m = __ballot(keep);
     if (keep) {
         const int idx = __popcll(m & ((1ull << lane) - 1ull));
         sh.act_bin[idx] = lane;
-        sh.act_w[idx] = (float)w;
+        sh.act_w[idx] = w;
     }
-    // plane frame in voxel units; it only drives conservative footprint tests, so FP32
+    if (lane == 0) sh.kact = __popcll(m);
+    return __popcll(m);
+}
+
+// One lane: the plane frame in voxel units (it only drives conservative footprint tests, so
+// FP32): unit in-plane axes fu, fw, their pixel lengths lu, lw, unit normal fm and its dominant
+// axis dax.
+__device__ __forceinline__ void slice_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                            SetupLds& sh) {
     const double inv_h = vd->inv_h;
     float u[3], v[3];
 #pragma unroll
@@ -97,19 +112,25 @@ __device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const 
     for (int a = 0; a < 3; ++a) nm[a] *= rm;
     if (fabsf(nm[1]) > fabsf(nm[dax])) dax = 1;
     if (fabsf(nm[2]) > fabsf(nm[dax])) dax = 2;
-    if (lane == 0) {
+    const float ilu = 1.0f / lu, ilv = 1.0f / lv;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            sh.fm[a] = nm[a];
-            sh.fu[a] = u[a] / lu;
-            sh.fw[a] = v[a] / lv;
-        }
-        sh.lu = lu;
-        sh.lw = lv;
-        sh.dax = dax;
-        sh.kact = __popcll(m);
+    for (int a = 0; a < 3; ++a) {
+        sh.fm[a] = nm[a];
+        sh.fu[a] = u[a] * ilu;
+        sh.fw[a] = v[a] * ilv;
     }
-    return __popcll(m);
+    sh.lu = lu;
+    sh.lw = lv;
+    sh.dax = dax;
+}
+
+// Wave 0 only: slice pose, Eq. 1 / thresholds / Eq. 2 per bin, survivors compacted, and the
+// plane frame (lane 0).  Returns the number of surviving bins; T receives the composed pose.
+__device__ __forceinline__ int slice_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SetupLds& sh,
+                                           double T[12]) {
+    const int kact = slice_gates(vd, s, sh, T);
+    if ((threadIdx.x & 63) == 0) slice_frame(vd, s, T, sh);
+    return kact;
 }
 
 struct SlicePos {            // per-workgroup uniform position terms
@@ -154,7 +175,8 @@ constexpr int kBinChunk = 16;        // gathers issued together per voxel
 // x * m with m = ceil(2^32 / d), exact for 0 <= x < 2^16 and 2 <= d < 2^16 (m exceeds 2^32 / d
 // by less than 1, which moves x * m / 2^32 by less than 2^-16, less than the 1/d gap between
 // x / d and the next integer).  d = 1 passes x through.  m is set from a correctly rounded FP64
-// quotient: 2^32 / d is either an integer (exact in FP64) or at least 1/d from one.
+// integer quotient: with 2^32 = q d + r, floor((2^32 - 1) / d) is q - 1 when r = 0 and q
+// otherwise, so one more is ceil(2^32 / d) in both cases.
 struct SmallDiv {
     uint32_t m;
     int d;
@@ -163,7 +185,7 @@ struct SmallDiv {
 __device__ __forceinline__ SmallDiv small_div(int d) {
     SmallDiv s;
     s.d = d;
-    s.m = d > 1 ? (uint32_t)ceil(4294967296.0 / (double)d) : 0u;
+    s.m = d > 1 ? 0xFFFFFFFFu / (uint32_t)d + 1u : 0u;
     return s;
 }
 

@@ -14,16 +14,17 @@
 //           as short runs along the plane normal's dominant axis (one thread per column of the
 //           other two axes), tested and listed; then every listed voxel gathers its surviving
 //           bins' pairs and blends them into V_v = sum_b w_b c_vb a_vb / sum_b w_b c_vb, kept in
-//           LDS as (V_v, 1), or (0, 0) when no surviving bin holds a sample (or the voxel lies
+//           LDS as one float, NaN when no surviving bin holds a sample (or the voxel lies
 //           outside the grid);
 //   pixels  FP64 position, the 8 cell values from LDS, tent weights, num / den or NaN.
-// Storing (V, valid) lets a pixel add w V and w valid with two multiply-adds per corner: an
-// invalid or out-of-grid corner adds exactly nothing, as the sums over valid voxels require.
+// A pixel whose 8 corners are all valid sums w V and w directly; a NaN corner sends it to the
+// sums over its valid corners only (w * 0 and w * 1 terms, the same bits where all are valid).
 //
 // A single reslice launches one workgroup per 16 x 16 tile; each workgroup evaluates the
-// request setup and its tile's record itself (wave 0), since no other memory holds them.  A batch
+// request setup and its tile's record itself, since no other memory holds them: the bins on one
+// wave and the plane and tile geometry on another, at the same time.  A batch
 // runs the request setup once per request and the tile records once per tile (`k_tiles_setup`:
-// one wave per request, one lane per tile; it also appends the units to a list), then one
+// one workgroup per request, one thread per tile; it also appends the units to a list), then one
 // persistent kernel over all staged units (`k_tiles`), which reads both records through scalar
 // loads, with tiles of 32 x 32 pixels wherever their voxel box fits the LDS budget.  The
 // per-voxel and per-pixel arithmetic does not depend on the tile, so a request gives the same
@@ -43,6 +44,7 @@ constexpr int kColsMax = 1024;       // box columns per tile
 constexpr int kSlotsMax = 1280;      // (box brick, bin) table entries per tile
 constexpr int kRunSpan = 127;        // box voxels along the dominant axis, less one, at most
 constexpr int kThreadsBatch = 256;   // threads of a batch workgroup
+constexpr int kSetupThreads = 256;   // threads of a batch setup workgroup (one request at a time)
 constexpr int kTileBig = 32;         // batched tile edge where the box fits
 constexpr int kFillRun = 4096;       // pixels per unit of a batched request that is all NaN
 
@@ -103,18 +105,12 @@ __device__ __forceinline__ bool tile_fits(const SliceRec& rec, int T) {
            rec.depth <= kRunSpan;
 }
 
-// One wave: the per-request setup of a radius-1 reslice, in FP64 on the device, into `rec`.
-// Lane 0 returns the number of work units (tiles) of the request and its mode in *mode_out.
-__device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SliceRec& rec, int max_tile,
-                             int* mode_out) {
-    double T[12];
-    const int kact = slice_setup(vd, s, rec, T);
-    const int lane = threadIdx.x & 63;
-    if (lane >= kact) {          // bins past the survivors: no slots, zero weight
-        rec.act_bin[lane] = 0;
-        rec.act_w[lane] = 0.0f;
-    }
-    if (lane != 0) return 0;
+// One lane: the request's plane in voxel coordinates (FP64), its frame, volume view and output,
+// and the slab of a tile: voxels with |m.(v - c0)| < |m|_1 (plus slop for FP32 rounding of
+// coordinates up to the grid's size) form runs of at most ceil(2 half) voxels along dax.
+__device__ __forceinline__ void request_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                              SliceRec& rec) {
+    slice_frame(vd, s, T, rec);
     const double inv_h = vd->inv_h;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -126,14 +122,17 @@ __device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, 
     rec.out = s.out;
     rec.W = s.W;
     rec.H = s.H;
-    // the slab of a tile: voxels with |m.(v - c0)| < |m|_1 (plus slop for FP32 rounding of
-    // coordinates up to the grid's size) form runs of at most ceil(2 half) voxels along dax
     const int nmax = max(vd->nx, max(vd->ny, vd->nz));
     const float slop = 2e-3f + 1e-6f * (float)(nmax + 64);
     const float l1m = fabsf(rec.fm[0]) + fabsf(rec.fm[1]) + fabsf(rec.fm[2]);
     rec.slop = slop;
     rec.half = (l1m + slop) * fabsf(1.0f / rec.fm[rec.dax]);
     rec.depth = (int)ceilf(2.0f * rec.half);
+}
+
+// One lane, once the frame and the surviving bins are known: the mode and the tile edge.
+__device__ __forceinline__ int request_mode(SliceRec& rec, int max_tile) {
+    const int kact = rec.kact;
     int mode = kact > 0 ? 2 : 0, tile = 16;
     if (kact > 0) {
         if (max_tile >= kTileBig && tile_fits(rec, kTileBig)) {
@@ -144,17 +143,39 @@ __device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, 
         }
     }
     rec.mode = mode;
-    *mode_out = mode;
     rec.tile = tile;
-    rec.tiles_x = (s.W + tile - 1) / tile;
-    rec.ntiles = rec.tiles_x * ((s.H + tile - 1) / tile);
+    rec.tiles_x = (rec.W + tile - 1) / tile;
+    rec.ntiles = rec.tiles_x * ((rec.H + tile - 1) / tile);
+    return mode;
+}
+
+// Bins past the survivors: no slots, zero weight (one wave, lane b for bin b).
+__device__ __forceinline__ void pad_bins(SliceRec& rec, int kact) {
+    const int lane = threadIdx.x & 63;
+    if (lane >= kact) {
+        rec.act_bin[lane] = 0;
+        rec.act_w[lane] = 0.0f;
+    }
+}
+
+// One wave: the per-request setup of a radius-1 reslice, in FP64 on the device, into `rec`.
+// Lane 0 returns the number of work units (tiles) of the request and its mode in *mode_out.
+__device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, SliceRec& rec, int max_tile,
+                             int* mode_out) {
+    double T[12];
+    const int kact = slice_gates(vd, s, rec, T);
+    pad_bins(rec, kact);
+    if ((threadIdx.x & 63) != 0) return 0;
+    request_frame(vd, s, T, rec);
+    *mode_out = request_mode(rec, max_tile);
     return rec.ntiles;
 }
 
-// One thread: the record of tile t of a staged request.  The box is the four corner pixels'
-// cells with one voxel of margin (positions are affine in (i, j), so the corners' cells bound
-// every pixel's cell; the margin absorbs rounding), clipped to [-1, n].
-__device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
+// One thread: the record of tile t of a staged request, all but what depends on the number of
+// surviving bins (`tile_bins`).  The box is the four corner pixels' cells with one voxel of
+// margin (positions are affine in (i, j), so the corners' cells bound every pixel's cell; the
+// margin absorbs rounding), clipped to [-1, n].  Needs the request's frame and tile edge.
+__device__ void tile_geometry(const SliceRec& rec, int r, int t, TileRec& tr) {
     const int T = rec.tile, W = rec.W, H = rec.H;
     const int ty = t / rec.tiles_x, tx = t - ty * rec.tiles_x;
     const int i0 = tx * T, j0 = ty * T;
@@ -182,7 +203,7 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
     }
     const int dax = rec.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
     const int bp = hi[pax] - lo[pax] + 1, bq = hi[qax] - lo[qax] + 1;
-    const int depth = rec.depth, kactp = (rec.kact + 7) & ~7;
+    const int depth = rec.depth;
     int blo[3], bdim[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -193,7 +214,7 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
     // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
     // check only keeps the LDS accesses in bounds
     const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kRunSpan && bp * bq <= kColsMax &&
-                      bp * bq * depth <= kItemsMax && nbb * kactp <= kSlotsMax && hi[dax] - lo[dax] <= kRunSpan;
+                      bp * bq * depth <= kItemsMax && hi[dax] - lo[dax] <= kRunSpan;
     tr.r = r;
     tr.mode = (!empty && fits) ? 1 : 0;
     tr.i0 = i0;
@@ -216,9 +237,7 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
     tr.ncols = bp * bq;
     tr.depth = depth;
     tr.nbb = nbb;
-    tr.kactp = kactp;
     tr.m_bp = small_div(max(bp, 1)).m;
-    tr.m_kactp = small_div(max(kactp, 1)).m;
     tr.m_bdx = small_div(max(bdim[0], 1)).m;
     tr.m_bdy = small_div(max(bdim[1], 1)).m;
     // every voxel with weight for a pixel of the tile lies within |m.(v - c0)| < |m|_1 and,
@@ -232,6 +251,19 @@ __device__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
     tr.hi_v = (float)(j1 - j0) * rec.lw + tr.thr_v;
     tr.inv_md = 1.0f / rec.fm[dax];
     tr.half = rec.half;
+}
+
+// One thread: the parts of a tile record that depend on the number of surviving bins.
+__device__ __forceinline__ void tile_bins(const SliceRec& rec, TileRec& tr) {
+    const int kactp = (rec.kact + 7) & ~7;
+    tr.kactp = kactp;
+    tr.m_kactp = small_div(max(kactp, 1)).m;
+    if (tr.nbb * kactp > kSlotsMax) tr.mode = 0;
+}
+
+__device__ __forceinline__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
+    tile_geometry(rec, r, t, tr);
+    tile_bins(rec, tr);
 }
 
 // Slots phase: the table entry of every (box brick, bin) pair, -1 past the surviving bins.  The
@@ -632,43 +664,59 @@ __global__ void __launch_bounds__(256) k_reslice_tile(const VolDev* __restrict__
     __shared__ SliceRec rec;
     __shared__ TileRec tr;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
+    // the request setup on two waves at once: wave 0 the bins (Eq. 1, gates, Eq. 2), wave 1 the
+    // plane, its frame and this tile's geometry (16 x 16 tiles); then the parts that need both
+    double T[12];
     if (threadIdx.x < 64) {
-        int mode = 0;
-        (void)request_setup(vd, s, rec, 16, &mode);
-        if (threadIdx.x == 0 && mode == 1) compute_tile(rec, 0, t, tr);
+        pad_bins(rec, slice_gates(vd, s, rec, T));
+    } else if (threadIdx.x < 128) {
+        slice_pose(vd, s, T);
+        if (threadIdx.x == 64) {
+            request_frame(vd, s, T, rec);
+            rec.tile = 16;
+            rec.tiles_x = (s.W + 15) / 16;
+            tile_geometry(rec, 0, t, tr);
+        }
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && request_mode(rec, 16) == 1) tile_bins(rec, tr);
     __syncthreads();
     if (ui(rec.mode) == 1) run_tile<DT, 256>(rec, tr, tl);
     else direct_tile<DT>(rec, t);
 }
 
-// Batch setup: one wave per request.  The request record, then the records of its tiles (one
-// lane each) when it stages them; the units are appended: staged tiles' records from the front
+// Batch setup: one workgroup per request.  Its first wave writes the request record, then every
+// thread writes the records of tiles (one at a time) when it stages them; the units are appended: staged tiles' records from the front
 // of `tiles` (counts[0]), the other requests' units (request, tile) from the back of `units`
 // (counts[2]: entry k at cap - 1 - k), so that each kind runs in a kernel of its own.
-__global__ void __launch_bounds__(64) k_tiles_setup(const BatchReq* __restrict__ reqs, SliceRec* __restrict__ recs,
-                                                    int2* __restrict__ units, TileRec* __restrict__ tiles,
-                                                    int* __restrict__ counts, int cap) {
+__global__ void __launch_bounds__(kSetupThreads) k_tiles_setup(const BatchReq* __restrict__ reqs,
+                                                               SliceRec* __restrict__ recs, int2* __restrict__ units,
+                                                               TileRec* __restrict__ tiles, int* __restrict__ counts,
+                                                               int cap) {
     __shared__ SliceRec rec;
+    __shared__ int sh[3];                 // units, mode, first entry of the request's units
     const int nreq = counts[1];
     for (int r = blockIdx.x; r < nreq; r += gridDim.x) {
-        int mode = 0;
-        int nt = request_setup(reqs[r].vol, reqs[r].s, rec, kTileBig, &mode);
-        nt = __shfl(nt, 0);
-        mode = __shfl(mode, 0);
+        if (threadIdx.x < 64) {
+            int mode = 0;
+            int nt = request_setup(reqs[r].vol, reqs[r].s, rec, kTileBig, &mode);
+            if (threadIdx.x == 0) {
+                // a request with no surviving bin is filled with NaN in flat runs of kFillRun
+                // pixels (fewer units than its tiles), marked by a negative tile index
+                if (mode == 0) nt = (int)(((int64_t)reqs[r].s.W * reqs[r].s.H + kFillRun - 1) / kFillRun);
+                sh[0] = nt;
+                sh[1] = mode;
+                sh[2] = atomicAdd(counts + (mode == 1 ? 0 : 2), nt);
+            }
+        }
         __syncthreads();
+        const int nt = sh[0], mode = sh[1], base = sh[2];
         {   // the record to global memory (the tile kernels read it)
             const int* src = reinterpret_cast<const int*>(&rec);
             int* dst = reinterpret_cast<int*>(recs + r);
-            for (int w = threadIdx.x; w < (int)(sizeof(SliceRec) / sizeof(int)); w += 64) dst[w] = src[w];
+            for (int w = threadIdx.x; w < (int)(sizeof(SliceRec) / sizeof(int)); w += kSetupThreads) dst[w] = src[w];
         }
-        // a request with no surviving bin is filled with NaN in flat runs of kFillRun pixels
-        // (fewer units than its tiles), marked by a negative tile index
-        if (mode == 0) nt = (int)(((int64_t)reqs[r].s.W * reqs[r].s.H + kFillRun - 1) / kFillRun);
-        int base = 0;
-        if (threadIdx.x == 0) base = atomicAdd(counts + (mode == 1 ? 0 : 2), nt);
-        base = __shfl(base, 0);
-        for (int k = threadIdx.x; k < nt; k += 64) {
+        for (int k = threadIdx.x; k < nt; k += kSetupThreads) {
             if (mode == 1) compute_tile(rec, r, k, tiles[base + k]);
             else units[cap - 1 - (base + k)] = make_int2(r, mode == 0 ? ~k : k);
         }
@@ -753,7 +801,8 @@ hipError_t launch_reslice_tile(const VolDev* vd, int dtype, const SliceArgs& s, 
 hipError_t launch_tiles_batch(int dtype, const BatchReq* reqs, SliceRec* recs, int2* units, TileRec* tiles,
                               int* counts, int nreq_max, int cap, hipStream_t stream) {
     const int sgrid = nreq_max < 1024 ? (nreq_max > 0 ? nreq_max : 1) : 1024;
-    hipLaunchKernelGGL(k_tiles_setup, dim3(sgrid), dim3(64), 0, stream, reqs, recs, units, tiles, counts, cap);
+    hipLaunchKernelGGL(k_tiles_setup, dim3(sgrid), dim3(kSetupThreads), 0, stream, reqs, recs, units, tiles, counts,
+                       cap);
 #define L(D)                                                                                                   \
     hipLaunchKernelGGL(k_tiles<D>, dim3(tiles_grid<D>()), dim3(kThreadsBatch), 0, stream, recs, tiles, counts); \
     hipLaunchKernelGGL(k_tiles_direct<D>, dim3(1024), dim3(256), 0, stream, recs, units, counts, cap)
