@@ -433,6 +433,10 @@ typedef struct {
     double busy_seconds;      /* host-measured time with at least one tick in flight         */
     int64_t frames;           /* frames compounded through dare_server_submit_frames         */
     double compound_seconds;  /* host-measured time spent compounding them                   */
+    double kernel_seconds;    /* device-measured: sum over ticks of the span of their kernels */
+    double device_busy_seconds; /* device-measured: union of those spans (ticks on different
+                                   streams overlap), i.e. time the device ran served kernels  */
+    int64_t untimed_ticks;    /* ticks whose kernel span could not be read (not in the above) */
 } dare_server_stats;
 
 typedef struct {

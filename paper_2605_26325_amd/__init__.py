@@ -61,7 +61,8 @@ class ServerConfig(ct.Structure):
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("rejected", ct.c_int64),
                 ("ticks", ct.c_int64), ("pixels", ct.c_int64), ("busy_seconds", ct.c_double),
-                ("frames", ct.c_int64), ("compound_seconds", ct.c_double)]
+                ("frames", ct.c_int64), ("compound_seconds", ct.c_double), ("kernel_seconds", ct.c_double),
+                ("device_busy_seconds", ct.c_double), ("untimed_ticks", ct.c_int64)]
 
 
 class RequestTimes(ct.Structure):

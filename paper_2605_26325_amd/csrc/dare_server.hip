@@ -80,14 +80,102 @@ struct Request {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t ev_kernels = nullptr, ev_done = nullptr;
+    hipEvent_t ev_start = nullptr, ev_kernels = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
     char* ws = nullptr;           // device workspace: header, requests, units, setup records
     uint64_t ws_off = UINT64_MAX; // its place in the arena
     char* staging = nullptr;      // pinned host copy of the uploaded part
     bool busy = false;
     bool kernels_seen = false;
+    double last_end = 0.0;        // device time at which this slot's last timed tick's kernels ended
     std::vector<uint64_t> tickets;
+};
+
+// Device time of the ticks' kernels.  Each tick's kernels lie between two timing events on its
+// slot's stream; their spans are summed, and their union (ticks on different streams overlap)
+// is the time the device spent on served kernels.  Event times are taken against a reference
+// event on an otherwise idle stream, moved forward about once a second so that the single
+// precision of hipEventElapsedTime stays well below a microsecond.
+struct DeviceClock {
+    hipStream_t stream = nullptr;
+    hipEvent_t ref[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool moving = false;          // ref[1 - cur] recorded, not yet reached
+    double off = 0.0;             // seconds from the first reference to ref[cur]
+    double host_t = 0.0;          // host time at which ref[cur] was taken
+    double kernel_seconds = 0.0;  // sum of spans
+    double folded = 0.0;          // union of the spans no later span can overlap
+    std::vector<std::pair<double, double>> open;   // the other spans
+
+    hipError_t init(double now) {
+        hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&ref[k]);
+        if (e == hipSuccess) e = hipEventRecord(ref[0], stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ref[0]);
+        host_t = now;
+        return e;
+    }
+    void destroy() {
+        for (hipEvent_t& r : ref)
+            if (r) (void)hipEventDestroy(r);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    // Seconds from the first reference to event `ev` (completed); false if it cannot be timed.
+    bool at(hipEvent_t ev, double* t) const {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ref[cur], ev) != hipSuccess) return false;
+        *t = off + 1e-3 * (double)ms;
+        return true;
+    }
+    void advance(double now) {
+        if (!stream || now - host_t < 1.0) return;
+        if (!moving) {
+            moving = hipEventRecord(ref[1 - cur], stream) == hipSuccess;
+        } else if (hipEventQuery(ref[1 - cur]) == hipSuccess) {
+            double t = 0.0;
+            if (at(ref[1 - cur], &t)) {
+                off = t;
+                cur = 1 - cur;
+            }
+            moving = false;
+            host_t = now;
+        }
+    }
+    // Add the span [t0, t1].  No span added later starts before `horizon`.
+    void add(double t0, double t1, double horizon) {
+        kernel_seconds += t1 - t0;
+        open.emplace_back(t0, t1);
+        if (open.size() < 256) return;
+        std::sort(open.begin(), open.end());
+        std::vector<std::pair<double, double>> keep;
+        double a = open[0].first, b = open[0].second;
+        auto flush = [&](double x, double y) {
+            if (y <= horizon) folded += y - x;
+            else keep.emplace_back(x, y);
+        };
+        for (size_t k = 1; k < open.size(); ++k) {
+            if (open[k].first <= b) {
+                b = std::max(b, open[k].second);
+            } else {
+                flush(a, b);
+                a = open[k].first;
+                b = open[k].second;
+            }
+        }
+        flush(a, b);
+        open.swap(keep);
+    }
+    double busy() const {
+        std::vector<std::pair<double, double>> v(open);
+        std::sort(v.begin(), v.end());
+        double u = folded, b = -1e300;
+        for (const auto& iv : v) {
+            if (iv.second <= b) continue;
+            u += iv.second - std::max(iv.first, b);
+            b = iv.second;
+        }
+        return u;
+    }
 };
 
 }  // namespace
@@ -124,6 +212,7 @@ struct dare_server {
     std::thread th;
     double busy_since = -1.0;
     bool failed = false;
+    DeviceClock clock;
 };
 
 namespace {
@@ -157,6 +246,26 @@ void release_request(dare_server* S, Request& r) {
     S->vols[r.vol].pending -= 1;
 }
 
+// Device span of a tick whose kernels have finished.  A later tick of a busy slot starts after
+// that slot's last timed tick (stream order); an idle slot's next tick starts after now.
+void time_tick(dare_server* S, Slot& sl) {
+    float ms = 0.0f;
+    double t0 = 0.0;
+    if (hipEventElapsedTime(&ms, sl.ev_start, sl.ev_kernels) != hipSuccess || !S->clock.at(sl.ev_start, &t0)) {
+        S->stats.untimed_ticks += 1;
+        return;
+    }
+    const double t1 = t0 + 1e-3 * (double)std::max(ms, 0.0f);
+    sl.last_end = t1;
+    double horizon = 1e300;
+    for (int k = 0; k < S->cfg.n_streams; ++k) {
+        const Slot& o = S->slots[k];
+        if (o.busy && &o != &sl && !o.kernels_seen) horizon = std::min(horizon, o.last_end);
+    }
+    S->clock.add(t0, t1, horizon);
+    S->stats.kernel_seconds = S->clock.kernel_seconds;
+}
+
 // Complete finished ticks.  Caller holds the lock.
 void reap(dare_server* S) {
     for (int k = 0; k < S->cfg.n_streams; ++k) {
@@ -166,10 +275,15 @@ void reap(dare_server* S) {
         if (!sl.kernels_seen && hipEventQuery(sl.ev_kernels) == hipSuccess) {
             sl.kernels_seen = true;
             for (uint64_t id : sl.tickets) S->reqs[id].t.t_device_done = t;
+            time_tick(S, sl);
         }
         const hipError_t q = hipEventQuery(sl.ev_done);
         if (q == hipErrorNotReady) continue;
         const bool ok = q == hipSuccess;
+        if (ok && !sl.kernels_seen) {
+            sl.kernels_seen = true;
+            time_tick(S, sl);
+        }
         for (uint64_t id : sl.tickets) {
             Request& r = S->reqs[id];
             if (r.t.t_device_done == 0.0) r.t.t_device_done = t;
@@ -241,6 +355,7 @@ bool launch_tick(dare_server* S, Slot& sl) {
     const uint64_t upload = host_units ? S->o_units + bunits.size() * sizeof(int2)
                                        : S->o_req + breqs.size() * sizeof(BatchReq);
     hipError_t e = hipMemcpyAsync(sl.ws, sl.staging, upload, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess) e = hipEventRecord(sl.ev_start, sl.stream);
     if (e == hipSuccess) e = S->cfg.use_graphs ? hipGraphLaunch(sl.graph, sl.stream) : enqueue_kernels(S, sl);
     if (e == hipSuccess) e = hipEventRecord(sl.ev_kernels, sl.stream);
     for (size_t k = 0; e == hipSuccess && k < sl.tickets.size(); ++k) {
@@ -311,6 +426,7 @@ void scheduler(dare_server* S) {
     while (!S->stop.load()) {
         reap(S);
         while (run_frames_job(S, lk)) reap(S);
+        S->clock.advance(now_s());
         for (int k = 0; k < S->cfg.n_streams; ++k) {
             Slot& sl = S->slots[k];
             if (sl.busy) continue;
@@ -457,9 +573,11 @@ dare_status dare_server_create(const dare_server_config* cfg, void* arena_dev, u
     for (int k = 0; k < cfg->n_streams && e == hipSuccess; ++k) {
         Slot& sl = S->slots[k];
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_kernels, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&sl.ev_start);
+        if (e == hipSuccess) e = hipEventCreate(&sl.ev_kernels);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = S->clock.init(now_s());
     if (e != hipSuccess) {
         dare_server_destroy(S);
         return DARE_ERR_HIP;
@@ -643,6 +761,7 @@ dare_status dare_server_get_stats(dare_server* S, dare_server_stats* out) {
     std::lock_guard<std::mutex> lk(S->mu);
     *out = S->stats;
     if (S->busy_since >= 0.0) out->busy_seconds += now_s() - S->busy_since;
+    out->device_busy_seconds = S->clock.busy();
     return DARE_OK;
 }
 
@@ -661,10 +780,12 @@ dare_status dare_server_destroy(dare_server* S) {
             const hipError_t q = hipStreamSynchronize(sl.stream);
             if (q != hipSuccess) e = q;
         }
+        if (sl.ev_start) (void)hipEventDestroy(sl.ev_start);
         if (sl.ev_kernels) (void)hipEventDestroy(sl.ev_kernels);
         if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    S->clock.destroy();
     release_workspaces(S);
     delete S;
     return e == hipSuccess ? DARE_OK : DARE_ERR_HIP;
