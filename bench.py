@@ -163,7 +163,13 @@ def percentile(xs, q):
 class Console:
     """A simulated expert console: a probe pose following a smooth random walk
     (Ornstein-Uhlenbeck velocity and angular velocity, tau = 1 s, 5 mm/s and
-    20 deg/s scales), starting at an acquired pose, kept inside the volume."""
+    20 deg/s scales), starting at an acquired pose, kept inside the volume and
+    within MAX_TILT_DEG of the starting orientation (both reflected at the
+    bound): an unbounded orientation walk drifts, within a minute, to planes
+    that no acquisition direction passes the angular gates for, and those
+    reslice to all-NaN images."""
+
+    MAX_TILT_DEG = 10.0
 
     def __init__(self, rng, wl, vol_id, sizes):
         self.rng = rng
@@ -171,6 +177,7 @@ class Console:
         self.wl = wl
         f = int(rng.integers(len(wl.sweep.image_poses)))
         self.R = wl.sweep.image_poses[f][:3, :3].copy()
+        self.R0 = self.R.copy()
         self.c = wl.sweep.centers[f].copy()
         self.v = np.zeros(3)
         self.w = np.zeros(3)
@@ -192,7 +199,12 @@ class Console:
             if self.c[k] > self.hi[k]:
                 self.c[k] = 2 * self.hi[k] - self.c[k]
                 self.v[k] = -self.v[k]
-        self.R = synth.rotvec_to_matrix(self.w * dt) @ self.R
+        R = synth.rotvec_to_matrix(self.w * dt) @ self.R
+        cos_t = (np.trace(R @ self.R0.T) - 1.0) / 2.0
+        if cos_t < np.cos(np.deg2rad(self.MAX_TILT_DEG)):
+            self.w = -self.w                   # reflect at the orientation bound
+        else:
+            self.R = R
         n = int(self.sizes[int(self.rng.integers(len(self.sizes)))])
         L = self.wl.dims[0] * self.wl.spacing
         pitch = (L / n, L / n)

@@ -91,11 +91,15 @@ __device__ __forceinline__ int slice_gates(const VolDev* __restrict__ vd, const 
     return __popcll(m);
 }
 
-// One lane: the plane frame in voxel units (it only drives conservative footprint tests, so
-// FP32): unit in-plane axes fu, fw, their pixel lengths lu, lw, unit normal fm and its dominant
-// axis dax.
-__device__ __forceinline__ void slice_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
-                                            SetupLds& sh) {
+// The plane frame in voxel units (it only drives conservative footprint tests, so FP32): unit
+// in-plane axes fu, fw, their pixel lengths lu, lw, unit normal fm and its dominant axis dax.
+struct SliceFrame {
+    float fm[3], fu[3], fw[3], lu, lw;
+    int dax;
+};
+
+__device__ __forceinline__ SliceFrame frame_of(const VolDev* __restrict__ vd, const SliceArgs& s,
+                                               const double T[12]) {
     const double inv_h = vd->inv_h;
     float u[3], v[3];
 #pragma unroll
@@ -103,25 +107,43 @@ __device__ __forceinline__ void slice_frame(const VolDev* __restrict__ vd, const
         u[a] = (float)(T[a * 4 + 0] * s.sx * inv_h);
         v[a] = (float)(T[a * 4 + 1] * s.sy * inv_h);
     }
-    const float lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const float lv = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    SliceFrame f;
+    f.lu = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    f.lw = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     float nm[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
     const float rm = 1.0f / sqrtf(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
-    int dax = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) nm[a] *= rm;
+    int dax = 0;
     if (fabsf(nm[1]) > fabsf(nm[dax])) dax = 1;
     if (fabsf(nm[2]) > fabsf(nm[dax])) dax = 2;
-    const float ilu = 1.0f / lu, ilv = 1.0f / lv;
+    const float ilu = 1.0f / f.lu, ilv = 1.0f / f.lw;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        sh.fm[a] = nm[a];
-        sh.fu[a] = u[a] * ilu;
-        sh.fw[a] = v[a] * ilv;
+        f.fm[a] = nm[a];
+        f.fu[a] = u[a] * ilu;
+        f.fw[a] = v[a] * ilv;
     }
-    sh.lu = lu;
-    sh.lw = lv;
-    sh.dax = dax;
+    f.dax = dax;
+    return f;
+}
+
+__device__ __forceinline__ void store_frame(const SliceFrame& f, SetupLds& sh) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        sh.fm[a] = f.fm[a];
+        sh.fu[a] = f.fu[a];
+        sh.fw[a] = f.fw[a];
+    }
+    sh.lu = f.lu;
+    sh.lw = f.lw;
+    sh.dax = f.dax;
+}
+
+// One lane: the plane frame into the setup record.
+__device__ __forceinline__ void slice_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                            SetupLds& sh) {
+    store_frame(frame_of(vd, s, T), sh);
 }
 
 // Wave 0 only: slice pose, Eq. 1 / thresholds / Eq. 2 per bin, survivors compacted, and the

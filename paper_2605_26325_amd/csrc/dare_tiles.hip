@@ -89,63 +89,122 @@ __device__ __forceinline__ int box_edge_bound(int T, double ex, double ey) {
     return (int)floor(ext * (1.0 + 1e-9) + 1e-6) + 5;
 }
 
+// Entry i of a 3-vector held in registers, without indexing it (which would put it in memory).
+template <class T>
+__device__ __forceinline__ T pick3(const T (&v)[3], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+
+// What a tile record needs of its request, held in registers by the thread that writes it.
+struct Plane {
+    double c00[3], ex[3], ey[3];          // voxel coordinates of pixel (i, j): c00 + i ex + j ey
+    SliceFrame f;
+    int n[3];
+    int W, H, tile, tiles_x, depth, kact;
+    float slop, half;
+};
+
+// The plane from a request record.
+__device__ __forceinline__ Plane plane_of(const SliceRec& rec) {
+    Plane pl;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pl.c00[a] = rec.c00[a];
+        pl.ex[a] = rec.ex[a];
+        pl.ey[a] = rec.ey[a];
+        pl.f.fm[a] = rec.fm[a];
+        pl.f.fu[a] = rec.fu[a];
+        pl.f.fw[a] = rec.fw[a];
+        pl.n[a] = rec.vol.n[a];
+    }
+    pl.f.lu = rec.lu;
+    pl.f.lw = rec.lw;
+    pl.f.dax = rec.dax;
+    pl.W = rec.W;
+    pl.H = rec.H;
+    pl.tile = rec.tile;
+    pl.tiles_x = rec.tiles_x;
+    pl.depth = rec.depth;
+    pl.kact = rec.kact;
+    pl.slop = rec.slop;
+    pl.half = rec.half;
+    return pl;
+}
+
 // Does a T x T tile of this request fit the LDS budget wherever it falls?
-__device__ __forceinline__ bool tile_fits(const SliceRec& rec, int T) {
-    const int dax = rec.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+__device__ __forceinline__ bool tile_fits(const Plane& pl, int T) {
+    const int dax = pl.f.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
     int e[3];
     int64_t nbb = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        e[a] = box_edge_bound(T, rec.ex[a], rec.ey[a]);
+        e[a] = box_edge_bound(T, pl.ex[a], pl.ey[a]);
         nbb *= e[a] / 8 + 2;
     }
-    const int64_t cols = (int64_t)e[pax] * e[qax];
-    const int kactp = (rec.kact + 7) & ~7;
-    return cols <= kColsMax && cols * rec.depth <= kItemsMax && nbb * kactp <= kSlotsMax && e[dax] <= kRunSpan &&
-           rec.depth <= kRunSpan;
+    const int64_t cols = (int64_t)pick3(e, pax) * pick3(e, qax);
+    const int kactp = (pl.kact + 7) & ~7;
+    return cols <= kColsMax && cols * pl.depth <= kItemsMax && nbb * kactp <= kSlotsMax && pick3(e, dax) <= kRunSpan &&
+           pl.depth <= kRunSpan;
 }
 
 // One lane: the request's plane in voxel coordinates (FP64), its frame, volume view and output,
 // and the slab of a tile: voxels with |m.(v - c0)| < |m|_1 (plus slop for FP32 rounding of
-// coordinates up to the grid's size) form runs of at most ceil(2 half) voxels along dax.
-__device__ __forceinline__ void request_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
-                                              SliceRec& rec) {
-    slice_frame(vd, s, T, rec);
+// coordinates up to the grid's size) form runs of at most ceil(2 half) voxels along dax.  Stored
+// in `rec` and returned (tile edge and surviving bins not yet set).
+__device__ __forceinline__ Plane request_frame(const VolDev* __restrict__ vd, const SliceArgs& s, const double T[12],
+                                               SliceRec& rec) {
+    Plane pl;
+    pl.f = frame_of(vd, s, T);
+    store_frame(pl.f, rec);
     const double inv_h = vd->inv_h;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        rec.c00[a] = (T[a * 4 + 3] - vd->origin[a]) * inv_h;
-        rec.ex[a] = (s.sx * T[a * 4 + 0]) * inv_h;
-        rec.ey[a] = (s.sy * T[a * 4 + 1]) * inv_h;
+        pl.c00[a] = (T[a * 4 + 3] - vd->origin[a]) * inv_h;
+        pl.ex[a] = (s.sx * T[a * 4 + 0]) * inv_h;
+        pl.ey[a] = (s.sy * T[a * 4 + 1]) * inv_h;
+        rec.c00[a] = pl.c00[a];
+        rec.ex[a] = pl.ex[a];
+        rec.ey[a] = pl.ey[a];
     }
-    rec.vol = view_of(vd);
+    const VolView vv = view_of(vd);
+    rec.vol = vv;
     rec.out = s.out;
-    rec.W = s.W;
-    rec.H = s.H;
-    const int nmax = max(vd->nx, max(vd->ny, vd->nz));
-    const float slop = 2e-3f + 1e-6f * (float)(nmax + 64);
-    const float l1m = fabsf(rec.fm[0]) + fabsf(rec.fm[1]) + fabsf(rec.fm[2]);
-    rec.slop = slop;
-    rec.half = (l1m + slop) * fabsf(1.0f / rec.fm[rec.dax]);
-    rec.depth = (int)ceilf(2.0f * rec.half);
+    rec.W = pl.W = s.W;
+    rec.H = pl.H = s.H;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pl.n[a] = vv.n[a];
+    const int nmax = max(vv.n[0], max(vv.n[1], vv.n[2]));
+    pl.slop = 2e-3f + 1e-6f * (float)(nmax + 64);
+    const float l1m = fabsf(pl.f.fm[0]) + fabsf(pl.f.fm[1]) + fabsf(pl.f.fm[2]);
+    pl.half = (l1m + pl.slop) * fabsf(1.0f / pick3(pl.f.fm, pl.f.dax));
+    pl.depth = (int)ceilf(2.0f * pl.half);
+    rec.slop = pl.slop;
+    rec.half = pl.half;
+    rec.depth = pl.depth;
+    pl.tile = 16;
+    pl.tiles_x = (s.W + 15) / 16;
+    pl.kact = 0;
+    return pl;
 }
 
 // One lane, once the frame and the surviving bins are known: the mode and the tile edge.
-__device__ __forceinline__ int request_mode(SliceRec& rec, int max_tile) {
-    const int kact = rec.kact;
+__device__ __forceinline__ int request_mode(Plane& pl, SliceRec& rec, int max_tile) {
+    const int kact = pl.kact;
     int mode = kact > 0 ? 2 : 0, tile = 16;
     if (kact > 0) {
-        if (max_tile >= kTileBig && tile_fits(rec, kTileBig)) {
+        if (max_tile >= kTileBig && tile_fits(pl, kTileBig)) {
             mode = 1;
             tile = kTileBig;
-        } else if (tile_fits(rec, 16)) {
+        } else if (tile_fits(pl, 16)) {
             mode = 1;
         }
     }
+    pl.tile = tile;
+    pl.tiles_x = (pl.W + tile - 1) / tile;
     rec.mode = mode;
     rec.tile = tile;
-    rec.tiles_x = (rec.W + tile - 1) / tile;
-    rec.ntiles = rec.tiles_x * ((rec.H + tile - 1) / tile);
+    rec.tiles_x = pl.tiles_x;
+    rec.ntiles = pl.tiles_x * ((pl.H + tile - 1) / tile);
     return mode;
 }
 
@@ -166,21 +225,21 @@ __device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, 
     const int kact = slice_gates(vd, s, rec, T);
     pad_bins(rec, kact);
     if ((threadIdx.x & 63) != 0) return 0;
-    request_frame(vd, s, T, rec);
-    *mode_out = request_mode(rec, max_tile);
+    Plane pl = request_frame(vd, s, T, rec);
+    pl.kact = kact;
+    *mode_out = request_mode(pl, rec, max_tile);
     return rec.ntiles;
 }
 
 // One thread: the record of tile t of a staged request, all but what depends on the number of
 // surviving bins (`tile_bins`).  The box is the four corner pixels' cells with one voxel of
 // margin (positions are affine in (i, j), so the corners' cells bound every pixel's cell; the
-// margin absorbs rounding), clipped to [-1, n].  Needs the request's frame and tile edge.
-__device__ void tile_geometry(const SliceRec& rec, int r, int t, TileRec& tr) {
-    const int T = rec.tile, W = rec.W, H = rec.H;
-    const int ty = t / rec.tiles_x, tx = t - ty * rec.tiles_x;
+// margin absorbs rounding), clipped to [-1, n].
+__device__ __forceinline__ void tile_geometry(const Plane& pl, int r, int t, TileRec& tr) {
+    const int T = pl.tile, W = pl.W, H = pl.H;
+    const int ty = t / pl.tiles_x, tx = t - ty * pl.tiles_x;
     const int i0 = tx * T, j0 = ty * T;
     const int i1 = min(i0 + T - 1, W - 1), j1 = min(j0 + T - 1, H - 1);
-    const int n[3] = {rec.vol.n[0], rec.vol.n[1], rec.vol.n[2]};
     int lo[3], hi[3];
     float c0[3];
     bool empty = false;
@@ -190,31 +249,31 @@ __device__ void tile_geometry(const SliceRec& rec, int r, int t, TileRec& tr) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double ci = (double)((k & 1) ? i1 : i0), cj = (double)((k & 2) ? j1 : j0);
-            const double c = fma(cj, rec.ey[a], fma(ci, rec.ex[a], rec.c00[a]));
+            const double c = fma(cj, pl.ey[a], fma(ci, pl.ex[a], pl.c00[a]));
             const int f = (int)fmin(fmax(floor(c), -1048576.0), 1048576.0);
             mn = k == 0 ? f : min(mn, f);
             mx = k == 0 ? f : max(mx, f);
             if (k == 0) c0[a] = (float)c;
         }
         lo[a] = max(mn - 1, -1);
-        hi[a] = min(mx + 2, n[a]);
+        hi[a] = min(mx + 2, pl.n[a]);
         // no in-grid voxel in reach: every pixel of the tile is unassigned
-        empty = empty || max(lo[a], 0) > min(hi[a], n[a] - 1);
+        empty = empty || max(lo[a], 0) > min(hi[a], pl.n[a] - 1);
     }
-    const int dax = rec.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
-    const int bp = hi[pax] - lo[pax] + 1, bq = hi[qax] - lo[qax] + 1;
-    const int depth = rec.depth;
+    const int dax = pl.f.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    const int bp = pick3(hi, pax) - pick3(lo, pax) + 1, bq = pick3(hi, qax) - pick3(lo, qax) + 1;
+    const int depth = pl.depth;
     int blo[3], bdim[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         blo[a] = max(lo[a], 0) >> 3;
-        bdim[a] = (min(hi[a], n[a] - 1) >> 3) - blo[a] + 1;
+        bdim[a] = (min(hi[a], pl.n[a] - 1) >> 3) - blo[a] + 1;
     }
     const int nbb = bdim[0] * bdim[1] * bdim[2];
     // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
     // check only keeps the LDS accesses in bounds
     const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kRunSpan && bp * bq <= kColsMax &&
-                      bp * bq * depth <= kItemsMax && hi[dax] - lo[dax] <= kRunSpan;
+                      bp * bq * depth <= kItemsMax && pick3(hi, dax) - pick3(lo, dax) <= kRunSpan;
     tr.r = r;
     tr.mode = (!empty && fits) ? 1 : 0;
     tr.i0 = i0;
@@ -229,8 +288,8 @@ __device__ void tile_geometry(const SliceRec& rec, int r, int t, TileRec& tr) {
         tr.blo[a] = blo[a];
         tr.bdim[a] = bdim[a];
         tr.c0[a] = c0[a];
-        l1u += fabsf(rec.fu[a]);
-        l1w += fabsf(rec.fw[a]);
+        l1u += fabsf(pl.f.fu[a]);
+        l1w += fabsf(pl.f.fw[a]);
     }
     tr.bp = bp;
     tr.bq = bq;
@@ -243,27 +302,27 @@ __device__ void tile_geometry(const SliceRec& rec, int r, int t, TileRec& tr) {
     // every voxel with weight for a pixel of the tile lies within |m.(v - c0)| < |m|_1 and,
     // along the in-plane axes, within the tile's extent widened by |u|_1, |w|_1 (the margins
     // cover FP32 rounding and the pose rigidity tolerance)
-    const float slop = rec.slop;
-    tr.thr_n = fabsf(rec.fm[0]) + fabsf(rec.fm[1]) + fabsf(rec.fm[2]) + slop;
+    const float slop = pl.slop;
+    tr.thr_n = fabsf(pl.f.fm[0]) + fabsf(pl.f.fm[1]) + fabsf(pl.f.fm[2]) + slop;
     tr.thr_u = l1u + 0.02f + slop;
     tr.thr_v = l1w + 0.02f + slop;
-    tr.hi_u = (float)(i1 - i0) * rec.lu + tr.thr_u;
-    tr.hi_v = (float)(j1 - j0) * rec.lw + tr.thr_v;
-    tr.inv_md = 1.0f / rec.fm[dax];
-    tr.half = rec.half;
+    tr.hi_u = (float)(i1 - i0) * pl.f.lu + tr.thr_u;
+    tr.hi_v = (float)(j1 - j0) * pl.f.lw + tr.thr_v;
+    tr.inv_md = 1.0f / pick3(pl.f.fm, dax);
+    tr.half = pl.half;
 }
 
 // One thread: the parts of a tile record that depend on the number of surviving bins.
-__device__ __forceinline__ void tile_bins(const SliceRec& rec, TileRec& tr) {
-    const int kactp = (rec.kact + 7) & ~7;
+__device__ __forceinline__ void tile_bins(int kact, TileRec& tr) {
+    const int kactp = (kact + 7) & ~7;
     tr.kactp = kactp;
     tr.m_kactp = small_div(max(kactp, 1)).m;
     if (tr.nbb * kactp > kSlotsMax) tr.mode = 0;
 }
 
-__device__ __forceinline__ void compute_tile(const SliceRec& rec, int r, int t, TileRec& tr) {
-    tile_geometry(rec, r, t, tr);
-    tile_bins(rec, tr);
+__device__ __forceinline__ void compute_tile(const Plane& pl, int r, int t, TileRec& tr) {
+    tile_geometry(pl, r, t, tr);
+    tile_bins(pl.kact, tr);
 }
 
 // Slots phase: the table entry of every (box brick, bin) pair, -1 past the surviving bins.  The
@@ -430,12 +489,12 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
 // Pairs of every surviving bin for U listed voxels of a thread: the slot rows of NB bins are
 // read from LDS 4 at a time, then the NB x U pair loads are issued before any is used.  A pair
 // that is not loaded (no slot, or no voxel) stays zero and adds nothing.
-template <int DT, int U>
-__device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& tl, const bool (&ok)[U],
+template <int DT, int U, int NB>
+__device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& tl, int kactp, const bool (&ok)[U],
                                        const int (&row)[U], const int (&loc)[U], float (&A)[U], float (&B)[U]) {
     using PT = Pair<DT>;
     using T = typename PT::T;
-    constexpr int NB = bins_per_round<DT>();
+    static_assert(NB % 4 == 0, "slot rows are read 4 entries at a time");
     const gptr<const T> data = global((const T*)rec.vol.data);
     const int kact = ui(rec.kact);
 #pragma unroll
@@ -446,8 +505,9 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int g = 0; g < NB; g += 4) {
+                // rows hold kactp entries (a multiple of 8, -1 past the survivors)
                 int4 s4 = make_int4(-1, -1, -1, -1);
-                if (ok[u]) s4 = *reinterpret_cast<const int4*>(&tl.slot[row[u] + k0 + g]);
+                if (ok[u] && k0 + g < kactp) s4 = *reinterpret_cast<const int4*>(&tl.slot[row[u] + k0 + g]);
                 sl[u][g] = s4.x;
                 sl[u][g + 1] = s4.y;
                 sl[u][g + 2] = s4.z;
@@ -480,9 +540,8 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
 
 // Voxels phase, second part: every listed voxel's surviving bins gathered and blended into
 // (V_v, 1), or (0, 0) when none holds a sample.
-template <int DT, int NT>
+template <int DT, int NT, int U, int NB>
 __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
-    constexpr int U = items_per_round<DT>();
     const int nlist = ui(tl.nlist), kactp = ui(tr.kactp);
     for (int base = 0; base < nlist; base += U * NT) {
         bool ok[U];
@@ -496,7 +555,7 @@ __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec
             loc[u] = (ent[u] >> 11) & 511;
         }
         float A[U], B[U];
-        gather<DT, U>(rec, tl, ok, row, loc, A, B);
+        gather<DT, U, NB>(rec, tl, kactp, ok, row, loc, A, B);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
@@ -629,7 +688,8 @@ __device__ __forceinline__ void nan_tile(const SliceRec& rec, const TileRec& tr)
 }
 
 // One staged tile; `rec` and `tr` are the request's and the tile's records (LDS or global).
-template <int DT, int NT>
+// U listed voxels per thread and NB bins per round in the gather.
+template <int DT, int NT, int U, int NB>
 __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     if (ui(tr.mode) != 1) {
         nan_tile<NT>(rec, tr);
@@ -647,7 +707,7 @@ __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr,
     }
     store_slots<DT, NT>(rec, tr, tl, sl);
     __syncthreads();
-    gather_voxels<DT, NT>(rec, tr, tl);
+    gather_voxels<DT, NT, U, NB>(rec, tr, tl);
     __syncthreads();
     switch (dax) {
         case 0: stage_pixels<DT, 0, NT>(rec, tr, tl); break;
@@ -671,17 +731,15 @@ __global__ void __launch_bounds__(256) k_reslice_tile(const VolDev* __restrict__
         pad_bins(rec, slice_gates(vd, s, rec, T));
     } else if (threadIdx.x < 128) {
         slice_pose(vd, s, T);
-        if (threadIdx.x == 64) {
-            request_frame(vd, s, T, rec);
-            rec.tile = 16;
-            rec.tiles_x = (s.W + 15) / 16;
-            tile_geometry(rec, 0, t, tr);
-        }
+        if (threadIdx.x == 64) tile_geometry(request_frame(vd, s, T, rec), 0, t, tr);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && request_mode(rec, 16) == 1) tile_bins(rec, tr);
+    if (threadIdx.x == 0) {
+        Plane pl = plane_of(rec);
+        if (request_mode(pl, rec, 16) == 1) tile_bins(pl.kact, tr);
+    }
     __syncthreads();
-    if (ui(rec.mode) == 1) run_tile<DT, 256>(rec, tr, tl);
+    if (ui(rec.mode) == 1) run_tile<DT, 256, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl);
     else direct_tile<DT>(rec, t);
 }
 
@@ -716,9 +774,12 @@ __global__ void __launch_bounds__(kSetupThreads) k_tiles_setup(const BatchReq* _
             int* dst = reinterpret_cast<int*>(recs + r);
             for (int w = threadIdx.x; w < (int)(sizeof(SliceRec) / sizeof(int)); w += kSetupThreads) dst[w] = src[w];
         }
-        for (int k = threadIdx.x; k < nt; k += kSetupThreads) {
-            if (mode == 1) compute_tile(rec, r, k, tiles[base + k]);
-            else units[cap - 1 - (base + k)] = make_int2(r, mode == 0 ? ~k : k);
+        if (mode == 1) {
+            const Plane pl = plane_of(rec);
+            for (int k = threadIdx.x; k < nt; k += kSetupThreads) compute_tile(pl, r, k, tiles[base + k]);
+        } else {
+            for (int k = threadIdx.x; k < nt; k += kSetupThreads)
+                units[cap - 1 - (base + k)] = make_int2(r, mode == 0 ? ~k : k);
         }
         __syncthreads();
     }
@@ -739,7 +800,7 @@ __global__ void __launch_bounds__(kThreadsBatch) k_tiles(const SliceRec* __restr
     for (int u = beg + (int)(blockIdx.x >> 3); u < end; u += per) {
         const TileRec& tr = tiles[u];
         const SliceRec& rec = recs[ui(tr.r)];
-        run_tile<DT, kThreadsBatch>(rec, tr, tl);
+        run_tile<DT, kThreadsBatch, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl);
         __syncthreads();
     }
 }
