@@ -22,10 +22,60 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
 }
 
-// Nearest voxel of frame pixel (i, j); false when outside the grid.
-__device__ __forceinline__ bool pixel_voxel(const VolDev* __restrict__ vd, const FrameDesc* __restrict__ fd,
-                                            int i, int j, double sx, double sy, int& vx, int& vy, int& vz) {
-    return frame_voxel(fd, vd->origin, vd->inv_h, vd->nx, vd->ny, vd->nz, i, j, sx, sy, vx, vy, vz);
+// Pointers by address space: constant (what a whole workgroup reads and no running kernel
+// writes: scalar loads) and global (per-lane accesses and atomics: global, not flat, operations).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// What the per-pixel kernels read of the volume header, through scalar loads.
+struct PixelView {
+    double origin[3], inv_h;
+    int nx, ny, nz, nbx, nby;
+    int64_t nbricks;
+    const FrameDesc* frames;
+    const int32_t* frame_bin;
+    int32_t* table;
+};
+
+__device__ __forceinline__ PixelView pixel_view(const VolDev* vd) {
+    const cptr<VolDev> c = (cptr<VolDev>)vd;
+    PixelView v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v.origin[a] = c->origin[a];
+    v.inv_h = c->inv_h;
+    v.nx = c->nx;
+    v.ny = c->ny;
+    v.nz = c->nz;
+    v.nbx = c->nbx;
+    v.nby = c->nby;
+    v.nbricks = c->nbricks;
+    v.frames = c->frames;
+    v.frame_bin = c->frame_bin;
+    v.table = c->table;
+    return v;
+}
+
+// Frame f's placement (translation and raw columns; the unit axes are not needed here), through
+// scalar loads: a workgroup works on one frame.
+__device__ __forceinline__ FrameDesc frame_uniform(const PixelView& v, int f) {
+    const cptr<FrameDesc> p = (cptr<FrameDesc>)v.frames + f;
+    FrameDesc d;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d.t[a] = p->t[a];
+        d.e0[a] = p->e0[a];
+        d.e1[a] = p->e1[a];
+        d.xh[a] = 0.0;
+        d.nh[a] = 0.0;
+    }
+    d.pad = 0.0;
+    return d;
+}
+
+__device__ __forceinline__ int64_t brick_entry(const PixelView& v, int b, int vx, int vy, int vz) {
+    return (int64_t)b * v.nbricks + ((int64_t)(vz >> 3) * v.nby + (vy >> 3)) * v.nbx + (vx >> 3);
 }
 
 __device__ __forceinline__ int64_t brick_entry(const VolDev* vd, int b, int vx, int vy, int vz) {
@@ -154,18 +204,21 @@ __global__ void __launch_bounds__(256) k_assign_bins(VolDev* vd, int n, int K0) 
 }
 
 __device__ __forceinline__ void mark_entry(VolDev* vd, int64_t e) {
-    int32_t* te = vd->table + e;
-    const int cur = __atomic_load_n(te, __ATOMIC_RELAXED);
+    const gptr<int32_t> te = (gptr<int32_t>)vd->table + e;
+    const int cur = __hip_atomic_load(te, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cur == -1) {
-        if (atomicCAS(te, -1, -2) == -1) {
+        int expected = -1;
+        if (__hip_atomic_compare_exchange_strong(te, &expected, -2, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
             const uint32_t k = atomicAdd(&vd->st.new_count, 1u);
-            if (k < vd->cap) vd->new_list[k] = (int32_t)e;
+            if (k < vd->cap) ((gptr<int32_t>)vd->new_list)[k] = (int32_t)e;
         }
     } else if (cur >= 0) {
-        if (__atomic_load_n(vd->dirty_flags + cur, __ATOMIC_RELAXED) == 0u &&
-            atomicExch(vd->dirty_flags + cur, 1u) == 0u) {
+        const gptr<uint32_t> fl = (gptr<uint32_t>)vd->dirty_flags + cur;
+        if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+            __hip_atomic_exchange(fl, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
             const uint32_t d = atomicAdd(&vd->st.dirty_count, 1u);
-            vd->dirty_list[d] = cur;
+            ((gptr<int32_t>)vd->dirty_list)[d] = cur;
         }
     }
 }
@@ -182,11 +235,14 @@ __device__ __forceinline__ void mark_wave(VolDev* vd, int64_t e) {
 __global__ void __launch_bounds__(256) k_mark_pixels(VolDev* vd, int w, int h, double sx, double sy, int f0) {
     int bx, f;
     frame_block((w * h + 255) >> 8, f0, bx, f);
+    const PixelView v = pixel_view(vd);
+    const FrameDesc fd = frame_uniform(v, f);
+    const int bin = *((cptr<int32_t>)v.frame_bin + f);
     const int pix = bx * 256 + threadIdx.x;
     int64_t e = -1;
     int vx, vy, vz;
-    if (pix < w * h && pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz))
-        e = brick_entry(vd, vd->frame_bin[f], vx, vy, vz);
+    if (pix < w * h && frame_voxel(&fd, v.origin, v.inv_h, v.nx, v.ny, v.nz, pix % w, pix / w, sx, sy, vx, vy, vz))
+        e = brick_entry(v, bin, vx, vy, vz);
     mark_wave(vd, e);
 }
 
@@ -258,14 +314,22 @@ __global__ void __launch_bounds__(256) k_accumulate(const VolDev* __restrict__ v
                                                     int w, int h, double sx, double sy, int f0) {
     int bx, f;
     frame_block((w * h + 255) >> 8, f0, bx, f);
+    const PixelView v = pixel_view(vd);
+    const FrameDesc fd = frame_uniform(v, f);
+    const int bin = *((cptr<int32_t>)v.frame_bin + f);
+    const gptr<unsigned long long> acc = (gptr<unsigned long long>)((cptr<VolDev>)vd)->acc;
     const int pix = bx * 256 + threadIdx.x;
-    if (pix >= w * h) return;
-    int vx, vy, vz;
-    if (!pixel_voxel(vd, vd->frames + f, pix % w, pix / w, sx, sy, vx, vy, vz)) return;
-    const int slot = vd->table[brick_entry(vd, vd->frame_bin[f], vx, vy, vz)];
-    if (slot < 0) return;   // unreachable: every entry hit here was marked and allocated
-    const unsigned long long inten = frames[(size_t)f * w * h + pix];
-    atomicAdd(vd->acc + (size_t)slot * kBrickVox + brick_local(vx, vy, vz), (inten << 32) | 1ull);
+    int vx = 0, vy = 0, vz = 0;
+    const bool ok =
+        pix < w * h && frame_voxel(&fd, v.origin, v.inv_h, v.nx, v.ny, v.nz, pix % w, pix / w, sx, sy, vx, vy, vz);
+    // the pixel and its table entry, both loads in flight together (lanes without a voxel read
+    // entry 0 of each, and drop what they read)
+    const unsigned long long inten = ((gptr<const uint8_t>)frames)[ok ? (size_t)f * w * h + pix : 0];
+    const int slot = ((gptr<const int32_t>)v.table)[ok ? brick_entry(v, bin, vx, vy, vz) : 0];
+    asm volatile("" ::"v"(inten), "v"(slot));
+    if (!ok || slot < 0) return;   // slot < 0 is unreachable: every entry hit was marked and allocated
+    __hip_atomic_fetch_add(acc + (size_t)slot * kBrickVox + brick_local(vx, vy, vz), (inten << 32) | 1ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // K4 for fan frames.
