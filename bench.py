@@ -708,49 +708,61 @@ def run_out_of_core(dare, torch, geom, prm, frames, poses, pitch, total_bricks, 
     return res
 
 
-def run_evaluation(dare, torch, synth, wl, frames, poses, geom, every, bricks, log):
-    """Held-out frames (every ``every``-th, offset every/2) left out of the reconstruction and
-    resliced at their own poses from the rest, by DARE and by plain mean compounding (thresholds
-    at 180 degrees, k = 0: every sample weighs 1); each reslice scored with NCC and SSIM against
-    the acquired frame and against the same view rendered without speckle (the frames' speckle is
-    drawn independently per frame, so no reconstruction can predict it)."""
-    dev = frames.device
-    F, Hf, Wf = frames.shape
-    pitch = wl.sweep.pitch
-    held = [f for f in range(int(F)) if f % every == every // 2]
-    kept = torch.tensor([f for f in range(int(F)) if f % every != every // 2], device=dev)
-    fr_k, po_k = frames.index_select(0, kept).contiguous(), poses.index_select(0, kept).contiguous()
+def run_evaluation(dare, torch, synth, config, bricks, log):
+    """The evaluation protocol of Sec. 2.2 and Sec. 3 on config 1 or 2: reconstruct from the
+    initial sweep set at its tracked poses (each sweep misregistered by a seeded rigid offset),
+    reslice at the tracked poses of a secondary, different sweep, and score every reslice with
+    NCC and SSIM against that sweep's acquired frame and against the same view rendered without
+    speckle (speckle is drawn per frame, so no reconstruction can predict it); DARE against plain
+    mean compounding (thresholds at 180 degrees, k = 0: every sample weighs 1)."""
+    dev = torch.device("cuda:0")
+    pair = synth.eval_pair(config)
+    wl, sw = pair.initial, pair.secondary
+    frames = wl.render(dev)
+    sec = sw.render(dev)
+    poses = torch.from_numpy(np.ascontiguousarray(pair.initial_tracked)).to(dev)
+    geom = dare.make_geometry(wl.origin, wl.spacing, wl.dims, wl.calib)
+    G, Hf, Wf = sec.shape
+    pitch = sw.sweep.pitch
+    echo = synth.render.render_frames(dataclasses.replace(wl.phantom, speckle_sigma=0.0), sw.sweep.probe_poses,
+                                      wl.calib, Wf, Hf, pitch, seed=0, device=dev)
     ws_c = torch.empty(int(dare.lib.dare_compare_workspace_bytes()), dtype=torch.uint8, device=dev)
     img = torch.empty((Hf, Wf), dtype=torch.float32, device=dev)
-    echo = synth.render.render_frames(dataclasses.replace(wl.phantom, speckle_sigma=0.0),
-                                      np.asarray(wl.sweep.probe_poses)[held], wl.calib, Wf, Hf, pitch,
-                                      seed=0, device=dev)
-    out = {"held_out_frames": len(held), "reconstructed_from": int(kept.numel()), "frame_px": [Wf, Hf]}
+    out = {"initial_frames": int(frames.shape[0]), "secondary_frames": int(G), "frame_px": [Wf, Hf],
+           "tracking_offsets_mm_deg": pair.offsets_mm_deg,
+           "protocol": "reconstruct from the initial sweeps at their tracked poses; reslice at the secondary "
+                       "sweep's tracked poses; score against its frames (rendered at its true poses)"}
+    q = lambda xs: [round(float(np.nanpercentile(xs, p_)), 4) for p_ in (25, 50, 75)]  # noqa: E731
     for name, prm_e in (("dare", dare.default_params()),
                         ("plain_mean", dare.default_params(k_normal=0.0, k_inplane=0.0, thr_normal_deg=180.0,
                                                            thr_inplane_deg=180.0))):
         v_e = dare.Volume(geom, prm_e, dtype="f32", bricks=bricks)
-        v_e.reconstruct(fr_k, po_k, pitch)
+        v_e.reconstruct(frames, poses, wl.sweep.pitch)
         res = {"vs_frame": ([], []), "vs_echo": ([], [])}
         fracs = []
         t_cmp = 0.0
-        for k, f in enumerate(held):
-            v_e.reslice(wl.sweep.probe_poses[f], Wf, Hf, pitch, out=img)
+        for k in range(G):
+            v_e.reslice(pair.secondary_tracked[k], Wf, Hf, pitch, out=img)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            c = dare.compare_to_frame(img, frames[f], ws_c)
+            c = dare.compare_to_frame(img, sec[k], ws_c)
             t_cmp += time.perf_counter() - t0
             ce = dare.compare_to_frame(img, echo[k], ws_c)
             for key, cc in (("vs_frame", c), ("vs_echo", ce)):
                 res[key][0].append(cc[0])
                 res[key][1].append(cc[1])
             fracs.append(c[2] / (Wf * Hf))
-        q = lambda xs: [round(float(np.nanpercentile(xs, p_)), 4) for p_ in (25, 50, 75)]  # noqa: E731
-        out[name] = {key: {"ncc_q25_median_q75": q(v[0]), "ssim_q25_median_q75": q(v[1])} for key, v in res.items()}
+        out[name] = {}
+        for key, (ncc, ssim) in res.items():
+            qn, qs = q(ncc), q(ssim)
+            out[name][key] = {"ncc_q25_median_q75": qn, "ncc_iqr": round(qn[2] - qn[0], 4),
+                              "ssim_q25_median_q75": qs, "ssim_iqr": round(qs[2] - qs[0], 4)}
         out[name]["assigned_fraction_mean"] = round(float(np.mean(fracs)), 4)
-        out[name]["compare_ms_per_image"] = round(1e3 * t_cmp / len(held), 3)
-        log(f"evaluation {wl.name.split(':')[0]} {name}: {out[name]}")
+        out[name]["compare_ms_per_image"] = round(1e3 * t_cmp / G, 3)
+        log(f"evaluation config {config} {name}: {out[name]}")
         del v_e
+    del frames, sec, echo, poses
+    torch.cuda.synchronize()
     return out
 
 
@@ -1369,24 +1381,46 @@ def main():
                     "max_abs_grey": round(float(d.max().item()) if d.numel() else 0.0, 4),
                     "mean_abs_grey": round(float(d.mean().item()) if d.numel() else 0.0, 5),
                     "nan_mask_mismatch": int((torch.isfinite(a) != torch.isfinite(b)).sum().item())}
+                # the binning tolerance: the same comparison with the grid binned at smaller delta,
+                # and the largest delta at which the worst pixel differs by less than one grey level
+                sweep_d = []
+                tmp = torch.empty((H, W), dtype=torch.float32, device=dev)
+                for tol in (5.0, 3.0, 2.0, 1.0, 0.5):
+                    v_d = dare.Volume(geom, dare.default_params(bin_tol_deg=tol), dtype="f32", bricks=nb * 64)
+                    st_d = v_d.reconstruct(frames, poses, pitch_f)
+                    worst, tot, cnt, mism = 0.0, 0.0, 0, 0
+                    for k in range(nl):
+                        v_d.reslice(sl.probe_poses[k], W, H, pitch, out=tmp)
+                        a_k, b_k = lit_out[k].double(), tmp.double()
+                        both_k = torch.isfinite(a_k) & torch.isfinite(b_k)
+                        d_k = (a_k - b_k).abs()[both_k]
+                        if d_k.numel():
+                            worst = max(worst, float(d_k.max().item()))
+                            tot += float(d_k.sum().item())
+                            cnt += int(d_k.numel())
+                        mism += int((torch.isfinite(a_k) != torch.isfinite(b_k)).sum().item())
+                    inf_d = v_d.info()
+                    sweep_d.append({"bin_tol_deg": tol, "bins": int(inf_d.bins), "saturated": bool(inf_d.saturated),
+                                    "max_abs_grey": round(worst, 4), "mean_abs_grey": round(tot / max(cnt, 1), 5),
+                                    "nan_mask_mismatch": mism})
+                    del v_d, st_d
+                below = [e["bin_tol_deg"] for e in sweep_d if e["max_abs_grey"] < 1.0]
+                literal_res["tent_vs_binned_by_bin_tol"] = sweep_d
+                literal_res["largest_bin_tol_below_one_grey"] = max(below) if below else None
+                del tmp
             log(f"per-sample store {mode_name}: {ms * 1e3:.1f} us per 512^2 slice ({n_samples} samples)")
         log(f"per-sample store: {literal_res}")
         del store, lit_out
         torch.cuda.synchronize()
 
-    # ---- evaluation protocol (Sec. 3: NCC and SSIM of reslices against the acquired frames) on
-    # held-out frames of config 1 (two sweeps whose beams are tilted +-20 deg: the views differ in
-    # direction) and config 2 (three azimuths with vertical beams: the views share the beam)
+    # ---- evaluation protocol (Sec. 2.2, Sec. 3): NCC and SSIM of reslices at a secondary sweep's
+    # poses against its frames, the volume built from a different, misregistered sweep set; config 1
+    # (two sweeps tilted +-20 deg, secondary at +10 deg) and config 2 (three azimuths, secondary at
+    # 10 deg azimuth)
     evaluation = None
     if not args.no_forms and not args.no_literal:
-        wl1 = synth.config1()
-        fr1 = wl1.render(dev)
-        po1 = torch.from_numpy(np.ascontiguousarray(wl1.sweep.probe_poses, np.float32)).to(dev)
-        g1 = dare.make_geometry(wl1.origin, wl1.spacing, wl1.dims, wl1.calib)
-        evaluation = {"config1": run_evaluation(dare, torch, synth, wl1, fr1, po1, g1, 10, None, log),
-                      "config2": run_evaluation(dare, torch, synth, wl, frames, poses, geom, 20, nb * 40, log)}
-        del fr1, po1
-        torch.cuda.synchronize()
+        evaluation = {"config1": run_evaluation(dare, torch, synth, 1, None, log),
+                      "config2": run_evaluation(dare, torch, synth, 2, nb * 40, log)}
 
     # ---- curvilinear probes (binning per column sector) and out-of-core bricks
     curvilinear, out_of_core = None, None

@@ -23,4 +23,5 @@ from .sweeps import (  # noqa: F401
 from .render import render_frames  # noqa: F401
 from .configs import (  # noqa: F401
     Workload, config1, config2, config3_slices, config5, serving_volume, tiny_workload, fan_beams, fan_config, fan_config2,
+    EvalPair, eval_pair, tracking_offsets, tracked,
 )

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .phantom import Phantom, make_phantom
-from .poses import WORLD_OFFSET_MM, make_calibration
+from .poses import WORLD_OFFSET_MM, make_calibration, rotvec_to_matrix
 from .render import render_frames
 from .sweeps import SliceSet, Sweep, azimuth_sweeps, linear_tilted_sweeps, random_walk_sweep, slice_poses
 
@@ -158,3 +158,79 @@ def tiny_workload(seed: int, N: int = 8, n_frames: int = 6, w: int = 6, n_slices
                      (N * h / slice_w, N * h / slice_h), N, h, C, max_rot_deg=20.0)
     return Workload(f"tiny {N}^3 seed {seed}", (N, N, N), h, WORLD_OFFSET_MM.copy(), C, ph, sw, sl,
                     frame_seed=seed)
+
+
+# ---- evaluation protocol: an initial sweep set for reconstruction and a secondary, different
+# sweep for reslicing and ground truth, each sweep tracked with a rigid misregistration of its own
+
+@dataclass
+class EvalPair:
+    initial: Workload            # frames rendered at true poses; reconstruct with `initial_tracked`
+    initial_tracked: np.ndarray  # (F,4,4) float32 tracked probe poses of the initial frames
+    secondary: Workload          # its frames are the ground truth
+    secondary_tracked: np.ndarray  # (G,4,4) float32 tracked poses: the reslice poses
+    offsets_mm_deg: list         # per sweep (initial sweeps, then the secondary): |t| mm, angle deg
+
+
+def tracking_offsets(seed: int, n: int, centre, trans_mm: float, rot_deg: float) -> list:
+    """n rigid world transforms (4x4): a rotation about ``centre`` by a rotation vector with
+    N(0, rot_deg) components, then a translation with N(0, trans_mm) components."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    c = np.asarray(centre, np.float64)
+    for _ in range(n):
+        R = rotvec_to_matrix(np.deg2rad(rng.normal(0.0, rot_deg, 3)))
+        t = rng.normal(0.0, trans_mm, 3)
+        M = np.eye(4)
+        M[:3, :3] = R
+        M[:3, 3] = c - R @ c + t
+        out.append(M)
+    return out
+
+
+def tracked(sweep: Sweep, offsets: list) -> np.ndarray:
+    """What the tracker reports: sweep k's true probe poses moved by offsets[k]."""
+    P = np.asarray(sweep.probe_poses, np.float64)
+    out = np.empty_like(P)
+    for f in range(len(P)):
+        out[f] = offsets[int(sweep.sweep_id[f])] @ P[f]
+        out[f, 3, :] = (0.0, 0.0, 0.0, 1.0)
+    return out.astype(np.float32)
+
+
+def _offset_size(M: np.ndarray, centre) -> tuple:
+    """(displacement of the volume centre in mm, rotation angle in degrees)."""
+    c = np.asarray(centre, np.float64)
+    ang = float(np.degrees(np.arccos(np.clip((np.trace(M[:3, :3]) - 1.0) / 2.0, -1.0, 1.0))))
+    return (round(float(np.linalg.norm(M[:3, :3] @ c + M[:3, 3] - c)), 3), round(ang, 3))
+
+
+def eval_pair(config: int, trans_vox: float = 0.5, rot_lever_vox: float = 0.5) -> EvalPair:
+    """The two-sweep protocol on config 1 or 2.  Config 1: the two +-20 degree tilted sweeps,
+    then a secondary sweep of 40 frames tilted +10 degrees (10 degrees from one initial sweep,
+    30 from the other).  Config 2: the three azimuth sweeps, then a secondary sweep of 60 frames
+    at azimuth 10 degrees with the same jitter.  Secondary frames use speckle of their own.
+    Tracking offsets per sweep: translation components N(0, trans_vox voxels), rotation-vector
+    components N(0, r) with r the angle that moves a point half the grid away by rot_lever_vox
+    voxels, so that misregistration is of the order of a voxel at every grid size."""
+    if config == 1:
+        wl = config1()
+        N, h = wl.dims[0], wl.spacing
+        sec = linear_tilted_sweeps(N, h, 40, wl.sweep.width, wl.sweep.height, wl.sweep.pitch, (10.0,), wl.calib)
+        seed = 11
+    elif config == 2:
+        wl = config2(n_slices=1, n_near=1)
+        N, h = wl.dims[0], wl.spacing
+        sec = azimuth_sweeps(N, h, 60, wl.sweep.width, wl.sweep.height, wl.sweep.pitch, (10.0,), 1.0, 2.0,
+                             seed=224, calib=wl.calib)
+        seed = 22
+    else:
+        raise ValueError(config)
+    centre = WORLD_OFFSET_MM + 0.5 * (N - 1) * h
+    n0 = int(wl.sweep.sweep_id.max()) + 1
+    rot_deg = float(np.degrees(rot_lever_vox / (0.5 * N)))
+    offs = tracking_offsets(seed, n0 + 1, centre, trans_vox * h, rot_deg)
+    sw = Workload(wl.name + " secondary sweep", wl.dims, h, wl.origin, wl.calib, wl.phantom, sec, wl.slices,
+                  frame_seed=wl.frame_seed + 1000)
+    return EvalPair(initial=wl, initial_tracked=tracked(wl.sweep, offs[:n0]), secondary=sw,
+                    secondary_tracked=tracked(sec, [offs[n0]]), offsets_mm_deg=[_offset_size(M, centre) for M in offs])
