@@ -340,16 +340,27 @@ __device__ __forceinline__ void load_slots(const SliceRec& rec, const TileRec& t
     const gptr<const int32_t> table = global(rec.vol.table);
     const int64_t nbricks = rec.vol.nbricks;
     const int nbx = ui(rec.vol.nbx), nby = ui(rec.vol.nby);
+    // below 2^24 bricks per bin (grids up to 2048^3) every index product fits 24 x 24 -> 32 bits
+    const bool small = nbricks < (int64_t)1 << 24;
+    const uint32_t nb32 = (uint32_t)ui((int)(nbricks & 0xFFFFFF));
 #pragma unroll
     for (int i = 0; i < slots_per_thread<NT>(); ++i) {
         const int e = (int)threadIdx.x + NT * i;
-        const int bb = sdiv(e, dk), k = e - bb * kactp;
+        const int bb = sdiv(e, dk), k = e - (int)__umul24((uint32_t)bb, (uint32_t)kactp);
         sl[i] = -1;
         if (e < n && k < kact) {
-            const int byz = sdiv(bb, dx), bx = bb - byz * bdx;
-            const int bz = sdiv(byz, dy), by = byz - bz * bdy;
-            const int64_t brick = ((int64_t)(bz0 + bz) * nby + (by0 + by)) * nbx + (bx0 + bx);
-            sl[i] = table[(int64_t)rec.act_bin[k] * nbricks + brick];
+            const int byz = sdiv(bb, dx), bx = bb - (int)__umul24((uint32_t)byz, (uint32_t)bdx);
+            const int bz = sdiv(byz, dy), by = byz - (int)__umul24((uint32_t)bz, (uint32_t)bdy);
+            const int bin = rec.act_bin[k];
+            if (small) {
+                const uint32_t brick =
+                    __umul24(__umul24((uint32_t)(bz0 + bz), (uint32_t)nby) + (uint32_t)(by0 + by), (uint32_t)nbx) +
+                    (uint32_t)(bx0 + bx);
+                sl[i] = table[__umul24((uint32_t)bin, nb32) + brick];
+            } else {
+                const int64_t brick = ((int64_t)(bz0 + bz) * nby + (by0 + by)) * nbx + (bx0 + bx);
+                sl[i] = table[(int64_t)bin * nbricks + brick];
+            }
         }
     }
 }
