@@ -551,6 +551,11 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, budget_seconds, log, s
     log(f"serving at 64 x 30 Hz: {offered}")
     sat, mix = run_closed(srv, consoles, bufs, ring, sizes, sat_seconds, synth)
     log(f"serving saturated (closed loop, 2 in flight per console, grouped submit/poll): {sat}")
+    # (d) the same closed loop delivering into device buffers: no transfer over the host link
+    dbufs = [[torch.empty((1024 * 1024,), dtype=torch.float32, device=dev) for _ in range(ring)] for _ in range(64)]
+    sat_dev, _ = run_closed(srv, consoles, dbufs, ring, sizes, 0.5 * sat_seconds, synth)
+    log(f"serving saturated, results delivered to device buffers: {sat_dev}")
+    del dbufs
     srv.close()
 
     # the served path's roofline: the saturation run's algorithmic bytes over the union of its
@@ -610,7 +615,7 @@ def run_serving(dare, torch, synth, seconds, sat_seconds, budget_seconds, log, s
 
     res = {"volumes": [list(w.dims) for w in wls], "volume_MB": [round(b / 1e6, 1) for b in vol_bytes],
            "dtype": "bf16", "consoles": 64, "rate_hz_per_console": 30, "sizes": list(sizes), "offered": offered,
-           "saturation": sat, "small_budget": small}
+           "saturation": sat, "saturation_device_delivery": sat_dev, "small_budget": small}
     sample = {"workloads": wls[:3], "frames": host_frames[:3], "items": served_sample}
     return res, roofline_served, sample
 

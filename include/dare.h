@@ -408,7 +408,9 @@ dare_status dare_copy_probe(const void* src_dev, void* dst_dev, uint64_t n_bytes
  * size can be allocated in the arena; each tick uploads its request table,
  * replays a captured graph of the batched reslice on a free stream (ticks on
  * different streams overlap on the device), then copies every result into its
- * `host_out` buffer (pinned host memory keeps the copy asynchronous).
+ * `host_out` buffer (pinned host memory keeps the copy asynchronous; a device
+ * buffer on the server's GPU keeps the result there, with no transfer over
+ * the host link).
  * Volumes are admitted against a second budget, `volume_budget_bytes`: the
  * device bytes of the resident volumes' arenas (Sec. 4 names dataset size
  * against GPU memory as the limit to plan for); a removed volume returns its
@@ -466,7 +468,9 @@ dare_status dare_server_remove_volume(dare_server* s, int32_t volume_id, double 
 /* Device bytes and number of the volumes currently registered. */
 dare_status dare_server_volume_bytes(dare_server* s, uint64_t* resident_bytes, int32_t* resident_volumes);
 /* Queue a request.  host_out (required) receives height*width float32,
- * row-major, NaN where unassigned, once the request completes.  Returns
+ * row-major, NaN where unassigned, once the request completes: host memory
+ * (pinned or pageable) or device memory of the server's GPU, which must stay
+ * valid until the ticket completes.  Returns
  * QUEUE_FULL when max_queue requests wait, and INVALID_ARG when the request
  * can never fit the arena's result space or one tick. */
 dare_status dare_server_submit(dare_server* s, int32_t volume_id, const dare_slice_spec* spec,
@@ -493,8 +497,8 @@ dare_status dare_server_submit_frames(dare_server* s, int32_t volume_id, const u
 dare_status dare_server_submit_many(dare_server* s, int32_t n, const int32_t* volume_ids,
                                     const dare_slice_spec* specs, float* const* host_outs,
                                     uint64_t* tickets, int32_t* accepted);
-/* DARE_OK with *times filled (may be NULL) once the result is in host
- * memory, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed; for a
+/* DARE_OK with *times filled (may be NULL) once the result is in its
+ * host_out buffer, DARE_ERR_NOT_READY before, DARE_ERR_HIP if its tick failed; for a
  * frames ticket, its compounding status once compounded.  A ticket is
  * forgotten once poll has returned anything but NOT_READY. */
 dare_status dare_server_poll(dare_server* s, uint64_t ticket, dare_request_times* times);

@@ -360,7 +360,8 @@ bool launch_tick(dare_server* S, Slot& sl) {
     if (e == hipSuccess) e = hipEventRecord(sl.ev_kernels, sl.stream);
     for (size_t k = 0; e == hipSuccess && k < sl.tickets.size(); ++k) {
         Request& r = S->reqs[sl.tickets[k]];
-        e = hipMemcpyAsync(r.host_out, S->arena + r.out_off, r.bytes, hipMemcpyDeviceToHost, sl.stream);
+        // the result's destination may be host memory or device memory (unified addressing)
+        e = hipMemcpyAsync(r.host_out, S->arena + r.out_off, r.bytes, hipMemcpyDefault, sl.stream);
     }
     if (e == hipSuccess) e = hipEventRecord(sl.ev_done, sl.stream);
     const double t_launch = now_s();

@@ -1,8 +1,8 @@
 """GPU parity at the benchmark's full size: the config-2 volume (256^3 at 0.125 mm from 3 x 600
 frames of 256^2) and 512^2 slices at 0.0625 mm, resliced the way the benchmark times them (one
 launch per slice, and a call of 64 slices), checked on seeded sampled pixels that the FP64 oracle
-computes one by one (a 1 x 1 slice placed at the pixel), plus the compounded sums on sampled
-bricks.  Bars as in the other parity tests: |d| <= 1e-5 max(|ref|, 1), identical NaN masks,
+computes one by one (a 1 x 1 slice placed at the pixel), ten whole slices against the oracle's
+own full-size reslices (one launch each and batched), plus the compounded sums on sampled bricks.  Bars as in the other parity tests: |d| <= 1e-5 max(|ref|, 1), identical NaN masks,
 batched = alone bit for bit.
 """
 from __future__ import annotations
@@ -97,6 +97,42 @@ def test_config2_one_launch_per_slice_sampled(c2):
                 assert abs(got - ref) <= 1e-5 * max(abs(ref), 1.0), (k, i, j, got, ref)
                 checked += 1
     assert checked > SAMPLES          # the near-acquired slices are mostly assigned
+
+
+# whole slices: near-acquired ones spread over the set, and uniformly oriented ones
+WHOLE = (2, 63, 250, 500, 640, 798, 801, 900, 950, 998)
+
+
+def test_config2_whole_slices_single_and_batched(c2):
+    """Every pixel of ten full-size slices against the oracle's own 512^2 reslices, resliced one
+    launch each and in one batched call."""
+    dare, torch, wl, vol, g, prm = c2
+    sl = wl.slices
+    a, c = g.mean_count()
+    rn, rx = g.codebook.arrays()
+    specs = [dare.make_spec(sl.probe_poses[k], sl.width, sl.height, sl.pitch) for k in WHOLE]
+    n = len(WHOLE)
+    single = torch.full((n, sl.height, sl.width), -3.0, device="cuda")
+    for m in range(n):
+        dare.dare_reslice(vol, specs[m], single[m])
+    batched = torch.full((n, sl.height, sl.width), -5.0, device="cuda")
+    ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([vol] * n, specs), dtype=torch.uint8, device="cuda")
+    dare.dare_reslice_batch([vol] * n, specs, [batched[m] for m in range(n)], ws)
+    torch.cuda.synchronize()
+    single = single.cpu().numpy().astype(np.float64)
+    batched = batched.cpu().numpy().astype(np.float64)
+    assigned = 0
+    for m, k in enumerate(WHOLE):
+        note(f"config 2 slice {k}: all {sl.width * sl.height} pixels against the oracle")
+        ref = reslice.reslice(a, c, g.origin, g.spacing, rn, rx, wl.calib, sl.probe_poses[k], sl.width, sl.height,
+                              sl.pitch, prm)
+        for got in (single[m], batched[m]):
+            assert np.array_equal(np.isnan(got), np.isnan(ref)), k
+            ok = ~np.isnan(ref)
+            err = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), 1.0)
+            assert err.size == 0 or err.max() <= 1e-5, (k, float(err.max()))
+        assigned += int((~np.isnan(ref)).sum())
+    assert assigned > 1_000_000
 
 
 def test_config2_batch_of_64_equals_alone(c2):

@@ -232,3 +232,26 @@ def test_frames_compounded_in_request_order(env):
             assert np.array_equal(o.numpy(), ref.cpu().numpy(), equal_nan=True), k
     # before any frame every result is unassigned
     assert all(np.isnan(o.numpy()).all() for o in outs[0])
+
+
+def test_served_into_device_buffers_equals_alone(env):
+    """Results delivered to device buffers (no host transfer) equal the requests resliced alone."""
+    dare, torch, wl, vols = env
+    note("server delivering into device buffers")
+    reqs = _requests(wl, 24, seed=77)
+    ref = _alone(dare, torch, vols, reqs)
+    srv = dare.Server(64 << 20, n_streams=2, max_tick_requests=8)
+    ids = [srv.add_volume(v) for v in vols]
+    outs = [torch.full((H, W), -5.0, dtype=torch.float32, device="cuda") for (_, _, W, H, _) in reqs]
+    tickets = []
+    for (vi, P, W, H, pitch), o in zip(reqs, outs):
+        t = None
+        while t is None:
+            t = srv.submit(ids[vi], P, W, H, pitch, o)
+        tickets.append(t)
+    srv.drain()
+    assert all(srv.poll(t) is not None for t in tickets)
+    srv.close()
+    torch.cuda.synchronize()
+    for k in range(len(reqs)):
+        assert np.array_equal(outs[k].cpu().numpy(), ref[k], equal_nan=True), k
