@@ -595,15 +595,22 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         ey[a] = ud(rec.ey[a]);
     }
     const int shift = T == kTileBig ? 5 : 4;
+    // a thread keeps its column (NT is a multiple of the tile edge): the column's part of the
+    // position is computed once
+    static_assert(NT % kTileBig == 0, "threads of a workgroup cover whole tile rows");
+    const int li = (int)threadIdx.x & (T - 1), i = i0 + li;
+    double ci[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ci[a] = fma((double)i, ex[a], c00[a]);
     for (int idx = (int)threadIdx.x; idx < T * T; idx += NT) {
-        const int li = idx & (T - 1), lj = idx >> shift;
+        const int lj = idx >> shift;
         if (li >= ni || lj >= nj) continue;
-        const int i = i0 + li, j = j0 + lj;
+        const int j = j0 + lj;
         const gptr<float> out = outp + (size_t)j * W + i;
-        const double di = (double)i, dj = (double)j;
+        const double dj = (double)j;
         double c[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) c[a] = fma(dj, ey[a], fma(di, ex[a], c00[a]));
+        for (int a = 0; a < 3; ++a) c[a] = fma(dj, ey[a], ci[a]);
         if (!(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] && c[2] >= -1.0 &&
               c[2] < (double)n[2])) {
             *out = __builtin_nanf("");
