@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "dare_alloc.h"
+#include "dare_spans.h"
 #include "dare_staged.h"
 
 using namespace dare;
@@ -103,9 +104,7 @@ struct DeviceClock {
     bool moving = false;          // ref[1 - cur] recorded, not yet reached
     double off = 0.0;             // seconds from the first reference to ref[cur]
     double host_t = 0.0;          // host time at which ref[cur] was taken
-    double kernel_seconds = 0.0;  // sum of spans
-    double folded = 0.0;          // union of the spans no later span can overlap
-    std::vector<std::pair<double, double>> open;   // the other spans
+    SpanUnion spans;              // the ticks' kernel spans: their sum and their union
 
     hipError_t init(double now) {
         hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
@@ -141,18 +140,7 @@ struct DeviceClock {
             host_t = now;
         }
     }
-    // Add the span [t0, t1].  No span added later starts before `horizon`.
-    void add(double t0, double t1, double horizon) {
-        kernel_seconds += t1 - t0;
-        open.emplace_back(t0, t1);
-        if (open.size() < 256) return;
-        std::sort(open.begin(), open.end());
-        std::vector<std::pair<double, double>> keep;
-        double a = open[0].first, b = open[0].second;
-        auto flush = [&](double x, double y) {
-            if (y <= horizon) folded += y - x;
-            else keep.emplace_back(x, y);
-        };
+};
         for (size_t k = 1; k < open.size(); ++k) {
             if (open[k].first <= b) {
                 b = std::max(b, open[k].second);
@@ -262,8 +250,8 @@ void time_tick(dare_server* S, Slot& sl) {
         const Slot& o = S->slots[k];
         if (o.busy && &o != &sl && !o.kernels_seen) horizon = std::min(horizon, o.last_end);
     }
-    S->clock.add(t0, t1, horizon);
-    S->stats.kernel_seconds = S->clock.kernel_seconds;
+    S->clock.spans.add(t0, t1, horizon);
+    S->stats.kernel_seconds = S->clock.spans.sum();
 }
 
 // Complete finished ticks.  Caller holds the lock.
@@ -762,7 +750,7 @@ dare_status dare_server_get_stats(dare_server* S, dare_server_stats* out) {
     std::lock_guard<std::mutex> lk(S->mu);
     *out = S->stats;
     if (S->busy_since >= 0.0) out->busy_seconds += now_s() - S->busy_since;
-    out->device_busy_seconds = S->clock.busy();
+    out->device_busy_seconds = S->clock.spans.busy();
     return DARE_OK;
 }
 
