@@ -141,30 +141,6 @@ struct DeviceClock {
         }
     }
 };
-        for (size_t k = 1; k < open.size(); ++k) {
-            if (open[k].first <= b) {
-                b = std::max(b, open[k].second);
-            } else {
-                flush(a, b);
-                a = open[k].first;
-                b = open[k].second;
-            }
-        }
-        flush(a, b);
-        open.swap(keep);
-    }
-    double busy() const {
-        std::vector<std::pair<double, double>> v(open);
-        std::sort(v.begin(), v.end());
-        double u = folded, b = -1e300;
-        for (const auto& iv : v) {
-            if (iv.second <= b) continue;
-            u += iv.second - std::max(iv.first, b);
-            b = iv.second;
-        }
-        return u;
-    }
-};
 
 }  // namespace
 
