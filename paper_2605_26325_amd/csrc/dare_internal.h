@@ -32,7 +32,7 @@ constexpr int kBrickVox = 512;
 // every line it touches, where x-fastest rows of 8 would be used for 2-3 voxels of 8 when the
 // normal is near x.  Every kernel that reads or writes brick storage (accumulators, stored
 // pairs) takes positions from here.
-__host__ __device__ inline int brick_local(int vx, int vy, int vz) {
+__host__ __device__ constexpr int brick_local(int vx, int vy, int vz) {
     return ((vx & 6) << 6) | ((vy & 6) << 4) | ((vz & 6) << 2) | ((vz & 1) << 2) | ((vy & 1) << 1) | (vx & 1);
 }
 constexpr int kMaxBins = 64;
@@ -106,6 +106,7 @@ struct VolView {
     int64_t nbricks;
     int32_t n[3];
     int32_t nbx, nby;
+    uint32_t cap;                         // slots in the pool
     double origin[3];
     double inv_h;
 };

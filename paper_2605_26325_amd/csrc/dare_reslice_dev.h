@@ -226,6 +226,7 @@ __device__ __forceinline__ VolView view_of(const VolDev* __restrict__ vd) {
     v.n[2] = vd->nz;
     v.nbx = vd->nbx;
     v.nby = vd->nby;
+    v.cap = vd->cap;
 #pragma unroll
     for (int a = 0; a < 3; ++a) v.origin[a] = vd->origin[a];
     v.inv_h = vd->inv_h;

@@ -17,8 +17,8 @@
 //           LDS as one float, NaN when no surviving bin holds a sample (or the voxel lies
 //           outside the grid);
 //   pixels  FP64 position, the 8 cell values from LDS, tent weights, num / den or NaN.
-// A pixel whose 8 corners are all valid sums w V and w directly; a NaN corner sends it to the
-// sums over its valid corners only (w * 0 and w * 1 terms, the same bits where all are valid).
+// Where all 8 corners are valid the tent weights sum to 1 and the blend is the trilinear
+// interpolation (nested lerps); a NaN corner sends the pixel to the sums over its valid corners.
 //
 // A single reslice launches one workgroup per 16 x 16 tile; each workgroup evaluates the
 // request setup and its tile's record itself, since no other memory holds them: the bins on one
@@ -61,7 +61,7 @@ struct TileLds {
     alignas(16) int slot[kSlotsMax];                      // [box brick][bin], rows of kactp
     float2 scale[DT == DARE_FP8_E4M3 ? kSlotsMax : 1];    // FP8 value and count scales per slot
     signed char rs[kColsMax];                             // first voxel of each column's run, less lo_d
-    float V[kItemsMax];                                   // V_v, or NaN where not valid, [column][run]
+    alignas(16) float V[kItemsMax];                       // V_v, or NaN where not valid, [column][run]
     int list[kItemsMax];                                  // voxels to gather: e | local << 11 | brick << 20
     int nlist;
 };
@@ -427,11 +427,26 @@ __device__ __forceinline__ int run_start(const float (&c0)[3], const float (&m)[
     return (int)floorf(centre - half) + 1;
 }
 
+// The bits that voxel coordinate v along axis A contributes to its brick-local index: the index
+// interleaves the coordinates' bits, so it is the sum (an OR of disjoint fields) of one part per
+// axis, and a list entry can add the dominant axis's part to a per-column remainder.
+template <int A>
+__host__ __device__ constexpr int local_part(int v) {
+    return A == 0 ? ((v & 6) << 6) | (v & 1) : (A == 1 ? ((v & 6) << 4) | ((v & 1) << 1) : (v & 7) << 2);
+}
+constexpr bool local_parts_match() {
+    for (int x = 0; x < 8; ++x)
+        for (int y = 0; y < 8; ++y)
+            for (int z = 0; z < 8; ++z)
+                if (brick_local(x, y, z) != (local_part<0>(x) | local_part<1>(y) | local_part<2>(z))) return false;
+    return true;
+}
+static_assert(local_parts_match(), "the brick-local index is the sum of its per-axis parts");
+
 // Voxels phase, first part: one thread per box column (p, q) walks the column's run along the
 // dominant axis; each voxel is tested against the tile's slab and lateral extent (the test terms
-// of the column computed once, the axis term added per voxel).  Voxels outside (or outside the
-// grid) get (0, 0); the others are appended to the gather list (one LDS counter update per wave
-// and voxel of the run).
+// of the column computed once, the axis term added per voxel).  The voxels that pass are appended
+// to the gather list; the others keep the NaN that the run's entries of V start from.
 template <int DT, int DAX, int NT>
 __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
@@ -441,6 +456,8 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
     const int n[3] = {ui(rec.vol.n[0]), ui(rec.vol.n[1]), ui(rec.vol.n[2])};
     const int blo[3] = {ui(tr.blo[0]), ui(tr.blo[1]), ui(tr.blo[2])};
     const int bdx = ui(tr.bdim[0]), bdy = ui(tr.bdim[1]);
+    // box brick index = sum over axes of (v_a / 8 - blo_a) * stride_a
+    const int bstride[3] = {1, bdx, bdx * bdy};
     float m[3], fu[3], fw[3], c0[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -451,8 +468,8 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
     }
     const float thr_n = uf(tr.thr_n), thr_u = uf(tr.thr_u), thr_v = uf(tr.thr_v), hi_u = uf(tr.hi_u), hi_v = uf(tr.hi_v);
     const float inv_md = uf(tr.inv_md), half = uf(tr.half);
-    const int lane = (int)threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
+    // voxels along the dominant axis that may pass: inside the box and the grid
+    const int vlo = max(lo_d, 0), vhi = min(hi_d, n[DAX] - 1);
     for (int cb = 0; cb < ncols; cb += NT) {
         const int col = cb + (int)threadIdx.x;
         const bool live = col < ncols;
@@ -462,36 +479,30 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
         // a column that a pixel's cell uses has its run start within [lo_d - depth, lo_d + kRunSpan]
         if (live) tl.rs[col] = (signed char)min(max(rs - lo_d, -128), 127);
         const bool col_in = live && (unsigned)vp < (unsigned)n[PAX] && (unsigned)vq < (unsigned)n[QAX];
+        const int chi = col_in ? vhi : -1;
         const float dp = (float)vp - c0[PAX], dq = (float)vq - c0[QAX];
         const float bn = m[PAX] * dp + m[QAX] * dq;
         const float bu = fu[PAX] * dp + fu[QAX] * dq;
         const float bw = fw[PAX] * dp + fw[QAX] * dq;
-        int vb[3];
-        vb[PAX] = vp;
-        vb[QAX] = vq;
-        vb[DAX] = 0;
-        const int e0 = (int)__umul24((uint32_t)col, (uint32_t)depth);
+        // the column's part of a list entry (wrapping arithmetic: only passing voxels, whose
+        // coordinates lie in the grid, use it, and their entry is in range)
+        const uint32_t ent0 =
+            (uint32_t)__umul24((uint32_t)col, (uint32_t)depth) +
+            ((uint32_t)(local_part<PAX>(vp) | local_part<QAX>(vq)) << 11) +
+            ((uint32_t)(((vp >> 3) - blo[PAX]) * bstride[PAX] + ((vq >> 3) - blo[QAX]) * bstride[QAX] -
+                        blo[DAX] * bstride[DAX])
+             << 20);
         for (int k = 0; k < depth; ++k) {
             const int vd = rs + k;
-            vb[DAX] = vd;
             const float dd = (float)vd - c0[DAX];
             const float dn = bn + m[DAX] * dd, du = bu + fu[DAX] * dd, dv = bw + fw[DAX] * dd;
-            const bool pass = col_in && vd >= lo_d && vd <= hi_d && (unsigned)vd < (unsigned)n[DAX] &&
-                              fabsf(dn) < thr_n && du > -thr_u && du < hi_u && dv > -thr_v && dv < hi_v;
-            const int e = e0 + k;
-            if (live && !pass) tl.V[e] = __builtin_nanf("");
-            const unsigned long long mask = __ballot(pass);
-            if (mask == 0ull) continue;
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&tl.nlist, (int)__popcll(mask));
-            base = __shfl(base, 0);
+            const bool pass = vd >= vlo && vd <= chi && fabsf(dn) < thr_n && du > -thr_u && du < hi_u &&
+                              dv > -thr_v && dv < hi_v;
             if (pass) {
-                const int bb = (int)__umul24((uint32_t)((int)__umul24((uint32_t)((vb[2] >> 3) - blo[2]), (uint32_t)bdy) +
-                                                        ((vb[1] >> 3) - blo[1])),
-                                             (uint32_t)bdx) +
-                               ((vb[0] >> 3) - blo[0]);
-                tl.list[base + (int)__popcll(mask & below)] =
-                    e | (brick_local(vb[0], vb[1], vb[2]) << 11) | (bb << 20);
+                const int pos = atomicAdd(&tl.nlist, 1);
+                const uint32_t ent = ent0 + (uint32_t)k + ((uint32_t)local_part<DAX>(vd) << 11) +
+                                     ((uint32_t)__umul24((uint32_t)vd >> 3, (uint32_t)bstride[DAX]) << 20);
+                tl.list[pos] = (int)ent;
             }
         }
     }
@@ -499,15 +510,21 @@ __device__ __forceinline__ void classify_voxels(const SliceRec& rec, const TileR
 
 // Pairs of every surviving bin for U listed voxels of a thread: the slot rows of NB bins are
 // read from LDS 4 at a time, then the NB x U pair loads are issued before any is used.  A pair
-// that is not loaded (no slot, or no voxel) stays zero and adds nothing.
-template <int DT, int U, int NB>
-__device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& tl, int kactp, const bool (&ok)[U],
-                                       const int (&row)[U], const int (&loc)[U], float (&A)[U], float (&B)[U]) {
+// that is not loaded (no slot: -1, or anything outside the pool) stays zero and adds nothing.  A thread past the end of the list
+// reads the last entry's row (its result is not stored).  NARROW: the pool spans less than 4 GiB,
+// so a pair's byte offset from the pool's base fits 32 bits.
+template <int DT, int U, int NB, bool NARROW>
+__device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& tl, const int (&row)[U],
+                                       const int (&loc)[U], float (&A)[U], float (&B)[U]) {
     using PT = Pair<DT>;
     using T = typename PT::T;
-    static_assert(NB % 4 == 0, "slot rows are read 4 entries at a time");
+    static_assert(NB % 4 == 0 && 8 % NB == 0, "slot rows (kactp entries, a multiple of 8) are read 4 at a time");
+    constexpr int LG = sizeof(T) == 8 ? 3 : (sizeof(T) == 4 ? 2 : 1);
+    static_assert(sizeof(T) == (1u << LG), "pair size");
     const gptr<const T> data = global((const T*)rec.vol.data);
+    const gptr<const char> bytes = global((const char*)rec.vol.data);
     const int kact = ui(rec.kact);
+    const uint32_t cap = (uint32_t)ui((int)rec.vol.cap);
 #pragma unroll
     for (int u = 0; u < U; ++u) A[u] = B[u] = 0.0f;
     for (int k0 = 0; k0 < kact; k0 += NB) {
@@ -516,9 +533,7 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int g = 0; g < NB; g += 4) {
-                // rows hold kactp entries (a multiple of 8, -1 past the survivors)
-                int4 s4 = make_int4(-1, -1, -1, -1);
-                if (ok[u] && k0 + g < kactp) s4 = *reinterpret_cast<const int4*>(&tl.slot[row[u] + k0 + g]);
+                const int4 s4 = *reinterpret_cast<const int4*>(&tl.slot[row[u] + k0 + g]);
                 sl[u][g] = s4.x;
                 sl[u][g + 1] = s4.y;
                 sl[u][g + 2] = s4.z;
@@ -530,7 +545,12 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
 #pragma unroll
             for (int g = 0; g < NB; ++g) {
                 pr[u][g] = T{};
-                if (sl[u][g] >= 0) pr[u][g] = *(const T*)&data[((uint32_t)sl[u][g] << 9) | (uint32_t)loc[u]];
+                if ((uint32_t)sl[u][g] < cap) {   // a slot of the pool (-1: none)
+                    if constexpr (NARROW)
+                        pr[u][g] = *(const T*)&bytes[((uint32_t)sl[u][g] << (9 + LG)) | (uint32_t)loc[u]];
+                    else
+                        pr[u][g] = *(const T*)&data[(((size_t)sl[u][g] << 9) | (uint32_t)loc[u]) ];
+                }
             }
 #pragma unroll
         for (int g = 0; g < NB; ++g) {
@@ -549,11 +569,13 @@ __device__ __forceinline__ void gather(const SliceRec& rec, const TileLds<DT>& t
     }
 }
 
-// Voxels phase, second part: every listed voxel's surviving bins gathered and blended into
-// (V_v, 1), or (0, 0) when none holds a sample.
-template <int DT, int NT, int U, int NB>
-__device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
-    const int nlist = ui(tl.nlist), kactp = ui(tr.kactp);
+// Voxels phase, second part: every listed voxel's surviving bins gathered and blended into V_v,
+// NaN when none holds a sample.
+template <int DT, int NT, int U, int NB, bool NARROW>
+__device__ __forceinline__ void gather_list(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl, int nlist) {
+    using T = typename Pair<DT>::T;
+    constexpr int LG = sizeof(T) == 8 ? 3 : (sizeof(T) == 4 ? 2 : 1);
+    const int kactp = ui(tr.kactp);
     for (int base = 0; base < nlist; base += U * NT) {
         bool ok[U];
         int row[U], loc[U], ent[U];
@@ -561,12 +583,13 @@ __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec
         for (int u = 0; u < U; ++u) {
             const int i = base + u * NT + (int)threadIdx.x;
             ok[u] = i < nlist;
-            ent[u] = ok[u] ? tl.list[i] : 0;
+            ent[u] = tl.list[min(i, nlist - 1)];
             row[u] = (int)__umul24((uint32_t)ent[u] >> 20, (uint32_t)kactp);
-            loc[u] = (ent[u] >> 11) & 511;
+            // the pair's index in its brick, or its byte offset there where offsets are 32-bit
+            loc[u] = ((ent[u] >> 11) & 511) << (NARROW ? LG : 0);
         }
         float A[U], B[U];
-        gather<DT, U, NB>(rec, tl, kactp, ok, row, loc, A, B);
+        gather<DT, U, NB, NARROW>(rec, tl, row, loc, A, B);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
@@ -576,8 +599,22 @@ __device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec
     }
 }
 
-// Pixels phase of a staged tile: FP64 position, the cell's 8 (V, valid) values from LDS (two
-// adjacent run entries per cell column), tent weights.
+template <int DT, int NT, int U, int NB>
+__device__ __forceinline__ void gather_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
+    using T = typename Pair<DT>::T;
+    const int nlist = ui(tl.nlist);
+    if (nlist == 0) return;
+    const uint64_t pool_bytes = (uint64_t)(uint32_t)ui((int)rec.vol.cap) * kBrickVox * sizeof(T);
+    if (pool_bytes <= 0xFFFFFFFFull)
+        gather_list<DT, NT, U, NB, true>(rec, tr, tl, nlist);
+    else
+        gather_list<DT, NT, U, NB, false>(rec, tr, tl, nlist);
+}
+
+// Pixels phase of a staged tile: FP64 position, the cell's 8 values from LDS (two adjacent run
+// entries per cell column), then the tent blend.  With all 8 corners valid the weights sum to 1
+// and the blend is the trilinear interpolation, taken as nested lerps; a NaN corner makes that
+// NaN, and the pixel takes sum w V / sum w over its valid corners instead.
 template <int DT, int DAX, int NT>
 __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec& tr, const TileLds<DT>& tl) {
     constexpr int PAX = DAX == 0 ? 1 : 0, QAX = DAX == 2 ? 1 : 2;
@@ -586,7 +623,6 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
     const int lo_p = ui(tr.lo[PAX]), lo_q = ui(tr.lo[QAX]), lo_d = ui(tr.lo[DAX]);
     const int bp = ui(tr.bp), bq = ui(tr.bq), depth = ui(tr.depth);
     const int n[3] = {ui(rec.vol.n[0]), ui(rec.vol.n[1]), ui(rec.vol.n[2])};
-    const gptr<float> outp = global(rec.out);
     double c00[3], ex[3], ey[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -594,28 +630,25 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         ex[a] = ud(rec.ex[a]);
         ey[a] = ud(rec.ey[a]);
     }
-    const int shift = T == kTileBig ? 5 : 4;
+    const int shift = T == kTileBig ? 5 : 4, rstep = NT >> shift;
     // a thread keeps its column (NT is a multiple of the tile edge): the column's part of the
-    // position is computed once
+    // position is computed once, and its output pointer steps by whole rows
     static_assert(NT % kTileBig == 0, "threads of a workgroup cover whole tile rows");
     const int li = (int)threadIdx.x & (T - 1), i = i0 + li;
+    if (li >= ni) return;
     double ci[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) ci[a] = fma((double)i, ex[a], c00[a]);
-    for (int idx = (int)threadIdx.x; idx < T * T; idx += NT) {
-        const int lj = idx >> shift;
-        if (li >= ni || lj >= nj) continue;
-        const int j = j0 + lj;
-        const gptr<float> out = outp + (size_t)j * W + i;
-        const double dj = (double)j;
+    // run entries of the cell's four columns relative to column (cp, cq)
+    const int dcol[4] = {0, depth, bp * depth, (bp + 1) * depth};
+    int lj = (int)threadIdx.x >> shift;
+    gptr<float> out = global(rec.out) + ((size_t)(j0 + lj) * W + i);
+    const size_t ostep = (size_t)rstep * W;
+    for (; lj < nj; lj += rstep, out += ostep) {
+        const double dj = (double)(j0 + lj);
         double c[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) c[a] = fma(dj, ey[a], ci[a]);
-        if (!(c[0] >= -1.0 && c[0] < (double)n[0] && c[1] >= -1.0 && c[1] < (double)n[1] && c[2] >= -1.0 &&
-              c[2] < (double)n[2])) {
-            *out = __builtin_nanf("");
-            continue;
-        }
         int b[3];
         float fr[3];
 #pragma unroll
@@ -624,51 +657,49 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
             b[a] = (int)f;
             fr[a] = (float)(c[a] - f);
         }
+        // inside [-1, n) on every axis: the cell floor in [-1, n - 1]
+        if (!((uint32_t)b[0] + 1u < (uint32_t)n[0] + 1u && (uint32_t)b[1] + 1u < (uint32_t)n[1] + 1u &&
+              (uint32_t)b[2] + 1u < (uint32_t)n[2] + 1u)) {
+            *out = __builtin_nanf("");
+            continue;
+        }
         // the cell's columns lie in the box and its two layers in each column's run; the clamps
         // only keep the LDS reads in bounds
         const int cp = min(max(b[PAX] - lo_p, 0), bp - 2), cq = min(max(b[QAX] - lo_q, 0), bq - 2);
         const int col0 = (int)__umul24((uint32_t)cq, (uint32_t)bp) + cp;
+        const int e0 = (int)__umul24((uint32_t)col0, (uint32_t)depth), kd = b[DAX] - lo_d;
         const int cols[4] = {col0, col0 + 1, col0 + bp, col0 + bp + 1};
         float lov[4], hiv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = min(max(b[DAX] - lo_d - (int)tl.rs[cols[q]], 0), depth - 2);
-            const int e = (int)__umul24((uint32_t)cols[q], (uint32_t)depth) + k;
+            const int k = min(max(kd - (int)tl.rs[cols[q]], 0), depth - 2);
+            const int e = e0 + dcol[q] + k;
             lov[q] = tl.V[e];
             hiv[q] = tl.V[e + 1];
         }
-        const float wp[2] = {1.0f - fr[PAX], fr[PAX]}, wq[2] = {1.0f - fr[QAX], fr[QAX]};
-        const float wd[2] = {1.0f - fr[DAX], fr[DAX]};
-        // all 8 corners valid: plain sums (a NaN corner makes num NaN); otherwise the sums over
-        // the valid corners, as w * 0 and w * 1 terms, which give the same bits where all are valid
-        float t[8];
+        float lq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float wpq = wp[q & 1] * wq[q >> 1];
-            t[2 * q] = wpq * wd[0];
-            t[2 * q + 1] = wpq * wd[1];
-        }
-        float num = 0.0f, den = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            num = __builtin_fmaf(t[2 * q], lov[q], num);
-            den = den + t[2 * q];
-            num = __builtin_fmaf(t[2 * q + 1], hiv[q], num);
-            den = den + t[2 * q + 1];
-        }
-        if (__builtin_isnan(num)) {
-            num = 0.0f;
-            den = 0.0f;
+        for (int q = 0; q < 4; ++q) lq[q] = __builtin_fmaf(fr[DAX], hiv[q] - lov[q], lov[q]);
+        const float l0 = __builtin_fmaf(fr[PAX], lq[1] - lq[0], lq[0]);
+        const float l1 = __builtin_fmaf(fr[PAX], lq[3] - lq[2], lq[2]);
+        float val = __builtin_fmaf(fr[QAX], l1 - l0, l0);
+        if (__builtin_isnan(val)) {
+            const float wp[2] = {1.0f - fr[PAX], fr[PAX]}, wq[2] = {1.0f - fr[QAX], fr[QAX]};
+            const float wd[2] = {1.0f - fr[DAX], fr[DAX]};
+            float num = 0.0f, den = 0.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                const float wpq = wp[q & 1] * wq[q >> 1];
+                const float t0 = wpq * wd[0], t1 = wpq * wd[1];
                 const bool v0 = !__builtin_isnan(lov[q]), v1 = !__builtin_isnan(hiv[q]);
-                num = __builtin_fmaf(t[2 * q], v0 ? lov[q] : 0.0f, num);
-                den = __builtin_fmaf(t[2 * q], v0 ? 1.0f : 0.0f, den);
-                num = __builtin_fmaf(t[2 * q + 1], v1 ? hiv[q] : 0.0f, num);
-                den = __builtin_fmaf(t[2 * q + 1], v1 ? 1.0f : 0.0f, den);
+                num = __builtin_fmaf(t0, v0 ? lov[q] : 0.0f, num);
+                den = __builtin_fmaf(t0, v0 ? 1.0f : 0.0f, den);
+                num = __builtin_fmaf(t1, v1 ? hiv[q] : 0.0f, num);
+                den = __builtin_fmaf(t1, v1 ? 1.0f : 0.0f, den);
             }
+            val = den > 0.0f ? num * __builtin_amdgcn_rcpf(den) : __builtin_nanf("");
         }
-        *out = den > 0.0f ? num * __builtin_amdgcn_rcpf(den) : __builtin_nanf("");
+        *out = val;
     }
 }
 
@@ -715,6 +746,11 @@ __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr,
     }
     int sl[slots_per_thread<NT>()];
     load_slots<NT>(rec, tr, sl);
+    {   // every run entry starts NaN; the gather overwrites the listed voxels'
+        const int nitems = (int)__umul24((uint32_t)ui(tr.ncols), (uint32_t)ui(tr.depth));
+        const float4 nan4 = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+        for (int i = 4 * (int)threadIdx.x; i < nitems; i += 4 * NT) *reinterpret_cast<float4*>(&tl.V[i]) = nan4;
+    }
     if (threadIdx.x == 0) tl.nlist = 0;
     __syncthreads();
     const int dax = ui(rec.dax);
@@ -803,12 +839,19 @@ __global__ void __launch_bounds__(kSetupThreads) k_tiles_setup(const BatchReq* _
     }
 }
 
+// Waves per SIMD that the LDS of a batch tile workgroup allows (the register budget is held to it).
+template <int DT>
+constexpr int tiles_waves_per_eu() {
+    return (160 * 1024 / (int)sizeof(TileLds<DT>)) * (kThreadsBatch / 64) / 4;
+}
+
 // Batch tiles: a persistent grid over the staged tiles.  XCD x (workgroups are dealt to the 8
 // XCDs round-robin) takes the x-th eighth of the list, in order, so that neighbouring tiles of a
 // request, which share the voxels along their edges, are read through one L2.  Both records are
 // read through scalar loads.
 template <int DT>
-__global__ void __launch_bounds__(kThreadsBatch) k_tiles(const SliceRec* __restrict__ recs,
+__global__ void __launch_bounds__(kThreadsBatch) __attribute__((amdgpu_waves_per_eu(tiles_waves_per_eu<DT>())))
+k_tiles(const SliceRec* __restrict__ recs,
                                                          const TileRec* __restrict__ tiles,
                                                          const int* __restrict__ counts) {
     __shared__ TileLds<DT> tl;
