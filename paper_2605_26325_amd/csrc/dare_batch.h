@@ -2,6 +2,8 @@
 // kernels and the host planners (the C ABI's batch call and the server).
 #pragma once
 
+#include <cstddef>
+
 #include "dare_internal.h"
 
 namespace dare {
@@ -12,12 +14,19 @@ struct BatchReq {
     SliceArgs s;
 };
 
-// Batch header at the start of a workspace: int32 {units, requests, units at the list's back,
-// 0}.  At radius 1 the units are appended on the device, so counts[0] and counts[2] must be
-// uploaded as 0; at other radii the host uploads the unit list and its length in counts[0].
+// Batch header at the start of a workspace: int32 counts {units, requests, units at the list's
+// back, 0}, then the radius-1 tile kernel's claim counter of each of the 8 XCDs, each on a
+// 256-byte line of its own (claims[x][0]: counters that share a line serialise each other's
+// atomics).  At radius 1 the units are appended on the device, so counts[0] and counts[2] must be
+// uploaded as 0, and so must the claims; at other radii the host uploads the unit list and its
+// length in counts[0].  The kernels address the header as int32 words from counts.
+constexpr int kClaimStride = 64;          // int32 words between two XCDs' claim counters
 struct BatchHeader {
     int32_t counts[4];
+    int32_t pad[kClaimStride - 4];
+    int32_t claims[8][kClaimStride];
 };
+static_assert(offsetof(BatchHeader, claims) == kClaimStride * sizeof(int32_t), "claims follow one line of counts");
 
 constexpr int kBatchMaxReq = 4096;        // requests per launch group (grid of the setup pass)
 
@@ -55,7 +64,7 @@ struct TileRec {
 hipError_t launch_reslice_tile(const VolDev* vd, int dtype, const SliceArgs& s, hipStream_t stream);
 // Radius 1, a batch: setup pass (one workgroup per request: the request record, then one tile
 // record per thread) + persistent tile kernel + the per-pixel kernel for requests too coarse to stage.
-// `counts[0]` and `counts[2]` must hold 0 and `counts[1]` the number of requests when the stream
+// `counts[0]`, `counts[2]` and the claims must hold 0 and `counts[1]` the number of requests when the stream
 // reaches the launch; `units` and `tiles` hold `cap` entries, at least tile_units_max() per
 // request in all.
 hipError_t launch_tiles_batch(int dtype, const BatchReq* reqs, SliceRec* recs, int2* units, TileRec* tiles,

@@ -845,23 +845,38 @@ constexpr int tiles_waves_per_eu() {
     return (160 * 1024 / (int)sizeof(TileLds<DT>)) * (kThreadsBatch / 64) / 4;
 }
 
-// Batch tiles: a persistent grid over the staged tiles.  XCD x (workgroups are dealt to the 8
-// XCDs round-robin) takes the x-th eighth of the list, in order, so that neighbouring tiles of a
-// request, which share the voxels along their edges, are read through one L2.  Both records are
+// The k-th tile of XCD x: the XCDs take blocks of kTileBlock consecutive tiles of the list in
+// turn.  Neighbouring tiles of a request, which share the voxels along their edges, mostly fall
+// in one block and so are read through one L2, while the blocks spread each request's cost (its
+// surviving bins, how much of it leaves the grid) over all XCDs.
+constexpr int kTileBlock = 32;
+__device__ __forceinline__ int xcd_tile(int x, int k) {
+    return ((k / kTileBlock) * 8 + x) * kTileBlock + (k % kTileBlock);
+}
+
+// Batch tiles: a persistent grid over the staged tiles.  Workgroups are dealt to the 8 XCDs
+// round-robin; XCD x's workgroups claim its tiles one at a time from its counter in the batch
+// header, so that a workgroup that drew cheap tiles (few surviving bins, pixels outside the grid)
+// takes more.  A workgroup's first claim is implicit (k = its rank in the XCD); the others come
+// from the counter, offset by the number of workgroups per XCD, and each is issued at the start
+// of the tile before it, so that its latency overlaps that tile's table reads.  Claims grow with
+// k and so do their tiles: a workgroup stops at its first claim past the list.  Both records are
 // read through scalar loads.
 template <int DT>
 __global__ void __launch_bounds__(kThreadsBatch) __attribute__((amdgpu_waves_per_eu(tiles_waves_per_eu<DT>())))
-k_tiles(const SliceRec* __restrict__ recs,
-                                                         const TileRec* __restrict__ tiles,
-                                                         const int* __restrict__ counts) {
+k_tiles(const SliceRec* __restrict__ recs, const TileRec* __restrict__ tiles, int* __restrict__ counts) {
     __shared__ TileLds<DT> tl;
+    __shared__ int take;
     const int n = counts[0];
-    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
-    const int beg = (int)((int64_t)n * xcd >> 3), end = (int)((int64_t)n * (xcd + 1) >> 3);
-    for (int u = beg + (int)(blockIdx.x >> 3); u < end; u += per) {
+    const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+    int* claims = counts + kClaimStride * (1 + x);
+    for (int u = xcd_tile(x, (int)(blockIdx.x >> 3)); u < n; u = ui(take)) {
+        int k = 0;
+        if (threadIdx.x == 0) k = per + atomicAdd(claims, 1);
         const TileRec& tr = tiles[u];
         const SliceRec& rec = recs[ui(tr.r)];
         run_tile<DT, kThreadsBatch, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl);
+        if (threadIdx.x == 0) take = xcd_tile(x, k);
         __syncthreads();
     }
 }
