@@ -736,8 +736,42 @@ __device__ __forceinline__ void nan_tile(const SliceRec& rec, const TileRec& tr)
     }
 }
 
-// One staged tile; `rec` and `tr` are the request's and the tile's records (LDS or global).
-// U listed voxels per thread and NB bins per round in the gather.
+// The voxels phase of a staged tile whose slot-table entries `sl` are loaded (or in flight);
+// `rec` and `tr` are the request's and the tile's records (LDS or global).  U listed voxels per
+// thread and NB bins per round in the gather.  `last` runs before the barrier that ends the phase.
+template <int DT, int NT, int U, int NB, class Last>
+__device__ __forceinline__ void stage_voxels(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl,
+                                             const int (&sl)[slots_per_thread<NT>()], Last&& last) {
+    {   // every run entry starts NaN; the gather overwrites the listed voxels'
+        const int nitems = (int)__umul24((uint32_t)ui(tr.ncols), (uint32_t)ui(tr.depth));
+        const float4 nan4 = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+        for (int i = 4 * (int)threadIdx.x; i < nitems; i += 4 * NT) *reinterpret_cast<float4*>(&tl.V[i]) = nan4;
+    }
+    if (threadIdx.x == 0) tl.nlist = 0;
+    __syncthreads();
+    switch (ui(rec.dax)) {
+        case 0: classify_voxels<DT, 0, NT>(rec, tr, tl); break;
+        case 1: classify_voxels<DT, 1, NT>(rec, tr, tl); break;
+        default: classify_voxels<DT, 2, NT>(rec, tr, tl); break;
+    }
+    store_slots<DT, NT>(rec, tr, tl, sl);
+    __syncthreads();
+    gather_voxels<DT, NT, U, NB>(rec, tr, tl);
+    last();
+    __syncthreads();
+}
+
+// The pixels phase of a staged tile whose voxels phase is done.
+template <int DT, int NT>
+__device__ __forceinline__ void stage_tile_pixels(const SliceRec& rec, const TileRec& tr, const TileLds<DT>& tl) {
+    switch (ui(rec.dax)) {
+        case 0: stage_pixels<DT, 0, NT>(rec, tr, tl); break;
+        case 1: stage_pixels<DT, 1, NT>(rec, tr, tl); break;
+        default: stage_pixels<DT, 2, NT>(rec, tr, tl); break;
+    }
+}
+
+// One tile, start to end.
 template <int DT, int NT, int U, int NB>
 __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr, TileLds<DT>& tl) {
     if (ui(tr.mode) != 1) {
@@ -746,28 +780,8 @@ __device__ __forceinline__ void run_tile(const SliceRec& rec, const TileRec& tr,
     }
     int sl[slots_per_thread<NT>()];
     load_slots<NT>(rec, tr, sl);
-    {   // every run entry starts NaN; the gather overwrites the listed voxels'
-        const int nitems = (int)__umul24((uint32_t)ui(tr.ncols), (uint32_t)ui(tr.depth));
-        const float4 nan4 = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
-        for (int i = 4 * (int)threadIdx.x; i < nitems; i += 4 * NT) *reinterpret_cast<float4*>(&tl.V[i]) = nan4;
-    }
-    if (threadIdx.x == 0) tl.nlist = 0;
-    __syncthreads();
-    const int dax = ui(rec.dax);
-    switch (dax) {
-        case 0: classify_voxels<DT, 0, NT>(rec, tr, tl); break;
-        case 1: classify_voxels<DT, 1, NT>(rec, tr, tl); break;
-        default: classify_voxels<DT, 2, NT>(rec, tr, tl); break;
-    }
-    store_slots<DT, NT>(rec, tr, tl, sl);
-    __syncthreads();
-    gather_voxels<DT, NT, U, NB>(rec, tr, tl);
-    __syncthreads();
-    switch (dax) {
-        case 0: stage_pixels<DT, 0, NT>(rec, tr, tl); break;
-        case 1: stage_pixels<DT, 1, NT>(rec, tr, tl); break;
-        default: stage_pixels<DT, 2, NT>(rec, tr, tl); break;
-    }
+    stage_voxels<DT, NT, U, NB>(rec, tr, tl, sl, [] {});
+    stage_tile_pixels<DT, NT>(rec, tr, tl);
 }
 
 // Single reslice: one workgroup per 16 x 16 tile; wave 0 evaluates the request setup, then lane
@@ -859,25 +873,44 @@ __device__ __forceinline__ int xcd_tile(int x, int k) {
 // header, so that a workgroup that drew cheap tiles (few surviving bins, pixels outside the grid)
 // takes more.  A workgroup's first claim is implicit (k = its rank in the XCD); the others come
 // from the counter, offset by the number of workgroups per XCD, and each is issued at the start
-// of the tile before it, so that its latency overlaps that tile's table reads.  Claims grow with
+// of the tile before it, so that its latency overlaps that tile's voxels phase.  Claims grow with
 // k and so do their tiles: a workgroup stops at its first claim past the list.  Both records are
 // read through scalar loads.
 template <int DT>
 __global__ void __launch_bounds__(kThreadsBatch) __attribute__((amdgpu_waves_per_eu(tiles_waves_per_eu<DT>())))
 k_tiles(const SliceRec* __restrict__ recs, const TileRec* __restrict__ tiles, int* __restrict__ counts) {
+    constexpr int NT = kThreadsBatch;
     __shared__ TileLds<DT> tl;
     __shared__ int take;
     const int n = counts[0];
     const int x = blockIdx.x & 7, per = gridDim.x >> 3;
     int* claims = counts + kClaimStride * (1 + x);
-    for (int u = xcd_tile(x, (int)(blockIdx.x >> 3)); u < n; u = ui(take)) {
+    // the slot-table entries of the next staged tile are read before the pixels phase of the
+    // current one, so that their latency overlaps it
+    int sl[slots_per_thread<NT>()];
+    int u = xcd_tile(x, (int)(blockIdx.x >> 3));
+    if (u < n && ui(tiles[u].mode) == 1) load_slots<NT>(recs[ui(tiles[u].r)], tiles[u], sl);
+    while (u < n) {
         int k = 0;
         if (threadIdx.x == 0) k = per + atomicAdd(claims, 1);
         const TileRec& tr = tiles[u];
         const SliceRec& rec = recs[ui(tr.r)];
-        run_tile<DT, kThreadsBatch, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl);
-        if (threadIdx.x == 0) take = xcd_tile(x, k);
+        const bool staged = ui(tr.mode) == 1;
+        auto next = [&] {
+            if (threadIdx.x == 0) take = xcd_tile(x, k);
+        };
+        if (staged) {
+            stage_voxels<DT, NT, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl, sl, next);
+        } else {
+            next();
+            __syncthreads();
+        }
+        const int un = ui(take);
+        if (un < n && ui(tiles[un].mode) == 1) load_slots<NT>(recs[ui(tiles[un].r)], tiles[un], sl);
+        if (staged) stage_tile_pixels<DT, NT>(rec, tr, tl);
+        else nan_tile<NT>(rec, tr);
         __syncthreads();
+        u = un;
     }
 }
 
