@@ -233,6 +233,16 @@ __device__ __forceinline__ VolView view_of(const VolDev* __restrict__ vd) {
     return v;
 }
 
+// Tent weight 1 - |o - f| / R of the voxel at integer offset o (-R < o <= R) from the cell floor
+// along one axis, for a sample at fraction f of its cell, with g = 1 - f.  Both come from the
+// FP64 position (f = c - floor(c), g = floor(c) + 1 - c), and the low side (o <= 0) is written
+// through g: as f nears 1 it rounds to 1 in FP32 while g stays positive, so a voxel whose FP64
+// weight is positive keeps a positive weight (and a pixel whose only valid voxels lie there stays
+// assigned, as in FP64).
+__device__ __forceinline__ float tent_weight(int o, float f, float g, int R, float invR) {
+    return o <= 0 ? fmaxf(0.0f, ((float)(R - 1 + o) + g) * invR) : fmaxf(0.0f, ((float)(R - o) + f) * invR);
+}
+
 // Per-pixel gather of the 8 cell voxels over the surviving bins (no staging).  The whole
 // workgroup works on one request: bin ids and weights are broadcast as scalars.  All loads of
 // NB bins are issued before any is used (indices of absent voxels point at entry 0, which
@@ -244,7 +254,9 @@ __device__ __forceinline__ float pixel_direct(const VolView& vv, const SetupLds&
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
     const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
     const float fx = (float)(c[0] - f0), fy = (float)(c[1] - f1), fz = (float)(c[2] - f2);
-    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+    // the low voxel's weight from FP64 (tent_weight at R = 1)
+    const float gx = (float)(f0 + 1.0 - c[0]), gy = (float)(f1 + 1.0 - c[1]), gz = (float)(f2 + 1.0 - c[2]);
+    const float wx[2] = {gx, fx}, wy[2] = {gy, fy}, wz[2] = {gz, fz};
     const int nbx = vv.nbx, nby = vv.nby;
     int tix[8], lix[8];
     bool in[8];
@@ -348,6 +360,7 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
         const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
         const int x0 = (int)f0, y0 = (int)f1, z0 = (int)f2;
         const float fr[3] = {(float)(c[0] - f0), (float)(c[1] - f1), (float)(c[2] - f2)};
+        const float gr[3] = {(float)(f0 + 1.0 - c[0]), (float)(f1 + 1.0 - c[1]), (float)(f2 + 1.0 - c[2])};
         const int span = 2 * R;
         const int nbx = vd->nbx, nby = vd->nby;
         const typename PT::T* __restrict__ data = (const typename PT::T*)vd->data;
@@ -356,15 +369,15 @@ __device__ __forceinline__ void reslice_unit_rn(const VolDev* __restrict__ vd, c
             const int oz = r / span - R + 1, oy = r % span - R + 1;
             const int vz = z0 + oz, vy = y0 + oy;
             if ((unsigned)vz >= (unsigned)nz || (unsigned)vy >= (unsigned)ny) continue;
-            const float tz = fmaxf(0.0f, 1.0f - fabsf((float)oz - fr[2]) * invR);
-            const float ty = fmaxf(0.0f, 1.0f - fabsf((float)oy - fr[1]) * invR);
+            const float tz = tent_weight(oz, fr[2], gr[2], R, invR);
+            const float ty = tent_weight(oy, fr[1], gr[1], R, invR);
             const float tyz = ty * tz;
             if (!(tyz > 0.0f)) continue;
             const int rb = ((vz >> 3) * nby + (vy >> 3)) * nbx;
             for (int ox = -R + 1; ox <= R; ++ox) {
                 const int vx = x0 + ox;
                 if ((unsigned)vx >= (unsigned)nx) continue;
-                const float tx = fmaxf(0.0f, 1.0f - fabsf((float)ox - fr[0]) * invR);
+                const float tx = tent_weight(ox, fr[0], gr[0], R, invR);
                 const float t = tx * tyz;
                 if (!(t > 0.0f)) continue;
                 float A = 0.0f, B = 0.0f;

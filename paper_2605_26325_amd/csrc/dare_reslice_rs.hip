@@ -286,13 +286,14 @@ __device__ __forceinline__ void reslice_tile_rs(const VolDev* __restrict__ vd, c
     const double f0 = floor(c[0]), f1 = floor(c[1]), f2 = floor(c[2]);
     const int b0[3] = {(int)f0, (int)f1, (int)f2};
     const float fr[3] = {(float)(c[0] - f0), (float)(c[1] - f1), (float)(c[2] - f2)};
+    const float gr[3] = {(float)(f0 + 1.0 - c[0]), (float)(f1 + 1.0 - c[1]), (float)(f2 + 1.0 - c[2])};
     const float invR = 1.0f / (float)R;
     // tent weights per axis for offsets -R+1 .. R
     float tw[3][2 * R];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int o = 0; o < 2 * R; ++o) tw[a][o] = fmaxf(0.0f, 1.0f - fabsf((float)(o - R + 1) - fr[a]) * invR);
+        for (int o = 0; o < 2 * R; ++o) tw[a][o] = tent_weight(o - R + 1, fr[a], gr[a], R, invR);
     float num = 0.0f, den = 0.0f;
     if (mode == 2) {
         for (int oz = 0; oz < 2 * R; ++oz)

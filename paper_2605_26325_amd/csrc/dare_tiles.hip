@@ -684,8 +684,12 @@ __device__ __forceinline__ void stage_pixels(const SliceRec& rec, const TileRec&
         const float l1 = __builtin_fmaf(fr[PAX], lq[3] - lq[2], lq[2]);
         float val = __builtin_fmaf(fr[QAX], l1 - l0, l0);
         if (__builtin_isnan(val)) {
-            const float wp[2] = {1.0f - fr[PAX], fr[PAX]}, wq[2] = {1.0f - fr[QAX], fr[QAX]};
-            const float wd[2] = {1.0f - fr[DAX], fr[DAX]};
+            // the low voxel's weight from FP64 (tent_weight at R = 1)
+            float gr[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gr[a] = (float)((double)b[a] + 1.0 - c[a]);
+            const float wp[2] = {gr[PAX], fr[PAX]}, wq[2] = {gr[QAX], fr[QAX]};
+            const float wd[2] = {gr[DAX], fr[DAX]};
             float num = 0.0f, den = 0.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {

@@ -241,6 +241,56 @@ def test_reslice_brute_force_tiny_grids(dare, torch_cuda, seed):
     assert np.isnan(vol.reslice(P, 20, 20, (0.3, 0.3)).cpu().numpy()).all()
 
 
+def test_tent_weight_of_the_last_layer(dare, torch_cuda):
+    """Pixels a hair below the grid's upper x face (c_x = n_x - 1e-9): the upper cell layer lies
+    outside the grid, and the lower one's tent weight (about 1e-9) is positive in FP64 but its
+    complement 1 - f rounds to 0 in FP32.  The oracle assigns these pixels from the lower layer
+    (Fig. 2 caption: the weighting by distance; Sec. 2.1: a pixel is unassigned only when no
+    voxel in reach holds a sample), and so must every kernel: staged tiles, the per-pixel gather
+    (coarse pitch), radius 2, single and batched."""
+    torch = torch_cuda
+    note("tent weight of a pixel at the grid's upper face")
+    rng = np.random.default_rng(77)
+    dims = (19, 13, 11)
+    K = 4
+    S, C = random_grid(rng, K, dims, p_empty=0.2)
+    origin = np.array([-850.0, 310.0, -1620.0])
+    h = 0.5
+    n0, x0 = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0])
+    rn, rx = [], []
+    for b in range(K):            # bins within 15 deg of the plane's normal: some pass the gates
+        R = rodrigues(random_unit(rng), math.radians(rng.uniform(0, 15)))
+        rn.append(R @ n0)
+        rx.append(R @ x0)
+    rn, rx = np.array(rn), np.array(rx)
+    calib = synth.make_calibration(16, 0.5)
+    a, c = quant.storage(S, C, "fp32")
+    cases = []
+    for W, H, sx, i_face in ((40, 24, 0.25, 37), (5, 4, 4.0, 2)):
+        # pixel column i_face at c_x = n_x - 1e-9; rows across y, a plane of constant z
+        T = np.eye(4)
+        T[:3, 0], T[:3, 1], T[:3, 2] = x0, np.cross(n0, x0), n0
+        c00 = (dims[0] - 1e-9) - i_face * sx / h
+        T[:3, 3] = origin + h * np.array([c00, 0.37, 4.3])
+        cases.append((T @ np.linalg.inv(calib), W, H, (sx, 0.25)))
+    for R in (1, 2):
+        prm = Params(radius_vox=R)
+        vol = make_volume(origin, h, dims, calib, prm)
+        upload_grid(vol, S, C, rn, rx)
+        specs = [dare.make_spec(P, W, H, pitch) for P, W, H, pitch in cases]
+        outs = [torch.full((H, W), -7.0, device="cuda") for _, W, H, _ in cases]
+        ws = torch.empty(dare.dare_reslice_batch_workspace_bytes([vol] * len(specs), specs), dtype=torch.uint8,
+                         device="cuda")
+        dare.dare_reslice_batch([vol] * len(specs), specs, outs, ws)
+        for (P, W, H, pitch), ob in zip(cases, outs):
+            ref = reslice.reslice(a, c, origin, h, rn, rx, calib, P, W, H, pitch, prm)
+            i_face = 37 if W == 40 else 2
+            assert np.count_nonzero(~np.isnan(ref[:, i_face])) >= H // 2, "the case must reach the face"
+            out = vol.reslice(P, W, H, pitch).cpu().numpy()
+            assert_parity(out, ref, what=f"R={R} {W}x{H} alone")
+            assert_parity(ob.cpu().numpy(), ref, what=f"R={R} {W}x{H} batched")
+
+
 @pytest.mark.parametrize("R", [2, 3, 4, 5, 8])
 def test_reslice_larger_radius(dare, torch_cuda, R):
     torch = torch_cuda
