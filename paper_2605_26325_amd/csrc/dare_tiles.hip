@@ -54,6 +54,14 @@ template <int DT>
 constexpr int items_per_round() { return 2; }
 template <int DT>
 constexpr int bins_per_round() { return DT == DARE_FP8_E4M3 ? 4 : 8; }
+// The same for the persistent batch kernel, whose register budget is held to 7 workgroups per CU:
+// 2-byte halves (BF16, FP16) take 4 voxels of 4 bins (16 pairs, one register each, a quarter
+// fewer gather rounds than 2 x 8); FP32 pairs (two registers) and FP8 (the scales besides) stay
+// at 2 voxels, as 4 would spill.
+template <int DT>
+constexpr int batch_items_per_round() { return DT == DARE_BF16 || DT == DARE_F16 ? 4 : 2; }
+template <int DT>
+constexpr int batch_bins_per_round() { return DT == DARE_F32 ? 8 : 4; }
 
 // LDS of a workgroup working on one staged tile.
 template <int DT>
@@ -904,7 +912,7 @@ k_tiles(const SliceRec* __restrict__ recs, const TileRec* __restrict__ tiles, in
             if (threadIdx.x == 0) take = xcd_tile(x, k);
         };
         if (staged) {
-            stage_voxels<DT, NT, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl, sl, next);
+            stage_voxels<DT, NT, batch_items_per_round<DT>(), batch_bins_per_round<DT>()>(rec, tr, tl, sl, next);
         } else {
             next();
             __syncthreads();
