@@ -819,13 +819,15 @@ def recv_arrays(fh):
 
 
 def _err_partial(got, ref):
-    """(max |got - ref|, sum, pixels, NaN masks equal) over the pixels the reference assigns."""
-    m = ~np.isnan(ref)
-    mask_eq = bool(np.array_equal(np.isnan(got), np.isnan(ref)))
+    """(max |got - ref|, sum, pixels, NaN masks equal, pixels whose NaN status differs), the
+    differences over the pixels both assign."""
+    gn, rn = np.isnan(got), np.isnan(ref)
+    mism = int(np.count_nonzero(gn != rn))
+    m = ~gn & ~rn
     if not m.any():
-        return 0.0, 0.0, 0, mask_eq
+        return 0.0, 0.0, 0, mism == 0, mism
     d = np.abs(got[m].astype(np.float64) - ref[m])
-    return float(d.max()), float(d.sum()), int(m.sum()), mask_eq
+    return float(d.max()), float(d.sum()), int(m.sum()), mism == 0, mism
 
 
 def _err_merge(parts):
@@ -833,7 +835,8 @@ def _err_merge(parts):
     tot = sum(p[1] for p in parts)
     cnt = sum(p[2] for p in parts)
     return {"max_abs_grey": round(worst, 6), "mean_abs_grey": round(tot / max(cnt, 1), 7),
-            "nan_mask_equal": all(p[3] for p in parts), "pixels": cnt}
+            "nan_mask_equal": all(p[3] for p in parts), "nan_mask_mismatch_pixels": sum(p[4] for p in parts),
+            "pixels": cnt}
 
 
 _OJ = {}      # the child's job state, set before its pool forks

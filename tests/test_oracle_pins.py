@@ -367,6 +367,37 @@ def test_affine_field_reproduced(R):
     np.testing.assert_allclose(out[ok], (cc @ alpha + beta)[ok], rtol=0, atol=1e-8)
 
 
+@pytest.mark.parametrize("R", [1, 2])
+def test_face_pixels_take_the_last_layer(R):
+    """Pixels 1e-9 below the grid's upper x face: their cells reach past the grid, so only the
+    last layer (and, at R = 2, the one before it with a weight of about 1e-9) holds valid voxels.
+    The tent weights renormalised over the valid voxels (Fig. 2 caption; Sec. 2.1: unassigned only
+    when nothing in reach holds a sample) give the affine field's value on the last layer,
+    whatever the size of the surviving weights."""
+    rng = np.random.default_rng(30 + R)
+    dims = (14, 13, 15)
+    K = 2
+    _, Cn = random_grid(rng, K, dims, p_empty=0.0)
+    alpha, beta = np.array([1.7, -2.3, 0.9]), 41.0
+    zz, yy, xx = np.meshgrid(np.arange(dims[2]), np.arange(dims[1]), np.arange(dims[0]), indexing="ij")
+    g = alpha[0] * xx + alpha[1] * yy + alpha[2] * zz + beta
+    a = np.broadcast_to(g, (K,) + g.shape).astype(float)
+    rn = np.tile([0.0, 0.0, 1.0], (K, 1))
+    rx = np.tile([1.0, 0.0, 0.0], (K, 1))
+    origin, h = np.array([-850.0, 310.0, -1620.0]), 0.5
+    W, H, i_face = 8, 8, 7
+    T = np.eye(4)
+    T[:3, 3] = origin + h * np.array([(dims[0] - 1e-9) - i_face * 0.5, 2.3, 4.4])
+    out = reslice.reslice(a, Cn.astype(float), origin, h, rn, rx, np.eye(4), T, W, H, (0.25, 0.25),
+                          Params(radius_vox=R))
+    cc = homogeneous_coords(T, np.eye(4), W, H, (0.25, 0.25), origin, h)
+    assert np.all(cc[:, i_face, 0] < dims[0]) and np.all(cc[:, i_face, 0] > dims[0] - 1e-8)
+    face = out[:, i_face]
+    assert not np.isnan(face).any()
+    expect = alpha[0] * (dims[0] - 1) + alpha[1] * cc[:, i_face, 1] + alpha[2] * cc[:, i_face, 2] + beta
+    np.testing.assert_allclose(face, expect, rtol=0, atol=1e-6)
+
+
 def test_intensity_equivariance(cfg1, cfg1_grid):
     prm = Params()
     a, c = cfg1_grid.mean_count()
