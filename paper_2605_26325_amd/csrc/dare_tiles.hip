@@ -239,17 +239,17 @@ __device__ int request_setup(const VolDev* __restrict__ vd, const SliceArgs& s, 
     return rec.ntiles;
 }
 
-// One thread: the record of tile t of a staged request, all but what depends on the number of
-// surviving bins (`tile_bins`).  The box is the four corner pixels' cells with one voxel of
-// margin (positions are affine in (i, j), so the corners' cells bound every pixel's cell; the
-// margin absorbs rounding), clipped to [-1, n].
-__device__ __forceinline__ void tile_geometry(const Plane& pl, int r, int t, TileRec& tr) {
-    const int T = pl.tile, W = pl.W, H = pl.H;
-    const int ty = t / pl.tiles_x, tx = t - ty * pl.tiles_x;
+// One thread: the part of tile t's record that needs only the plane's position in voxel units
+// (c00 + i ex + j ey, FP64) and the grid: its pixels, and its voxel box, the four corner pixels'
+// cells with one voxel of margin below and two above (positions are affine in (i, j), so the
+// corners' cells bound every pixel's cell; the margin absorbs rounding), clipped to [-1, n], and
+// the box's bricks.  `mode` is left 1, or 0 when no in-grid voxel is in reach.
+__device__ __forceinline__ void tile_box(const double (&c00)[3], const double (&ex)[3], const double (&ey)[3],
+                                         const int (&n)[3], int T, int W, int H, int tiles_x, int r, int t,
+                                         TileRec& tr) {
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
     const int i0 = tx * T, j0 = ty * T;
     const int i1 = min(i0 + T - 1, W - 1), j1 = min(j0 + T - 1, H - 1);
-    int lo[3], hi[3];
-    float c0[3];
     bool empty = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -257,45 +257,47 @@ __device__ __forceinline__ void tile_geometry(const Plane& pl, int r, int t, Til
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double ci = (double)((k & 1) ? i1 : i0), cj = (double)((k & 2) ? j1 : j0);
-            const double c = fma(cj, pl.ey[a], fma(ci, pl.ex[a], pl.c00[a]));
+            const double c = fma(cj, ey[a], fma(ci, ex[a], c00[a]));
             const int f = (int)fmin(fmax(floor(c), -1048576.0), 1048576.0);
             mn = k == 0 ? f : min(mn, f);
             mx = k == 0 ? f : max(mx, f);
-            if (k == 0) c0[a] = (float)c;
+            if (k == 0) tr.c0[a] = (float)c;
         }
-        lo[a] = max(mn - 1, -1);
-        hi[a] = min(mx + 2, pl.n[a]);
+        const int lo = max(mn - 1, -1), hi = min(mx + 2, n[a]);
+        tr.lo[a] = lo;
+        tr.hi[a] = hi;
+        tr.blo[a] = max(lo, 0) >> 3;
+        tr.bdim[a] = (min(hi, n[a] - 1) >> 3) - tr.blo[a] + 1;
         // no in-grid voxel in reach: every pixel of the tile is unassigned
-        empty = empty || max(lo[a], 0) > min(hi[a], pl.n[a] - 1);
+        empty = empty || max(lo, 0) > min(hi, n[a] - 1);
     }
-    const int dax = pl.f.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
-    const int bp = pick3(hi, pax) - pick3(lo, pax) + 1, bq = pick3(hi, qax) - pick3(lo, qax) + 1;
-    const int depth = pl.depth;
-    int blo[3], bdim[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        blo[a] = max(lo[a], 0) >> 3;
-        bdim[a] = (min(hi[a], pl.n[a] - 1) >> 3) - blo[a] + 1;
-    }
-    const int nbb = bdim[0] * bdim[1] * bdim[2];
-    // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
-    // check only keeps the LDS accesses in bounds
-    const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kRunSpan && bp * bq <= kColsMax &&
-                      bp * bq * depth <= kItemsMax && pick3(hi, dax) - pick3(lo, dax) <= kRunSpan;
     tr.r = r;
-    tr.mode = (!empty && fits) ? 1 : 0;
+    tr.mode = empty ? 0 : 1;
     tr.i0 = i0;
     tr.j0 = j0;
     tr.ni = i1 - i0 + 1;
     tr.nj = j1 - j0 + 1;
+    tr.nbb = tr.bdim[0] * tr.bdim[1] * tr.bdim[2];
+    tr.m_bdx = small_div(max(tr.bdim[0], 1)).m;
+    tr.m_bdy = small_div(max(tr.bdim[1], 1)).m;
+}
+
+// One thread, after `tile_box`: the part of the record that needs the plane's frame (the box's
+// columns along the dominant axis, whether they fit the LDS budget, the slab and lateral
+// thresholds), all but what depends on the number of surviving bins (`tile_bins`).
+__device__ __forceinline__ void tile_frame(const Plane& pl, TileRec& tr) {
+    const int dax = pl.f.dax, pax = dax == 0 ? 1 : 0, qax = dax == 2 ? 1 : 2;
+    const int lo[3] = {tr.lo[0], tr.lo[1], tr.lo[2]}, hi[3] = {tr.hi[0], tr.hi[1], tr.hi[2]};
+    const int bp = pick3(hi, pax) - pick3(lo, pax) + 1, bq = pick3(hi, qax) - pick3(lo, qax) + 1;
+    const int depth = pl.depth;
+    // the request's bound makes every staged tile fit; a tile beyond it would be left NaN, so the
+    // check only keeps the LDS accesses in bounds
+    const bool fits = bp >= 2 && bq >= 2 && depth >= 2 && depth <= kRunSpan && bp * bq <= kColsMax &&
+                      bp * bq * depth <= kItemsMax && pick3(hi, dax) - pick3(lo, dax) <= kRunSpan;
+    tr.mode = (tr.mode == 1 && fits) ? 1 : 0;
     float l1u = 0.0f, l1w = 0.0f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        tr.lo[a] = lo[a];
-        tr.hi[a] = hi[a];
-        tr.blo[a] = blo[a];
-        tr.bdim[a] = bdim[a];
-        tr.c0[a] = c0[a];
         l1u += fabsf(pl.f.fu[a]);
         l1w += fabsf(pl.f.fw[a]);
     }
@@ -303,10 +305,7 @@ __device__ __forceinline__ void tile_geometry(const Plane& pl, int r, int t, Til
     tr.bq = bq;
     tr.ncols = bp * bq;
     tr.depth = depth;
-    tr.nbb = nbb;
     tr.m_bp = small_div(max(bp, 1)).m;
-    tr.m_bdx = small_div(max(bdim[0], 1)).m;
-    tr.m_bdy = small_div(max(bdim[1], 1)).m;
     // every voxel with weight for a pixel of the tile lies within |m.(v - c0)| < |m|_1 and,
     // along the in-plane axes, within the tile's extent widened by |u|_1, |w|_1 (the margins
     // cover FP32 rounding and the pose rigidity tolerance)
@@ -314,8 +313,8 @@ __device__ __forceinline__ void tile_geometry(const Plane& pl, int r, int t, Til
     tr.thr_n = fabsf(pl.f.fm[0]) + fabsf(pl.f.fm[1]) + fabsf(pl.f.fm[2]) + slop;
     tr.thr_u = l1u + 0.02f + slop;
     tr.thr_v = l1w + 0.02f + slop;
-    tr.hi_u = (float)(i1 - i0) * pl.f.lu + tr.thr_u;
-    tr.hi_v = (float)(j1 - j0) * pl.f.lw + tr.thr_v;
+    tr.hi_u = (float)(tr.ni - 1) * pl.f.lu + tr.thr_u;
+    tr.hi_v = (float)(tr.nj - 1) * pl.f.lw + tr.thr_v;
     tr.inv_md = 1.0f / pick3(pl.f.fm, dax);
     tr.half = pl.half;
 }
@@ -329,7 +328,8 @@ __device__ __forceinline__ void tile_bins(int kact, TileRec& tr) {
 }
 
 __device__ __forceinline__ void compute_tile(const Plane& pl, int r, int t, TileRec& tr) {
-    tile_geometry(pl, r, t, tr);
+    tile_box(pl.c00, pl.ex, pl.ey, pl.n, pl.tile, pl.W, pl.H, pl.tiles_x, r, t, tr);
+    tile_frame(pl, tr);
     tile_bins(pl.kact, tr);
 }
 
@@ -804,19 +804,37 @@ __global__ void __launch_bounds__(256) k_reslice_tile(const VolDev* __restrict__
     __shared__ SliceRec rec;
     __shared__ TileRec tr;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    // the request setup on two waves at once: wave 0 the bins (Eq. 1, gates, Eq. 2), wave 1 the
-    // plane, its frame and this tile's geometry (16 x 16 tiles); then the parts that need both
+    // the request setup on three waves at once: wave 0 the bins (Eq. 1, gates, Eq. 2), wave 1 the
+    // plane and its frame, wave 2 this tile's pixels and voxel box (16 x 16 tiles); then the
+    // parts that need them together
     double T[12];
     if (threadIdx.x < 64) {
         pad_bins(rec, slice_gates(vd, s, rec, T));
-    } else if (threadIdx.x < 128) {
+    } else if (threadIdx.x < 192) {
         slice_pose(vd, s, T);
-        if (threadIdx.x == 64) tile_geometry(request_frame(vd, s, T, rec), 0, t, tr);
+        if (threadIdx.x == 64) {
+            request_frame(vd, s, T, rec);
+        } else if (threadIdx.x == 128) {
+            // the plane's position in voxel units, as request_frame computes it
+            const double inv_h = vd->inv_h;
+            double c00[3], ex[3], ey[3];
+            const int n[3] = {vd->nx, vd->ny, vd->nz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                c00[a] = (T[a * 4 + 3] - vd->origin[a]) * inv_h;
+                ex[a] = (s.sx * T[a * 4 + 0]) * inv_h;
+                ey[a] = (s.sy * T[a * 4 + 1]) * inv_h;
+            }
+            tile_box(c00, ex, ey, n, 16, s.W, s.H, (s.W + 15) / 16, 0, t, tr);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         Plane pl = plane_of(rec);
-        if (request_mode(pl, rec, 16) == 1) tile_bins(pl.kact, tr);
+        if (request_mode(pl, rec, 16) == 1) {
+            tile_frame(pl, tr);
+            tile_bins(pl.kact, tr);
+        }
     }
     __syncthreads();
     if (ui(rec.mode) == 1) run_tile<DT, 256, items_per_round<DT>(), bins_per_round<DT>()>(rec, tr, tl);
